@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""GBP bundle-adjustment throughput on one MI355X: factor updates per second.
+
+One step is one synchronous GBP iteration over the whole workload: the
+relinearisation check (and relinearisation where due), every factor's two
+messages, every belief, and the per-problem reprojection statistics (the
+four compute phases of the hot path). The default workload is 256 uneven
+bundle-adjustment problems (10-125 keyframes, 100-2000 landmarks, 4-12
+observations per landmark, about 2.15 M factors) run as one batched graph;
+inputs are generated on the host and resident in HBM before timing starts.
+
+Printed: one JSON line with the throughput, the dominant kernel's roofline
+figures (live HIP-event timing on the library's stream) and the FP64 oracle
+timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+# Algorithmic bytes of one factor-phase update of one factor with FP32
+# factor state (the layout in paper_2003_03134_amd/csrc/gbp_internal.h):
+#   read  keyframe-side record 16 x 4 B, landmark-side J + message 11 x 4 B,
+#         factor-private record 15 x 4 B (r0, lin. offset, J*anchor),
+#         keyframe and landmark index 2 x 4 B, counter + flags 2 x 1 B;
+#   write messages to keyframe and landmark 2 x 5 x 4 B, counter 1 B.
+FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 15 * 4 + 2 * 4 + 2 + 2 * 5 * 4 + 1  # 219
+# plus, once per launch, every belief the factors gather (FP64 mean offset +
+# packed covariance): 27 doubles per keyframe, 9 per landmark.
+KF_BELIEF_BYTES = 27 * 8
+LM_BELIEF_BYTES = 9 * 8
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def factor_launch_bytes(nf, nk, nl):
+    return nf * FACTOR_BYTES_PER_FACTOR + nk * KF_BELIEF_BYTES + nl * LM_BELIEF_BYTES
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in ("gbp_kernels.hip", "gbp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2003_03134_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per factor-kernel launch from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_factor_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_workload(name):
+    import synth
+    if name == "config3":
+        probs = synth.make_config3(256)
+        desc = ("256 uneven BA problems batched (keyframes U{10..125}, landmarks "
+                "U{100..2000}, 4-12 obs/landmark, seeds 1000+p), FP32 factor state")
+    elif name == "config1":
+        probs = [synth.make_config1()]
+        desc = "125 keyframes, 1919 landmarks, 4-20 obs (fr3teddy sizes), 3% outliers"
+    elif name == "config2":
+        probs = [synth.make_config2()]
+        desc = "1000 keyframes, 40000 landmarks, power-law obs, 5% outliers"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return probs, desc
+
+
+def cpu_baseline(probs, budget_s, iters):
+    """FP64 oracle on the first problems of the workload until ~budget_s."""
+    import oracle
+    t_total, updates, used = 0.0, 0, 0
+    for p in probs:
+        o = oracle.Oracle(p, anneal=True)
+        t0 = time.perf_counter()
+        o.iterate(iters, 0.4, 2.0)
+        t_total += time.perf_counter() - t0
+        updates += p.n_factors * iters
+        used += 1
+        if t_total > budget_s:
+            break
+    return dict(value=updates / t_total, unit="factor-updates/s", cores=oracle.threads(),
+                kind="oracle",
+                sample=f"first {used} problems of the workload, {iters} iterations each "
+                       f"({updates} factor updates, {t_total:.1f} s)")
+
+
+def time_to_target(gbp, target=1.0, max_iters=600):
+    """Plain GBP on the paper-scale problem: iterations and wall time until
+    the mean error against noise-free projections of inliers is <= target."""
+    import synth
+    p = synth.make_config1()
+    s = gbp.GBPSolver(p)
+    s.set_reference(p.z_true, p.inlier)
+    logrow = s.iterate_logged(max_iters, 0.4, 2.0, log_every=1)
+    s2 = gbp.GBPSolver(p)
+    s2.set_reference(p.z_true, p.inlier)
+    s2.iterate_logged(max_iters, 0.4, 2.0, log_every=1)  # graph capture
+    s3 = gbp.GBPSolver(p)
+    s3.set_reference(p.z_true, p.inlier)
+    s3.synchronize()
+    t0 = time.perf_counter()
+    s3.iterate_logged(max_iters, 0.4, 2.0, log_every=1)
+    wall = time.perf_counter() - t0
+    are_ref = logrow[:, 0, 2]
+    hit = [i for i, a in enumerate(are_ref) if a <= target]
+    it = hit[0] + 1 if hit else None
+    for x in (s, s2, s3):
+        x.close()
+    return dict(problem="config1", target_px=target, iterations=it,
+                ms=(wall * 1e3 * it / max_iters) if it else None,
+                final_are_ref=float(are_ref[-1]), final_are_all=float(logrow[-1, 0, 1]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="config3")
+    ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--phase-iters", type=int, default=20)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-iters", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-target", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent problems shard trivially by problem; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2003_03134_amd as gbp
+    gbp.load_library()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a ROCm GPU")
+
+    log(f"generating workload {args.workload}")
+    t0 = time.perf_counter()
+    probs, desc = make_workload(args.workload)
+    nk = sum(p.n_keyframes for p in probs)
+    nl = sum(p.n_landmarks for p in probs)
+    nf = sum(p.n_factors for p in probs)
+    log(f"{len(probs)} problems, {nk} keyframes, {nl} landmarks, {nf} factors "
+        f"({time.perf_counter() - t0:.1f} s)")
+
+    solver = gbp.GBPSolver(probs if len(probs) > 1 else probs[0], precision=gbp.GBP_FP32)
+    zt = np.concatenate([p.z_true for p in probs])
+    inl = np.concatenate([p.inlier for p in probs])
+    solver.set_reference(zt, inl)
+
+    K, W = args.steps, args.warmup
+    c = max(1, min(args.chunk, K))
+    n_chunks, rem = K // c, K % c
+    log(f"warmup: >= {W} steps in chunks of {c}")
+    done = 0
+    while done < max(W, 1):
+        solver.iterate_logged(c, 0.4, 2.0, log_every=1)
+        done += c
+    if rem:
+        solver.iterate_logged(rem, 0.4, 2.0, log_every=1)
+    torch.cuda.synchronize()
+    solver.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log(f"timing {K} steps")
+    t0 = time.perf_counter()
+    ev0.record(solver.stream)
+    last = None
+    for _ in range(n_chunks):
+        last = solver.iterate_logged(c, 0.4, 2.0, log_every=1)
+    if rem:
+        last = solver.iterate_logged(rem, 0.4, 2.0, log_every=1)
+    ev1.record(solver.stream)
+    solver.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / K
+    value = nf * K / wall
+    log(f"{ms_per_step:.4f} ms/step wall ({ev_ms / K:.4f} ms/step by events), "
+        f"{value / 1e9:.3f} G factor-updates/s")
+
+    relin0 = solver.relinearisations
+    ph = solver.phase_times(args.phase_iters, 0.4, 2.0)
+    relin_frac = (solver.relinearisations - relin0) / (nf * args.phase_iters)
+    log(f"relinearised per iteration: {100 * relin_frac:.2f}% of factors")
+    log("phase ms/launch: " + ", ".join(f"{k} {v:.4f}" for k, v in ph.items()))
+    fbytes = factor_launch_bytes(nf, nk, nl)
+    achieved = fbytes / (ph["factor"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_factor", algorithmic_bytes_per_launch=int(fbytes),
+                    kernel_ms=round(ph["factor"], 5),
+                    phases_ms={k: round(v, 5) for k, v in ph.items()},
+                    relinearised_fraction=round(relin_frac, 5))
+    are = last[-1] if last is not None else None
+    solver.close()
+
+    extra = {}
+    if not args.no_target:
+        log("time to target on the paper-scale problem (plain GBP)")
+        extra["time_to_target_plain"] = time_to_target(gbp)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("FP64 oracle on a bounded sample (host cores)")
+        cpu = cpu_baseline(probs, args.cpu_budget, args.cpu_iters)
+        log(f"oracle: {cpu['value'] / 1e6:.2f} M factor-updates/s on {cpu['cores']} threads")
+
+    if are is not None:
+        extra["final_mean_are_all_px"] = float(np.mean(are[:, 1]))
+        extra["final_mean_are_ref_px"] = float(np.mean(are[:, 2]))
+    out = {
+        "metric": "GBP factor updates/s",
+        "value": round(value, 1),
+        "unit": "factor-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n_problems": len(probs),
+                   "n_keyframes": nk, "n_landmarks": nl, "n_factors": nf,
+                   "factor_state": "f32", "beliefs": "f64",
+                   "step": "relinearisation check + factor messages + beliefs + per-problem reprojection error",
+                   "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * gbp.h - C ABI of the MI355X (gfx950) Gaussian Belief Propagation
+ * bundle-adjustment library.
+ *
+ * The library runs synchronous GBP sweeps (Ortiz et al., "Bundle Adjustment
+ * on a Graph Processor", Section 5) over a keyframe / landmark /
+ * reprojection-factor graph (Section 4) on one GPU. Every entry point returns
+ * a gbp_status; nothing throws across the ABI. Host pointers are plain
+ * row-major arrays owned by the caller; the library copies what it needs.
+ * All device work is ordered on the stream given in gbp_options; calls that
+ * return host results synchronise that stream.
+ *
+ * Conventions (shared with the paper's problem statement, Section 4):
+ *   - keyframe pose x = (omega, t) in R^6, world -> camera: a world point l
+ *     maps to R(omega) l + t, R(omega) = Exp(omega) (axis-angle);
+ *   - landmark l in R^3, world frame;
+ *   - measurement z in pixels, h(x, l) = pi(R l + t) with a pinhole
+ *     projection (fx, fy, cx, cy), noise Sigma_M = sigma^2 I;
+ *   - Huber threshold huber_k in pixels (Section 6; N_sigma = huber_k/sigma),
+ *     huber_k <= 0 disables the robust kernel.
+ */
+#ifndef GBP_H
+#define GBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GBP_OK = 0,
+    GBP_EINVAL = -1,   /* bad argument: sizes, indices, options          */
+    GBP_ENOMEM = -2,   /* device or host allocation failed / no capacity */
+    GBP_EDEVICE = -3,  /* a HIP runtime call failed                       */
+    GBP_ENUMERIC = -4, /* a belief was not positive definite / not finite */
+    GBP_ESTATE = -5    /* call not valid in the problem's current state   */
+} gbp_status;
+
+/* Storage precision of per-factor state and messages. Beliefs (covariance
+ * and mean offsets), belief sums and the 6x6 / 3x3 solves are FP64 in both
+ * modes; the per-factor 2x2 marginalisation arithmetic is FP64 as well. */
+enum { GBP_FP64 = 0, GBP_FP32 = 1 };
+
+/* Message damping (Section 5, last paragraph): the paper damps the eta
+ * message; GBP_DAMP_ETA_LAMBDA damps the Lambda message with the same
+ * factor as well. */
+enum { GBP_DAMP_ETA = 0, GBP_DAMP_ETA_LAMBDA = 1 };
+
+typedef struct gbp_problem gbp_problem; /* opaque, owned by the library */
+
+/* Variables, factors and initial estimate of one problem (Section 4). */
+typedef struct {
+    int32_t n_keyframes, n_landmarks, n_factors;
+    const int32_t *factor_kf;      /* [n_factors] keyframe of each factor  */
+    const int32_t *factor_lm;      /* [n_factors] landmark of each factor  */
+    const double *kf_init;         /* [n_keyframes][6] initial (omega, t)  */
+    const double *lm_init;         /* [n_landmarks][3] initial position    */
+    const double *kf_anchor_info;  /* [n_keyframes] or NULL: a value a > 0
+                                      replaces that keyframe's automatic
+                                      prior by a*I at its initial pose      */
+} gbp_graph;
+
+typedef struct {
+    double fx, fy, cx, cy; /* pinhole intrinsics, pixels            */
+    double sigma_px;       /* measurement noise standard deviation  */
+} gbp_camera;
+
+typedef struct {
+    const double *z;       /* [n_factors][2] measured pixels        */
+} gbp_measurements;
+
+/* Hyperparameters; gbp_default_options fills in the paper's (Section 8). */
+typedef struct {
+    int32_t precision;             /* GBP_FP64 | GBP_FP32                   */
+    int32_t damp_mode;             /* GBP_DAMP_ETA | GBP_DAMP_ETA_LAMBDA     */
+    double beta;                   /* relinearisation distance, 0.01        */
+    int32_t relin_min_interval;    /* factor updates between relins, 10     */
+    int32_t undamped_after_relin;  /* undamped updates after relin, 8 (>=1) */
+    int32_t anneal;                /* 1: priors weaken over anneal_iters    */
+    int32_t prior_anneal_iters;    /* 10 (<= 64)                            */
+    double prior_weaken;           /* final prior scale, 0.01               */
+    double huber_k;                /* initial Huber threshold (px), 2       */
+    double zmin;                   /* minimum valid camera depth, 1e-3      */
+    int32_t max_keyframes;         /* capacity for gbp_add_keyframe growth  */
+    int32_t max_landmarks;         /*   (0: the created sizes)              */
+    int32_t max_factors;
+    void *workspace;               /* optional device memory (e.g. torch);
+                                      NULL: the library allocates           */
+    size_t workspace_bytes;
+    void *stream;                  /* hipStream_t; NULL: default stream     */
+} gbp_options;
+
+/* Reprojection statistics at the current belief means (Section 9.1: the
+ * average reprojection error; Section 9.4: a measurement is classed an
+ * outlier when it lies in the linear Huber regime). */
+typedef struct {
+    double are_all;        /* mean |z - h(mu)| over valid factors (px)     */
+    double are_quadratic;  /* mean over factors with |z - h| <= huber_k    */
+    double are_ref;        /* mean |z_ref - h(mu)| over the reference mask */
+    int64_t n_valid;       /* factors with camera depth > zmin             */
+    int64_t n_quadratic;
+    int64_t n_linear;      /* factors in the linear (outlier) regime       */
+    int64_t n_invalid;     /* factors with camera depth <= zmin            */
+    int64_t n_ref;
+} gbp_reproj;
+
+/* Fill opt with the paper's hyperparameters and FP32 storage. */
+void gbp_default_options(gbp_options *opt);
+
+/* Device bytes the library needs for n problems under opt (capacity
+ * included). Pass a workspace of at least this size, or NULL. */
+gbp_status gbp_workspace_bytes(int32_t n_problems, const gbp_graph *graphs,
+                               const gbp_options *opt, size_t *bytes);
+
+/* Build one problem (Section 4): validates indices, orders factors by
+ * landmark and keyframes' factors into a CSR, copies inputs to the device,
+ * linearises every factor at the initial estimate, builds the automatic
+ * priors and sets each belief to its prior (iteration clock t = 0).
+ * Returns GBP_EINVAL for out-of-range indices or sizes. */
+gbp_status gbp_create(const gbp_graph *graph, const gbp_camera *camera,
+                      const gbp_measurements *meas, const gbp_options *opt,
+                      gbp_problem **out);
+
+/* Build n independent problems that run as one block-diagonal graph and
+ * one launch sequence (arrays of n graphs / cameras / measurements). */
+gbp_status gbp_create_batch(int32_t n, const gbp_graph *graphs,
+                            const gbp_camera *cameras,
+                            const gbp_measurements *meas,
+                            const gbp_options *opt, gbp_problem **out);
+
+/* Relinearise (Section 5): beta < 0 selects every factor, otherwise the
+ * factors whose stacked [mu_k; mu_m] lies farther than beta from their
+ * linearisation point. The selected factors take the current means as their
+ * linearisation point, with the Huber threshold last set on the problem;
+ * the new linearisation is applied at the start of the next factor phase
+ * (nothing in between depends on it). *n_relin (may be NULL) receives the
+ * number selected; this call synchronises. */
+gbp_status gbp_relinearise(gbp_problem *p, double beta, int32_t *n_relin);
+
+/* n synchronous iterations (Section 5): relinearisation check, factor
+ * messages with damping `damping`, belief update. huber_k (px) is stored on
+ * the problem and used by every relinearisation from now on. Asynchronous:
+ * numerical failures are reported by the next synchronising call. */
+gbp_status gbp_iterate(gbp_problem *p, int32_t n, double damping,
+                       double huber_k);
+
+/* Current beliefs in the caller's variable order (problem-major for
+ * batches): means kf_mean [Nk][6], lm_mean [Nl][3]; information matrices
+ * kf_info [Nk][6][6] and lm_info [Nl][3][3] when not NULL. Synchronises;
+ * GBP_ENUMERIC if a belief failed to be positive definite since the last
+ * check (that belief keeps its last good value). */
+gbp_status gbp_beliefs(gbp_problem *p, double *kf_mean, double *lm_mean,
+                       double *kf_info, double *lm_info);
+
+/* Average reprojection error over all factors (every problem of a batch):
+ * *are_all, *are_inlier_quadratic and *n_linear_regime may be NULL. */
+gbp_status gbp_reproj_error(gbp_problem *p, double *are_all,
+                            double *are_inlier_quadratic,
+                            int32_t *n_linear_regime);
+
+/* Full statistics of one problem of a batch (problem_index >= 0) or of the
+ * whole graph (-1). Synchronises. */
+gbp_status gbp_reproj_stats(gbp_problem *p, int32_t problem_index,
+                            gbp_reproj *out);
+
+/* Reference pixels (e.g. noise-free projections) and a mask selecting the
+ * factors they apply to, in the caller's factor order; used for are_ref.
+ * NULL clears the reference. */
+gbp_status gbp_set_reference(gbp_problem *p, const double *z_ref,
+                             const uint8_t *mask);
+
+/* As gbp_iterate, and every log_every iterations records
+ * {t, are_all, are_ref, n_linear} of every problem into a device log; the
+ * log (n/log_every rows x n_problems x 4 doubles) is copied to log_out at
+ * the end, with no host synchronisation in between. */
+gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
+                              double huber_k, int32_t log_every,
+                              double *log_out);
+
+/* Incremental growth (Section 9.2) of a single (non-batched) problem:
+ * append one keyframe with initial pose `pose` (NULL: no keyframe),
+ * n_new_lm landmarks and n_new_f factors whose indices refer to the grown
+ * variable sets (new keyframe = old count, new landmarks follow the old
+ * ones). New factors are linearised at the current means; new variables get
+ * automatic priors from the new factors and their own annealing clock.
+ * GBP_ENOMEM when the capacity set at creation is exceeded. */
+gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6],
+                            int32_t n_new_lm, const double *lm_init,
+                            int32_t n_new_f, const int32_t *f_kf,
+                            const int32_t *f_lm, const double *z);
+
+/* Per-factor damping model: NULL restores the constant damping passed to
+ * gbp_iterate. `weights` is the BF16 parameter blob of the damping MLP
+ * (layout in gbp_mlp_param_count); it is evaluated every `every_k`
+ * iterations inside gbp_iterate. */
+gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
+                                 int32_t every_k);
+
+/* Per-phase timing (the compute phases of one iteration, Section 7 and
+ * Fig. 3): runs n iterations with each phase launched separately and
+ * bracketed by HIP events on the problem's stream, then writes the average
+ * milliseconds per launch of {factor phase (relinearisation check,
+ * relinearisation, messages), landmark beliefs, keyframe beliefs,
+ * reprojection statistics} to ms_out[4]. The iterations are real: the
+ * state advances by n. Synchronises. */
+gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping,
+                           double huber_k, double *ms_out);
+
+/* Number of factor relinearisations performed since creation (the subset
+ * of factors that relinearise each iteration, Section 7, Fig. 3), counting
+ * the initial linearisation as none. Synchronises. */
+gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations);
+
+/* Sizes: keyframes, landmarks, factors, problems, completed iterations. */
+gbp_status gbp_sizes(const gbp_problem *p, int32_t *n_keyframes,
+                     int32_t *n_landmarks, int32_t *n_factors,
+                     int32_t *n_problems, int32_t *t);
+
+/* Message describing the last error on this problem (never NULL). */
+const char *gbp_last_error(const gbp_problem *p);
+
+void gbp_destroy(gbp_problem *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBP_H */

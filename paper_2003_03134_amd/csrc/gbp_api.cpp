@@ -1,0 +1,812 @@
+// Host runtime and C ABI of the GBP bundle-adjustment library.
+//
+// Graph build (the paper's "predetermined" exchange schedule, Section 7,
+// becomes a fixed memory layout): within each problem, landmarks are ordered
+// by their first observing keyframe, factors by landmark (so a landmark's
+// incoming messages are contiguous) and each keyframe gets a CSR list of its
+// factors in increasing factor order. A batch is the block-diagonal
+// concatenation of its problems. Every buffer is carved from one device
+// workspace (caller-provided, e.g. a torch allocation, or allocated here).
+// Iterations are recorded once per (n, damping, Huber threshold) into a HIP
+// graph and replayed.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/gbp.h"
+#include "gbp_internal.h"
+
+using namespace gbp;
+
+namespace {
+
+struct GraphEntry {
+    int n;
+    double damping, huber;
+    int log_every;
+    hipGraphExec_t exec;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct gbp_problem {
+    int precision = GBP_FP32;
+    gbp_options opt{};
+    int np = 0, nk = 0, nl = 0, nf = 0;
+    int cap_k = 0, cap_l = 0, cap_f = 0;
+    // internal <-> caller ordering
+    std::vector<int> lm_int2user, f_int2user;
+    std::vector<int> kf_off, lm_off, f_off;  // internal offsets per problem
+    // host mirrors needed to rebuild the layout on growth
+    std::vector<int> h_fkf, h_flm, h_kf_row, h_kf_edge, h_lm_row;
+    std::vector<double> h_z, h_kf_anchor, h_lm_anchor;
+    std::vector<int> h_first_obs;  // first observing keyframe of each internal landmark
+    // device
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Dev<float> df{};
+    Dev<double> dd{};
+    int *d_count = nullptr;
+    double *d_zref = nullptr;
+    uint8_t *d_mask = nullptr;
+    bool has_ref = false;
+    int *d_perm = nullptr;
+    void *d_scratch = nullptr;
+    double *d_log = nullptr;
+    size_t log_cap = 0;
+    IterOpts iopt{};
+    double huber_k = 2.0;
+    int t = 0;
+    std::vector<GraphEntry> graphs;
+    bool use_graph = true;
+    int blk_factor = 256, blk_lm = 256, blk_kf = 256, factor_variant = 0;
+    std::string err;
+    bool broken = false;
+};
+
+namespace {
+
+gbp_status fail(gbp_problem *p, gbp_status st, const std::string &msg) {
+    if (p) p->err = msg;
+    return st;
+}
+
+#define HIP_TRY(p, call)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((p), GBP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Workspace layout: one entry per device array.
+struct Layout {
+    size_t total = 0;
+    std::vector<std::pair<void **, size_t>> items;
+    void add(void **ptr, size_t bytes) {
+        items.push_back({ptr, total});
+        total += align_up(bytes ? bytes : 1);
+    }
+};
+
+template <typename TS>
+void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
+    const size_t K = p->cap_k, M = p->cap_l, F = p->cap_f, P = p->np;
+    L.add((void **)&d.kf_anchor, K * 6 * 8);
+    L.add((void **)&d.lm_anchor, M * 3 * 8);
+    L.add((void **)&d.kf_pbase, K * 6 * 8);
+    L.add((void **)&d.lm_pbase, M * 3 * 8);
+    L.add((void **)&d.kf_pinfo, K * 8);
+    L.add((void **)&d.kf_t0, K * 4);
+    L.add((void **)&d.lm_t0, M * 4);
+    L.add((void **)&d.kf_prob, K * 4);
+    L.add((void **)&d.lm_prob, M * 4);
+    L.add((void **)&d.kf_bel, K * KBEL * 8);
+    L.add((void **)&d.lm_bel, M * LBEL * 8);
+    L.add((void **)&d.kf_info, K * 36 * 8);
+    L.add((void **)&d.lm_info, M * 9 * 8);
+    L.add((void **)&d.f_kf, F * 4);
+    L.add((void **)&d.f_lm, F * 4);
+    L.add((void **)&d.kf_row, (K + 1) * 4);
+    L.add((void **)&d.kf_edge, F * 4);
+    L.add((void **)&d.lm_row, (M + 1) * 4);
+    L.add((void **)&d.f_row_prob, (P + 1) * 4);
+    L.add((void **)&d.z, F * 2 * 8);
+    L.add((void **)&d.krec, F * KREC * sizeof(TS));
+    L.add((void **)&d.lrec, F * LREC * sizeof(TS));
+    L.add((void **)&d.arec, F * AREC * sizeof(TS));
+    L.add((void **)&d.cnt, F);
+    L.add((void **)&d.flags, F);
+    L.add((void **)&d.fdamp, F * 4);
+    L.add((void **)&d.prob, P * sizeof(ProbParams));
+    L.add((void **)&d.t_dev, 4);
+    L.add((void **)&d.status, 4);
+    L.add((void **)&d.pending_k, 8);
+    L.add((void **)&d.relin_queue, F * 4);
+    L.add((void **)&d.relin_count, 4);
+    L.add((void **)&d.relin_total, 8);
+    L.add((void **)&d.kf_pose, K * 12 * 8);
+    const size_t RB = F / RBLK + P + 1;
+    L.add((void **)&d.rblk_start, (RB + 1) * 4);
+    L.add((void **)&d.rblk_prob, RB * 4);
+    L.add((void **)&d.prob_rblk, (P + 1) * 4);
+    L.add((void **)&d.rblk_part, RB * 8 * 8);
+    L.add((void **)&d.are_out, P * 8 * 8);
+    L.add((void **)&p->d_count, 4);
+    L.add((void **)&p->d_zref, F * 2 * 8);
+    L.add((void **)&p->d_mask, F);
+    L.add((void **)&p->d_perm, F * 4);
+    L.add((void **)&p->d_scratch, F * 16 * 8);
+}
+
+void default_opts(gbp_options *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->precision = GBP_FP32;
+    o->damp_mode = GBP_DAMP_ETA;
+    o->beta = 0.01;
+    o->relin_min_interval = 10;
+    o->undamped_after_relin = 8;
+    o->anneal = 1;
+    o->prior_anneal_iters = 10;
+    o->prior_weaken = 0.01;
+    o->huber_k = 2.0;
+    o->zmin = 1e-3;
+}
+
+gbp_status check_opts(const gbp_options *o, std::string &msg) {
+    if (o->precision != GBP_FP32 && o->precision != GBP_FP64) { msg = "precision must be GBP_FP32 or GBP_FP64"; return GBP_EINVAL; }
+    if (o->damp_mode != GBP_DAMP_ETA && o->damp_mode != GBP_DAMP_ETA_LAMBDA) { msg = "bad damp_mode"; return GBP_EINVAL; }
+    if (o->undamped_after_relin < 1) { msg = "undamped_after_relin must be >= 1"; return GBP_EINVAL; }
+    if (o->relin_min_interval < 0 || o->relin_min_interval > 250) { msg = "relin_min_interval must be in [0, 250]"; return GBP_EINVAL; }
+    if (o->prior_anneal_iters < 0 || o->prior_anneal_iters > MAX_ANNEAL) { msg = "prior_anneal_iters must be in [0, 64]"; return GBP_EINVAL; }
+    if (!(o->prior_weaken > 0.0) || !(o->beta >= 0.0)) { msg = "prior_weaken must be > 0 and beta >= 0"; return GBP_EINVAL; }
+    return GBP_OK;
+}
+
+gbp_status check_graph(const gbp_graph *g, const gbp_measurements *m, const gbp_camera *c, std::string &msg) {
+    if (!g || !m || !c) { msg = "null argument"; return GBP_EINVAL; }
+    if (g->n_keyframes < 1 || g->n_landmarks < 0 || g->n_factors < 0) { msg = "bad sizes"; return GBP_EINVAL; }
+    if (g->n_factors > 0 && (!g->factor_kf || !g->factor_lm || !m->z)) { msg = "null factor arrays"; return GBP_EINVAL; }
+    if (!g->kf_init || (g->n_landmarks > 0 && !g->lm_init)) { msg = "null initial estimate"; return GBP_EINVAL; }
+    if (!(c->sigma_px > 0.0) || !(c->fx > 0.0) || !(c->fy > 0.0)) { msg = "bad camera"; return GBP_EINVAL; }
+    for (int f = 0; f < g->n_factors; ++f) {
+        if (g->factor_kf[f] < 0 || g->factor_kf[f] >= g->n_keyframes || g->factor_lm[f] < 0 ||
+            g->factor_lm[f] >= g->n_landmarks) {
+            msg = "factor " + std::to_string(f) + " has an out-of-range variable index";
+            return GBP_EINVAL;
+        }
+        if (!std::isfinite(m->z[2 * f]) || !std::isfinite(m->z[2 * f + 1])) {
+            msg = "factor " + std::to_string(f) + " has a non-finite measurement";
+            return GBP_EINVAL;
+        }
+    }
+    for (long i = 0; i < 6L * g->n_keyframes; ++i)
+        if (!std::isfinite(g->kf_init[i])) { msg = "non-finite keyframe initial estimate"; return GBP_EINVAL; }
+    for (long i = 0; i < 3L * g->n_landmarks; ++i)
+        if (!std::isfinite(g->lm_init[i])) { msg = "non-finite landmark initial estimate"; return GBP_EINVAL; }
+    return GBP_OK;
+}
+
+void fill_iopt(gbp_problem *p) {
+    IterOpts &o = p->iopt;
+    o.beta2 = p->opt.beta * p->opt.beta;
+    o.interval = p->opt.relin_min_interval;
+    o.undamped = p->opt.undamped_after_relin;
+    o.damp_mode = p->opt.damp_mode;
+    const int T = p->opt.anneal ? p->opt.prior_anneal_iters : 0;
+    o.anneal_iters = T;
+    for (int a = 0; a <= MAX_ANNEAL; ++a) o.scale[a] = p->opt.prior_weaken;
+    if (T > 0)
+        for (int a = 0; a <= T; ++a) o.scale[a] = std::pow(p->opt.prior_weaken, (double)a / (double)T);
+}
+
+template <typename TS>
+Dev<TS> &dev(gbp_problem *p);
+template <>
+Dev<float> &dev<float>(gbp_problem *p) { return p->df; }
+template <>
+Dev<double> &dev<double>(gbp_problem *p) { return p->dd; }
+
+// Build the internal ordering of the whole (possibly batched) graph.
+void build_order(gbp_problem *p, int n, const gbp_graph *gs, const gbp_measurements *ms,
+                 std::vector<int> &fkf, std::vector<int> &flm, std::vector<double> &z) {
+    p->kf_off.assign(n + 1, 0);
+    p->lm_off.assign(n + 1, 0);
+    p->f_off.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        p->kf_off[i + 1] = p->kf_off[i] + gs[i].n_keyframes;
+        p->lm_off[i + 1] = p->lm_off[i] + gs[i].n_landmarks;
+        p->f_off[i + 1] = p->f_off[i] + gs[i].n_factors;
+    }
+    p->nk = p->kf_off[n];
+    p->nl = p->lm_off[n];
+    p->nf = p->f_off[n];
+    p->lm_int2user.resize(p->nl);
+    p->f_int2user.resize(p->nf);
+    p->h_first_obs.assign(p->nl, 0);
+    fkf.resize(p->nf);
+    flm.resize(p->nf);
+    z.resize(2 * (size_t)p->nf);
+    for (int i = 0; i < n; ++i) {
+        const gbp_graph &g = gs[i];
+        const int K0 = p->kf_off[i], M0 = p->lm_off[i], F0 = p->f_off[i];
+        // landmarks ordered by first observing keyframe (locality of the
+        // keyframe-side gathers), ties by caller index
+        std::vector<int> first(g.n_landmarks, g.n_keyframes);
+        for (int f = 0; f < g.n_factors; ++f) first[g.factor_lm[f]] = std::min(first[g.factor_lm[f]], g.factor_kf[f]);
+        std::vector<int> lorder(g.n_landmarks);
+        std::iota(lorder.begin(), lorder.end(), 0);
+        std::stable_sort(lorder.begin(), lorder.end(), [&](int a, int b) { return first[a] < first[b]; });
+        std::vector<int> lrank(g.n_landmarks);
+        for (int r = 0; r < g.n_landmarks; ++r) {
+            lrank[lorder[r]] = r;
+            p->lm_int2user[M0 + r] = M0 + lorder[r];
+            p->h_first_obs[M0 + r] = first[lorder[r]];
+        }
+        std::vector<int> forder(g.n_factors);
+        std::iota(forder.begin(), forder.end(), 0);
+        std::stable_sort(forder.begin(), forder.end(), [&](int a, int b) {
+            int la = lrank[g.factor_lm[a]], lb = lrank[g.factor_lm[b]];
+            if (la != lb) return la < lb;
+            return g.factor_kf[a] < g.factor_kf[b];
+        });
+        for (int r = 0; r < g.n_factors; ++r) {
+            int f = forder[r];
+            p->f_int2user[F0 + r] = F0 + f;
+            fkf[F0 + r] = K0 + g.factor_kf[f];
+            flm[F0 + r] = M0 + lrank[g.factor_lm[f]];
+            z[2 * (size_t)(F0 + r)] = ms[i].z[2 * f];
+            z[2 * (size_t)(F0 + r) + 1] = ms[i].z[2 * f + 1];
+        }
+    }
+}
+
+void build_csr(gbp_problem *p) {
+    const int nk = p->nk, nl = p->nl, nf = p->nf;
+    p->h_kf_row.assign(nk + 1, 0);
+    p->h_lm_row.assign(nl + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+        p->h_kf_row[p->h_fkf[f] + 1]++;
+        p->h_lm_row[p->h_flm[f] + 1]++;
+    }
+    for (int k = 0; k < nk; ++k) p->h_kf_row[k + 1] += p->h_kf_row[k];
+    for (int m = 0; m < nl; ++m) p->h_lm_row[m + 1] += p->h_lm_row[m];
+    p->h_kf_edge.assign(nf, 0);
+    std::vector<int> fill(nk, 0);
+    for (int f = 0; f < nf; ++f) {
+        int k = p->h_fkf[f];
+        p->h_kf_edge[p->h_kf_row[k] + fill[k]++] = f;
+    }
+}
+
+void destroy_graphs(gbp_problem *p) {
+    for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+}
+
+template <typename TS>
+gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera *cams, int n) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    const int nk = p->nk, nl = p->nl, nf = p->nf;
+    d.nk = nk; d.nl = nl; d.nf = nf; d.np = n;
+    // per-variable host arrays
+    std::vector<double> kf_anchor(6 * (size_t)nk), lm_anchor(3 * (size_t)nl), kf_pinfo(nk, 0.0);
+    std::vector<int> kf_prob(nk), lm_prob(nl), zero_k(nk, 0), zero_l(nl, 0);
+    std::vector<ProbParams> pp(n);
+    for (int i = 0; i < n; ++i) {
+        const gbp_graph &g = gs[i];
+        for (int k = 0; k < g.n_keyframes; ++k) {
+            int K = p->kf_off[i] + k;
+            for (int c = 0; c < 6; ++c) kf_anchor[6 * (size_t)K + c] = g.kf_init[6 * (size_t)k + c];
+            kf_pinfo[K] = g.kf_anchor_info ? g.kf_anchor_info[k] : 0.0;
+            kf_prob[K] = i;
+        }
+        for (int r = 0; r < g.n_landmarks; ++r) {
+            int M = p->lm_off[i] + r;
+            int u = p->lm_int2user[M] - p->lm_off[i];
+            for (int c = 0; c < 3; ++c) lm_anchor[3 * (size_t)M + c] = g.lm_init[3 * (size_t)u + c];
+            lm_prob[M] = i;
+        }
+        const gbp_camera &c = cams[i];
+        pp[i] = ProbParams{c.fx, c.fy, c.cx, c.cy, c.sigma_px, 1.0 / (c.sigma_px * c.sigma_px), p->opt.zmin, 0.0};
+    }
+    p->h_kf_anchor = kf_anchor;
+    p->h_lm_anchor = lm_anchor;
+#define UP(dst, src, bytes) HIP_TRY(p, hipMemcpyAsync((void *)(dst), (const void *)(src), (bytes), hipMemcpyHostToDevice, s))
+    UP(d.kf_anchor, kf_anchor.data(), kf_anchor.size() * 8);
+    UP(d.lm_anchor, lm_anchor.data(), lm_anchor.size() * 8);
+    UP(d.kf_pinfo, kf_pinfo.data(), kf_pinfo.size() * 8);
+    UP(d.kf_prob, kf_prob.data(), kf_prob.size() * 4);
+    UP(d.lm_prob, lm_prob.data(), lm_prob.size() * 4);
+    UP(d.kf_t0, zero_k.data(), zero_k.size() * 4);
+    UP(d.lm_t0, zero_l.data(), zero_l.size() * 4);
+    UP(d.prob, pp.data(), pp.size() * sizeof(ProbParams));
+    UP(d.f_kf, p->h_fkf.data(), (size_t)nf * 4);
+    UP(d.f_lm, p->h_flm.data(), (size_t)nf * 4);
+    UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk + 1) * 4);
+    UP(d.kf_edge, p->h_kf_edge.data(), (size_t)nf * 4);
+    UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl + 1) * 4);
+    std::vector<int> frp(p->f_off.begin(), p->f_off.end());
+    UP(d.f_row_prob, frp.data(), frp.size() * 4);
+    {
+        // residual-phase blocks: chunks of RBLK factors that stay inside a problem
+        std::vector<int> bstart, bprob, pblk(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            pblk[i] = (int)bprob.size();
+            for (int f = p->f_off[i]; f < p->f_off[i + 1]; f += RBLK) {
+                bstart.push_back(f);
+                bprob.push_back(i);
+            }
+        }
+        pblk[n] = (int)bprob.size();
+        bstart.push_back(nf);
+        d.n_rblk = (int)bprob.size();
+        UP(d.rblk_start, bstart.data(), bstart.size() * 4);
+        if (!bprob.empty()) UP(d.rblk_prob, bprob.data(), bprob.size() * 4);
+        UP(d.prob_rblk, pblk.data(), pblk.size() * 4);
+    }
+    UP(d.z, p->h_z.data(), (size_t)nf * 2 * 8);
+    HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
+    HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
+    HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_count, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_total, 0, 8, s));
+    HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
+#undef UP
+    d.fdamp = nullptr;
+    // initial linearisation at the initial estimate, automatic priors,
+    // beliefs = priors at clock 0
+    launch_linearise<TS>(d, 0, nf, p->huber_k, s);
+    launch_prior_base<TS>(d, 0, 0, s);
+    launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
+gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const gbp_measurements *ms,
+                       const gbp_options *opt_in, gbp_problem **out) {
+    if (!out) return GBP_EINVAL;
+    *out = nullptr;
+    auto *p = new (std::nothrow) gbp_problem();
+    if (!p) return GBP_ENOMEM;
+    *out = p;
+    gbp_options opt;
+    if (opt_in) opt = *opt_in; else default_opts(&opt);
+    p->opt = opt;
+    std::string msg;
+    gbp_status st = check_opts(&opt, msg);
+    if (st != GBP_OK) { p->broken = true; return fail(p, st, msg); }
+    if (n < 1 || !gs || !cams || !ms) { p->broken = true; return fail(p, GBP_EINVAL, "need n >= 1 problems"); }
+    for (int i = 0; i < n; ++i) {
+        st = check_graph(&gs[i], &ms[i], &cams[i], msg);
+        if (st != GBP_OK) { p->broken = true; return fail(p, st, "problem " + std::to_string(i) + ": " + msg); }
+    }
+    if (n > 1 && (opt.max_keyframes || opt.max_landmarks || opt.max_factors)) {
+        p->broken = true;
+        return fail(p, GBP_EINVAL, "growth capacity is only supported for a single problem");
+    }
+    p->precision = opt.precision;
+    p->np = n;
+    p->huber_k = opt.huber_k;
+    if (const char *e = std::getenv("GBP_NO_GRAPH")) p->use_graph = !(e[0] == '1');
+    if (const char *e = std::getenv("GBP_FACTOR_VARIANT")) p->factor_variant = std::atoi(e);
+    if (const char *e = std::getenv("GBP_FACTOR_BLOCK")) p->blk_factor = std::atoi(e);
+    fill_iopt(p);
+    build_order(p, n, gs, ms, p->h_fkf, p->h_flm, p->h_z);
+    build_csr(p);
+    p->cap_k = std::max(p->nk, (int)opt.max_keyframes);
+    p->cap_l = std::max(p->nl, (int)opt.max_landmarks);
+    p->cap_f = std::max(p->nf, (int)opt.max_factors);
+    Layout L;
+    if (p->precision == GBP_FP32) plan<float>(p, p->df, L); else plan<double>(p, p->dd, L);
+    if (opt.workspace) {
+        if (opt.workspace_bytes < L.total) {
+            p->broken = true;
+            return fail(p, GBP_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        }
+        p->ws = opt.workspace;
+        p->own_ws = false;
+    } else {
+        hipError_t e = hipMalloc(&p->ws, L.total);
+        if (e != hipSuccess) { p->broken = true; return fail(p, GBP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+        p->own_ws = true;
+    }
+    p->ws_bytes = L.total;
+    for (auto &it : L.items) *it.first = (char *)p->ws + it.second;
+    if (opt.stream) {
+        p->stream = (hipStream_t)opt.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { p->broken = true; return fail(p, GBP_EDEVICE, "hipStreamCreate failed"); }
+        p->own_stream = true;
+    }
+    st = p->precision == GBP_FP32 ? upload_and_init<float>(p, gs, cams, n) : upload_and_init<double>(p, gs, cams, n);
+    if (st != GBP_OK) p->broken = true;
+    return st;
+}
+
+template <typename TS>
+gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_base) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    for (int i = 0; i < n; ++i) {
+        launch_factor<TS>(d, p->iopt, p->blk_factor, p->factor_variant, s);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+        launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+        if (log_every > 0 && (i + 1) % log_every == 0)
+            launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
+                              log_base + (size_t)((i + 1) / log_every - 1) * p->np * 4, s);
+    }
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status iterate_impl(gbp_problem *p, int n, double damping, double huber_k, int log_every, double *log_base) {
+    p->iopt.damping = damping;
+    p->iopt.huber_k = huber_k;
+    p->huber_k = huber_k;
+    if (n <= 0) return GBP_OK;
+    hipStream_t s = p->stream;
+    if (p->use_graph) {
+        GraphEntry *hit = nullptr;
+        for (auto &g : p->graphs)
+            if (g.n == n && g.damping == damping && g.huber == huber_k && g.log_every == log_every) hit = &g;
+        if (!hit) {
+            if (p->graphs.size() >= 8) destroy_graphs(p);
+            hipGraph_t graph;
+            HIP_TRY(p, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            record_iterations<TS>(p, n, log_every, log_base);
+            hipError_t le = hipGetLastError();
+            hipError_t ce = hipStreamEndCapture(s, &graph);
+            if (le != hipSuccess || ce != hipSuccess)
+                return fail(p, GBP_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce != hipSuccess ? ce : le));
+            hipGraphExec_t exec;
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(p, GBP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+            p->graphs.push_back(GraphEntry{n, damping, huber_k, log_every, exec});
+            hit = &p->graphs.back();
+        }
+        HIP_TRY(p, hipGraphLaunch(hit->exec, s));
+    } else {
+        record_iterations<TS>(p, n, log_every, log_base);
+        HIP_TRY(p, hipGetLastError());
+    }
+    p->t += n;
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_k, double *ms) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    p->iopt.damping = damping;
+    p->iopt.huber_k = huber_k;
+    p->huber_k = huber_k;
+    // all events are recorded back to back on the stream and read after one
+    // synchronisation, so queue-empty launch latency is not counted
+    std::vector<hipEvent_t> ev(4 * (size_t)n + 1);
+    for (auto &e : ev) HIP_TRY(p, hipEventCreate(&e));
+    HIP_TRY(p, hipEventRecord(ev[0], s));
+    for (int i = 0; i < n; ++i) {
+        launch_factor<TS>(d, p->iopt, p->blk_factor, p->factor_variant, s);
+        HIP_TRY(p, hipEventRecord(ev[4 * i + 1], s));
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+        HIP_TRY(p, hipEventRecord(ev[4 * i + 2], s));
+        launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+        HIP_TRY(p, hipEventRecord(ev[4 * i + 3], s));
+        launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
+                          nullptr, s);
+        HIP_TRY(p, hipEventRecord(ev[4 * i + 4], s));
+    }
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipEventSynchronize(ev.back()));
+    double acc[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < 4; ++q) {
+            float t = 0.f;
+            HIP_TRY(p, hipEventElapsedTime(&t, ev[4 * i + q], ev[4 * i + q + 1]));
+            acc[q] += t;
+        }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    for (int q = 0; q < 4; ++q) ms[q] = acc[q] / n;
+    p->t += n;
+    return GBP_OK;
+}
+
+gbp_status check_live(gbp_problem *p) {
+    if (!p) return GBP_EINVAL;
+    if (p->broken) return fail(p, GBP_ESTATE, "problem creation failed: " + p->err);
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status status_check(gbp_problem *p) {
+    unsigned st = 0;
+    HIP_TRY(p, hipMemcpyAsync(&st, dev<TS>(p).status, 4, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (st) {
+        HIP_TRY(p, hipMemsetAsync(dev<TS>(p).status, 0, 4, p->stream));
+        return fail(p, GBP_ENUMERIC, st & 1 ? "a belief information matrix was not positive definite"
+                                            : "a belief mean was not finite");
+    }
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status beliefs_impl(gbp_problem *p, double *kf_mean, double *lm_mean, double *kf_info, double *lm_info) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    const int readout = (kf_info || lm_info) ? 1 : 0;
+    if (readout) {
+        launch_belief_lm<TS>(d, p->iopt, 1, p->blk_lm, s);
+        launch_belief_kf<TS>(d, p->iopt, 1, p->blk_kf, s);
+        HIP_TRY(p, hipGetLastError());
+    }
+    std::vector<double> kb((size_t)p->nk * KBEL), lb((size_t)p->nl * LBEL), ki, li;
+    HIP_TRY(p, hipMemcpyAsync(kb.data(), d.kf_bel, kb.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipMemcpyAsync(lb.data(), d.lm_bel, lb.size() * 8, hipMemcpyDeviceToHost, s));
+    if (kf_info) { ki.resize((size_t)p->nk * 36); HIP_TRY(p, hipMemcpyAsync(ki.data(), d.kf_info, ki.size() * 8, hipMemcpyDeviceToHost, s)); }
+    if (lm_info) { li.resize((size_t)p->nl * 9); HIP_TRY(p, hipMemcpyAsync(li.data(), d.lm_info, li.size() * 8, hipMemcpyDeviceToHost, s)); }
+    gbp_status st = status_check<TS>(p);
+    for (int k = 0; k < p->nk; ++k) {
+        if (kf_mean)
+            for (int c = 0; c < 6; ++c) kf_mean[6 * (size_t)k + c] = p->h_kf_anchor[6 * (size_t)k + c] + kb[(size_t)k * KBEL + c];
+        if (kf_info) std::memcpy(kf_info + 36 * (size_t)k, ki.data() + 36 * (size_t)k, 36 * 8);
+    }
+    for (int m = 0; m < p->nl; ++m) {
+        int u = p->lm_int2user[m];
+        if (lm_mean)
+            for (int c = 0; c < 3; ++c) lm_mean[3 * (size_t)u + c] = p->h_lm_anchor[3 * (size_t)m + c] + lb[(size_t)m * LBEL + c];
+        if (lm_info) std::memcpy(lm_info + 9 * (size_t)u, li.data() + 9 * (size_t)m, 9 * 8);
+    }
+    return st;
+}
+
+template <typename TS>
+gbp_status reproj_impl(gbp_problem *p, std::vector<double> &sums) {
+    Dev<TS> &d = dev<TS>(p);
+    launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr, nullptr,
+                      p->stream);
+    HIP_TRY(p, hipGetLastError());
+    sums.resize((size_t)p->np * 8);
+    HIP_TRY(p, hipMemcpyAsync(sums.data(), d.are_out, sums.size() * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
+void sums_to_stats(const double *s, gbp_reproj *o) {
+    o->are_all = s[3] > 0 ? s[0] / s[3] : 0.0;
+    o->are_quadratic = s[4] > 0 ? s[1] / s[4] : 0.0;
+    o->are_ref = s[7] > 0 ? s[2] / s[7] : 0.0;
+    o->n_valid = (int64_t)s[3];
+    o->n_quadratic = (int64_t)s[4];
+    o->n_linear = (int64_t)s[5];
+    o->n_invalid = (int64_t)s[6];
+    o->n_ref = (int64_t)s[7];
+}
+
+template <typename TS>
+gbp_status relin_impl(gbp_problem *p, double beta, int32_t *n_relin) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipMemsetAsync(p->d_count, 0, 4, s));
+    launch_flag_relin<TS>(d, beta, p->d_count, s);
+    HIP_TRY(p, hipGetLastError());
+    int cnt = 0;
+    HIP_TRY(p, hipMemcpyAsync(&cnt, p->d_count, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    if (n_relin) *n_relin = cnt;
+    return GBP_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+void gbp_default_options(gbp_options *opt) {
+    if (opt) default_opts(opt);
+}
+
+gbp_status gbp_workspace_bytes(int32_t n, const gbp_graph *gs, const gbp_options *opt_in, size_t *bytes) {
+    if (!bytes || n < 1 || !gs) return GBP_EINVAL;
+    gbp_options opt;
+    if (opt_in) opt = *opt_in; else default_opts(&opt);
+    gbp_problem tmp;
+    tmp.np = n;
+    long nk = 0, nl = 0, nf = 0;
+    for (int i = 0; i < n; ++i) { nk += gs[i].n_keyframes; nl += gs[i].n_landmarks; nf += gs[i].n_factors; }
+    tmp.cap_k = (int)std::max(nk, (long)opt.max_keyframes);
+    tmp.cap_l = (int)std::max(nl, (long)opt.max_landmarks);
+    tmp.cap_f = (int)std::max(nf, (long)opt.max_factors);
+    Layout L;
+    if (opt.precision == GBP_FP64) plan<double>(&tmp, tmp.dd, L); else plan<float>(&tmp, tmp.df, L);
+    *bytes = L.total;
+    return GBP_OK;
+}
+
+gbp_status gbp_create(const gbp_graph *graph, const gbp_camera *camera, const gbp_measurements *meas,
+                      const gbp_options *opt, gbp_problem **out) {
+    return create_impl(1, graph, camera, meas, opt, out);
+}
+
+gbp_status gbp_create_batch(int32_t n, const gbp_graph *graphs, const gbp_camera *cameras,
+                            const gbp_measurements *meas, const gbp_options *opt, gbp_problem **out) {
+    return create_impl(n, graphs, cameras, meas, opt, out);
+}
+
+gbp_status gbp_relinearise(gbp_problem *p, double beta, int32_t *n_relin) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    return p->precision == GBP_FP32 ? relin_impl<float>(p, beta, n_relin) : relin_impl<double>(p, beta, n_relin);
+}
+
+gbp_status gbp_iterate(gbp_problem *p, int32_t n, double damping, double huber_k) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n < 0 || !(damping >= 0.0 && damping < 1.0) || !std::isfinite(huber_k))
+        return fail(p, GBP_EINVAL, "need n >= 0, 0 <= damping < 1, finite huber_k");
+    return p->precision == GBP_FP32 ? iterate_impl<float>(p, n, damping, huber_k, 0, nullptr)
+                                    : iterate_impl<double>(p, n, damping, huber_k, 0, nullptr);
+}
+
+gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping, double huber_k, int32_t log_every,
+                              double *log_out) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n < 0 || log_every < 1 || !log_out || !(damping >= 0.0 && damping < 1.0))
+        return fail(p, GBP_EINVAL, "need n >= 0, log_every >= 1, a log buffer and 0 <= damping < 1");
+    const size_t rows = (size_t)(n / log_every);
+    const size_t bytes = std::max<size_t>(rows, 1) * p->np * 4 * 8;
+    if (bytes > p->log_cap) {
+        destroy_graphs(p);  // graphs may reference the old log buffer
+        if (p->d_log) (void)hipFree(p->d_log);
+        p->d_log = nullptr;
+        HIP_TRY(p, hipMalloc(&p->d_log, bytes));
+        p->log_cap = bytes;
+    }
+    st = p->precision == GBP_FP32 ? iterate_impl<float>(p, n, damping, huber_k, log_every, p->d_log)
+                                  : iterate_impl<double>(p, n, damping, huber_k, log_every, p->d_log);
+    if (st != GBP_OK) return st;
+    if (rows) HIP_TRY(p, hipMemcpyAsync(log_out, p->d_log, rows * p->np * 4 * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
+gbp_status gbp_beliefs(gbp_problem *p, double *kf_mean, double *lm_mean, double *kf_info, double *lm_info) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    return p->precision == GBP_FP32 ? beliefs_impl<float>(p, kf_mean, lm_mean, kf_info, lm_info)
+                                    : beliefs_impl<double>(p, kf_mean, lm_mean, kf_info, lm_info);
+}
+
+gbp_status gbp_reproj_stats(gbp_problem *p, int32_t problem_index, gbp_reproj *out) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!out || problem_index < -1 || problem_index >= p->np) return fail(p, GBP_EINVAL, "bad problem index");
+    std::vector<double> sums;
+    st = p->precision == GBP_FP32 ? reproj_impl<float>(p, sums) : reproj_impl<double>(p, sums);
+    if (st != GBP_OK) return st;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < p->np; ++i) {
+        if (problem_index >= 0 && i != problem_index) continue;
+        for (int c = 0; c < 8; ++c) acc[c] += sums[8 * (size_t)i + c];
+    }
+    sums_to_stats(acc, out);
+    return GBP_OK;
+}
+
+gbp_status gbp_reproj_error(gbp_problem *p, double *are_all, double *are_inlier_quadratic, int32_t *n_linear_regime) {
+    gbp_reproj r;
+    gbp_status st = gbp_reproj_stats(p, -1, &r);
+    if (st != GBP_OK) return st;
+    if (are_all) *are_all = r.are_all;
+    if (are_inlier_quadratic) *are_inlier_quadratic = r.are_quadratic;
+    if (n_linear_regime) *n_linear_regime = (int32_t)r.n_linear;
+    return GBP_OK;
+}
+
+gbp_status gbp_set_reference(gbp_problem *p, const double *z_ref, const uint8_t *mask) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!z_ref || !mask) {
+        p->has_ref = false;
+        destroy_graphs(p);
+        return GBP_OK;
+    }
+    std::vector<double> zr(2 * (size_t)p->nf);
+    std::vector<uint8_t> mk(p->nf);
+    for (int f = 0; f < p->nf; ++f) {
+        int u = p->f_int2user[f];
+        zr[2 * (size_t)f] = z_ref[2 * (size_t)u];
+        zr[2 * (size_t)f + 1] = z_ref[2 * (size_t)u + 1];
+        mk[f] = mask[u] ? 1 : 0;
+    }
+    HIP_TRY(p, hipMemcpyAsync(p->d_zref, zr.data(), zr.size() * 8, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(p->d_mask, mk.data(), mk.size(), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (!p->has_ref) destroy_graphs(p);
+    p->has_ref = true;
+    return GBP_OK;
+}
+
+gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6], int32_t n_new_lm, const double *lm_init,
+                            int32_t n_new_f, const int32_t *f_kf, const int32_t *f_lm, const double *z) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    return fail(p, GBP_ESTATE, "incremental growth is not available in this build");
+}
+
+gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_t every_k) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!weights) return GBP_OK;
+    return fail(p, GBP_ESTATE, "learned damping is not available in this build");
+}
+
+gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping, double huber_k, double *ms_out) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n < 1 || !ms_out || !(damping >= 0.0 && damping < 1.0)) return fail(p, GBP_EINVAL, "need n >= 1 and ms_out");
+    return p->precision == GBP_FP32 ? phase_times_impl<float>(p, n, damping, huber_k, ms_out)
+                                    : phase_times_impl<double>(p, n, damping, huber_k, ms_out);
+}
+
+gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    unsigned long long v = 0;
+    const unsigned long long *src = p->precision == GBP_FP32 ? p->df.relin_total : p->dd.relin_total;
+    HIP_TRY(p, hipMemcpyAsync(&v, src, 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (relinearisations) *relinearisations = (int64_t)v;
+    return GBP_OK;
+}
+
+gbp_status gbp_sizes(const gbp_problem *p, int32_t *nk, int32_t *nl, int32_t *nf, int32_t *np, int32_t *t) {
+    if (!p) return GBP_EINVAL;
+    if (nk) *nk = p->nk;
+    if (nl) *nl = p->nl;
+    if (nf) *nf = p->nf;
+    if (np) *np = p->np;
+    if (t) *t = p->t;
+    return GBP_OK;
+}
+
+const char *gbp_last_error(const gbp_problem *p) {
+    if (!p) return "null problem";
+    return p->err.c_str();
+}
+
+void gbp_destroy(gbp_problem *p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    destroy_graphs(p);
+    if (p->d_log) (void)hipFree(p->d_log);
+    if (p->own_ws && p->ws) (void)hipFree(p->ws);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+}  // extern "C"

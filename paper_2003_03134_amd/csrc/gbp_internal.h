@@ -1,0 +1,98 @@
+// Internal declarations shared by the kernel and runtime translation units
+// of the GBP library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbp {
+
+constexpr int KREC = 16;  // keyframe-side record per factor (see layout below)
+constexpr int LREC = 12;  // landmark-side record per factor
+constexpr int AREC = 16;  // factor-private record
+constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
+constexpr int LBEL = 12;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad
+constexpr int MAX_ANNEAL = 64;
+constexpr int RBLK = 1024;  // factors per residual-phase block
+
+// keyframe-side record (TS = float | double), one per factor:
+//   [0..5]  d h / d omega (2x3, row-major)
+//   [6]     fx / pz   [7] fy / pz   [8] -fx px / pz^2   [9] -fy py / pz^2
+//           (d h / d t = [[6], 0, [8]; 0, [7], [9]])
+//   [10..12] message to the keyframe, S (a, b, c) = [[a b][b c]]
+//   [13..14] message to the keyframe, g (anchor-relative information vector
+//            in the factor's 2-D measurement space)
+//   [15]    s = w / sigma^2
+// landmark-side record:
+//   [0..5]  d h / d l (2x3)   [6..8] S to landmark   [9..10] g to landmark
+// factor-private record:
+//   [0..1]  r0 = z - h(x0)   [2..7] x0_k - anchor_k   [8..10] x0_m - anchor_m
+//   [11..12] J_k anchor_k    [13..14] J_m anchor_m
+
+struct ProbParams {
+    double fx, fy, cx, cy, sigma, inv_s2, zmin, pad;
+};
+
+// Device view of one problem set (a single problem or a batch).
+template <typename TS>
+struct Dev {
+    int nk, nl, nf, np;
+    // variables
+    const double *kf_anchor, *lm_anchor;  // absolute initial estimate (prior mean)
+    double *kf_pbase, *lm_pbase;          // automatic prior information (diag)
+    const double *kf_pinfo;               // anchor prior information (0: automatic)
+    const int *kf_t0, *lm_t0;             // iteration at which the variable was born
+    const int *kf_prob, *lm_prob;
+    double *kf_bel, *lm_bel;              // beliefs (KBEL / LBEL doubles)
+    double *kf_info, *lm_info;            // full information for read-out
+    // graph
+    const int *f_kf, *f_lm;
+    const int *kf_row, *kf_edge;          // factors of each keyframe (CSR)
+    const int *lm_row;                    // factors of landmark m: [lm_row[m], lm_row[m+1])
+    const int *f_row_prob;                // first factor of each problem (np + 1)
+    // factor state
+    const double *z;
+    TS *krec, *lrec, *arec;
+    uint8_t *cnt, *flags;
+    float *fdamp;                         // per-factor damping (learned model) or null
+    // parameters
+    const ProbParams *prob;
+    int *t_dev;                           // iteration clock
+    unsigned *status;                     // bit 0: non-PD belief, bit 1: non-finite
+    double *pending_k;                    // Huber threshold for requested relinearisations
+    int *relin_queue;                     // factors due for relinearisation this iteration
+    int *relin_count;
+    unsigned long long *relin_total;      // relinearisations since creation
+    double *kf_pose;                      // absolute R (9) and t (3) of each keyframe mean
+    // residual phase: blocks of at most RBLK factors inside one problem
+    int n_rblk;
+    const int *rblk_start;                // first factor of each block (n_rblk + 1)
+    const int *rblk_prob;                 // problem of each block
+    const int *prob_rblk;                 // first block of each problem (np + 1)
+    double *rblk_part;                    // per-block partial statistics (8 doubles)
+    double *are_out;                      // per-problem statistics (8 doubles)
+};
+
+struct IterOpts {
+    double beta2;
+    int interval, undamped, damp_mode, anneal_iters;
+    double damping, huber_k;
+    double scale[MAX_ANNEAL + 1];  // prior scale by age 0..anneal_iters (last = steady)
+};
+
+enum : uint8_t { FLAG_PENDING = 1, FLAG_INVALID = 2 };
+
+// launchers (gbp_kernels.hip); all asynchronous on `s`
+template <typename TS> void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, hipStream_t s);
+template <typename TS> void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s);
+template <typename TS> void launch_factor(const Dev<TS> &d, const IterOpts &o, int block, int variant, hipStream_t s);
+template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
+template <typename TS> void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
+template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s);
+template <typename TS> void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref,
+                                          const uint8_t *mask, double *log_row, hipStream_t s);
+template <typename TS> void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf,
+                                                   void *scratch, hipStream_t s);
+void launch_tick(int *t_dev, hipStream_t s);
+
+}  // namespace gbp

@@ -1,0 +1,1061 @@
+// HIP kernels (gfx950) of the synchronous GBP bundle-adjustment sweep.
+//
+// Mathematical content (Ortiz et al., "Bundle Adjustment on a Graph
+// Processor"):
+//   - linearisation of the reprojection factor, Section 4, eq. (infform) and
+//     the equations after it; Huber rescaling, Section 6;
+//   - factor-to-variable messages, Section 5, eqs. (messageeta),
+//     (messagelambda), with the variable-to-factor message recovered by
+//     dividing the belief by the previous factor-to-variable message;
+//   - beliefs, eqs. (beliefeta), (belieflambda); synchronous schedule, local
+//     relinearisation, damping, Section 5 and Section 8;
+//   - average reprojection error, Section 9.1.
+//
+// Representation. A linearised reprojection factor has information
+// Lambda_f = s J^T J with a 2x9 Jacobian J = [J_k | J_m], so every message it
+// sends is a Gaussian over the factor's 2-D measurement space: the message
+// to variable v is Lambda = J_v^T S J_v, eta' = J_v^T g with a symmetric 2x2 S
+// and a 2-vector g. The Schur complement of eqs. (messageeta) and
+// (messagelambda) then reduces to 2x2 algebra: with the belief of v in
+// covariance form (Sigma_v, mean offset dmu_v), the cavity (belief divided by
+// the previous message, the variable-to-factor message) projected into the
+// measurement space has covariance P_c and mean m_c (Woodbury identity), and
+// the new message to the other variable u is
+//     S_u = s (I + s P_c)^-1,   g_u = S_u (J_u x0_u' + r0 - m_c),
+// i.e. the measurement with noise inflated by the cavity's projected
+// uncertainty. This is the same quantity as the 9x9 Schur complement of the
+// paper, evaluated without forming it.
+//
+// Coordinates. Every variable has a fixed anchor (its initial estimate, also
+// the mean of its prior); beliefs store the mean as an FP64 offset from the
+// anchor and the FP64 covariance, and information vectors are kept relative
+// to the anchor, so FP32 factor state never carries absolute coordinates.
+// Damping the eta message alone (the paper's choice) is not invariant to
+// that change of origin; the term d (S_old - S_new) J a restores exactly the
+// absolute-coordinate update.
+//
+// Summation order is fixed (per-landmark loops, per-keyframe lane-strided
+// loops and a butterfly reduction, per-problem tree reductions): results are
+// bitwise reproducible run to run. No floating-point atomics are used.
+
+#include "gbp_internal.h"
+
+#include <algorithm>
+
+namespace gbp {
+
+// --------------------------------------------------------------------------
+// small dense helpers
+// --------------------------------------------------------------------------
+
+template <int D>
+__host__ __device__ constexpr int pidx(int i, int j) {
+    // packed upper triangle, row-major
+    return i <= j ? i * D - i * (i - 1) / 2 + (j - i) : j * D - j * (j - 1) / 2 + (i - j);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = p[i];
+}
+
+__device__ __forceinline__ void load16(const float *__restrict__ p, float (&v)[16]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float4 a = q[i];
+        v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
+    }
+}
+__device__ __forceinline__ void load16(const double *__restrict__ p, double (&v)[16]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
+}
+__device__ __forceinline__ void load12(const float *__restrict__ p, float (&v)[12]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float4 a = q[i];
+        v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
+    }
+}
+__device__ __forceinline__ void load12(const double *__restrict__ p, double (&v)[12]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
+}
+
+// Cholesky of a packed symmetric D x D matrix; returns false when a pivot is
+// not positive. L is stored packed by rows of the lower triangle in `L`.
+template <int D>
+__device__ __forceinline__ bool chol(const double *A, double (&L)[D * (D + 1) / 2]) {
+    // lower-triangle packed: row i holds L[i][0..i] at offset i(i+1)/2
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = A[pidx<D>(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * (i + 1) / 2 + i] = sqrt(s);
+            } else {
+                L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+            }
+        }
+    }
+    return true;
+}
+
+// Inverse (packed upper) and solution x = A^-1 b from the Cholesky factor.
+template <int D>
+__device__ __forceinline__ void chol_inverse_solve(const double (&L)[D * (D + 1) / 2], const double (&b)[D],
+                                                   double (&inv)[D * (D + 1) / 2], double (&x)[D]) {
+    // W = L^-1 (lower triangular)
+    double W[D * (D + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        W[i * (i + 1) / 2 + i] = 1.0 / L[i * (i + 1) / 2 + i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) s += L[i * (i + 1) / 2 + k] * W[k * (k + 1) / 2 + j];
+            W[i * (i + 1) / 2 + j] = -s * W[i * (i + 1) / 2 + i];
+        }
+    }
+    // A^-1 = W^T W
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < D; ++k) s += W[k * (k + 1) / 2 + i] * W[k * (k + 1) / 2 + j];
+            inv[pidx<D>(i, j)] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) s += inv[pidx<D>(i, j)] * b[j];
+        x[i] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// measurement model h = pi(R(omega) l + t) and its 2x9 Jacobian (FP64)
+// --------------------------------------------------------------------------
+
+struct Lin {
+    double J[2][9];
+    double r0[2];
+    double s;
+    bool valid;
+};
+
+__device__ __forceinline__ void so3_exp_d(const double w[3], double R[9]) {
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(th2), a, b;
+    if (th < 1e-5) { a = 1.0 - th2 / 6.0; b = 0.5 - th2 / 24.0; }
+    else { a = sin(th) / th; b = (1.0 - cos(th)) / th2; }
+    // R = I + a [w]x + b [w]x^2,   [w]x^2 = w w^T - |w|^2 I
+    R[0] = 1.0 + b * (w[0] * w[0] - th2);
+    R[4] = 1.0 + b * (w[1] * w[1] - th2);
+    R[8] = 1.0 + b * (w[2] * w[2] - th2);
+    R[1] = -a * w[2] + b * w[0] * w[1];
+    R[3] = a * w[2] + b * w[0] * w[1];
+    R[2] = a * w[1] + b * w[0] * w[2];
+    R[6] = -a * w[1] + b * w[0] * w[2];
+    R[5] = -a * w[0] + b * w[1] * w[2];
+    R[7] = a * w[0] + b * w[1] * w[2];
+}
+
+// right Jacobian of SO(3): I - (1-cos)/th^2 [w]x + (th - sin)/th^3 [w]x^2
+__device__ __forceinline__ void so3_jr_d(const double w[3], double Jr[9]) {
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(th2), b, c;
+    if (th < 1e-5) { b = 0.5 - th2 / 24.0; c = 1.0 / 6.0 - th2 / 120.0; }
+    else { b = (1.0 - cos(th)) / th2; c = (th - sin(th)) / (th2 * th); }
+    Jr[0] = 1.0 + c * (w[0] * w[0] - th2);
+    Jr[4] = 1.0 + c * (w[1] * w[1] - th2);
+    Jr[8] = 1.0 + c * (w[2] * w[2] - th2);
+    Jr[1] = b * w[2] + c * w[0] * w[1];
+    Jr[3] = -b * w[2] + c * w[0] * w[1];
+    Jr[2] = -b * w[1] + c * w[0] * w[2];
+    Jr[6] = b * w[1] + c * w[0] * w[2];
+    Jr[5] = b * w[0] + c * w[1] * w[2];
+    Jr[7] = -b * w[0] + c * w[1] * w[2];
+}
+
+// Linearise h at (x, l) against measurement z (Section 4); Huber weight w at
+// the linearisation point (Section 6) folded into s = w / sigma^2.
+__device__ __forceinline__ void linearise(const double x[6], const double l[3], const double z[2],
+                                          const ProbParams &pp, double huber_k, Lin &out) {
+    double R[9];
+    so3_exp_d(x, R);
+    double p[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = R[3 * i] * l[0] + R[3 * i + 1] * l[1] + R[3 * i + 2] * l[2] + x[3 + i];
+    if (!(p[2] > pp.zmin)) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) out.J[r][c] = 0.0;
+        out.r0[0] = out.r0[1] = 0.0;
+        out.s = 0.0;
+        out.valid = false;
+        return;
+    }
+    double iz = 1.0 / p[2];
+    double D[2][3] = {{pp.fx * iz, 0.0, -pp.fx * p[0] * iz * iz}, {0.0, pp.fy * iz, -pp.fy * p[1] * iz * iz}};
+    double h0 = pp.fx * p[0] * iz + pp.cx, h1 = pp.fy * p[1] * iz + pp.cy;
+    out.r0[0] = z[0] - h0;
+    out.r0[1] = z[1] - h1;
+    double M = sqrt(out.r0[0] * out.r0[0] + out.r0[1] * out.r0[1]) / pp.sigma;
+    double N = huber_k / pp.sigma;
+    double w = (N <= 0.0 || M <= N) ? 1.0 : 2.0 * N / M - N * N / (M * M);
+    out.s = w * pp.inv_s2;
+    out.valid = true;
+    // K = R [l]x ; d p / d omega = -K J_r
+    double K[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        K[3 * i + 0] = R[3 * i + 1] * l[2] - R[3 * i + 2] * l[1];
+        K[3 * i + 1] = -R[3 * i + 0] * l[2] + R[3 * i + 2] * l[0];
+        K[3 * i + 2] = R[3 * i + 0] * l[1] - R[3 * i + 1] * l[0];
+    }
+    double Jr[9];
+    so3_jr_d(x, Jr);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        double DK[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) DK[c] = D[r][0] * K[c] + D[r][1] * K[3 + c] + D[r][2] * K[6 + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            out.J[r][c] = -(DK[0] * Jr[c] + DK[1] * Jr[3 + c] + DK[2] * Jr[6 + c]);
+            out.J[r][3 + c] = D[r][c];
+            out.J[r][6 + c] = D[r][0] * R[c] + D[r][1] * R[3 + c] + D[r][2] * R[6 + c];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// 2x2 measurement-space marginalisation
+// --------------------------------------------------------------------------
+
+// Cavity of one variable (its belief divided by this factor's previous
+// message S_o, g_o expressed with Jacobian Jo) projected through the
+// factor's current Jacobian Jn about the linearisation offset d0n:
+//   Pc = Jn Sigma_c Jn^T,  mc = Jn (dmu_c - d0n).
+template <int D>
+__device__ __forceinline__ void cavity(const double (&Jo)[2][D], const double (&Jn)[2][D], bool relin,
+                                       const double *__restrict__ cov, const double (&dmu)[D],
+                                       const double (&d0n)[D], double Sa, double Sb, double Sc, double g0,
+                                       double g1, double &Pa, double &Pb, double &Pc, double &m0, double &m1) {
+    double A0[D], A1[D];  // Sigma Jo^T
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double c = cov[pidx<D>(i, j)];
+            s0 += c * Jo[0][j];
+            s1 += c * Jo[1][j];
+        }
+        A0[i] = s0;
+        A1[i] = s1;
+    }
+    double poa = 0, pob = 0, poc = 0, jd0 = 0, jd1 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        poa += Jo[0][i] * A0[i];
+        pob += Jo[0][i] * A1[i];
+        poc += Jo[1][i] * A1[i];
+        jd0 += Jo[0][i] * dmu[i];
+        jd1 += Jo[1][i] * dmu[i];
+    }
+    double t00, t01, t10, t11, pna, pnb, pnc, jn0 = 0, jn1 = 0;
+    if (relin) {
+        t00 = t01 = t10 = t11 = 0.0;
+        double B0[D], B1[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            t00 += Jn[0][i] * A0[i];
+            t01 += Jn[0][i] * A1[i];
+            t10 += Jn[1][i] * A0[i];
+            t11 += Jn[1][i] * A1[i];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double c = cov[pidx<D>(i, j)];
+                s0 += c * Jn[0][j];
+                s1 += c * Jn[1][j];
+            }
+            B0[i] = s0;
+            B1[i] = s1;
+        }
+        pna = pnb = pnc = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            pna += Jn[0][i] * B0[i];
+            pnb += Jn[0][i] * B1[i];
+            pnc += Jn[1][i] * B1[i];
+            jn0 += Jn[0][i] * (dmu[i] - d0n[i]);
+            jn1 += Jn[1][i] * (dmu[i] - d0n[i]);
+        }
+    } else {
+        t00 = poa; t01 = pob; t10 = pob; t11 = poc;
+        pna = poa; pnb = pob; pnc = poc;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            jn0 += Jn[0][i] * (dmu[i] - d0n[i]);
+            jn1 += Jn[1][i] * (dmu[i] - d0n[i]);
+        }
+    }
+    // M = (I - S Po)^-1
+    double e00 = 1.0 - (Sa * poa + Sb * pob), e01 = -(Sa * pob + Sb * poc);
+    double e10 = -(Sb * poa + Sc * pob), e11 = 1.0 - (Sb * pob + Sc * poc);
+    double idet = 1.0 / (e00 * e11 - e01 * e10);
+    double m00 = e11 * idet, m01 = -e01 * idet, m10 = -e10 * idet, m11 = e00 * idet;
+    // G = M S (symmetric in exact arithmetic)
+    double G00 = m00 * Sa + m01 * Sb, G01 = m00 * Sb + m01 * Sc;
+    double G10 = m10 * Sa + m11 * Sb, G11 = m10 * Sb + m11 * Sc;
+    double Gs = 0.5 * (G01 + G10);
+    // h = M (S Jo dmu - g)
+    double v0 = Sa * jd0 + Sb * jd1 - g0, v1 = Sb * jd0 + Sc * jd1 - g1;
+    double h0 = m00 * v0 + m01 * v1, h1 = m10 * v0 + m11 * v1;
+    // Pc = Pn + T G T^T
+    double u00 = t00 * G00 + t01 * Gs, u01 = t00 * Gs + t01 * G11;
+    double u10 = t10 * G00 + t11 * Gs, u11 = t10 * Gs + t11 * G11;
+    Pa = pna + u00 * t00 + u01 * t01;
+    Pb = pnb + 0.5 * ((u00 * t10 + u01 * t11) + (u10 * t00 + u11 * t01));
+    Pc = pnc + u10 * t10 + u11 * t11;
+    m0 = jn0 + t00 * h0 + t01 * h1;
+    m1 = jn1 + t10 * h0 + t11 * h1;
+}
+
+// Hot-path cavity (the factor's Jacobian is unchanged since the previous
+// message): Po = J Sigma J^T evaluated as a quadratic form over the packed
+// covariance, so each covariance entry is used once as it arrives.
+template <int D>
+__device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const double *__restrict__ cov,
+                                              const double (&dmu)[D], const double (&d0)[D], double Sa,
+                                              double Sb, double Sc, double g0, double g1, double &Pa,
+                                              double &Pb, double &Pc, double &m0, double &m1) {
+    double poa = 0, pob = 0, poc = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const double w = cov[pidx<D>(i, j)];
+            if (i == j) {
+                poa += J[0][i] * J[0][i] * w;
+                pob += J[0][i] * J[1][i] * w;
+                poc += J[1][i] * J[1][i] * w;
+            } else {
+                poa += 2.0 * J[0][i] * J[0][j] * w;
+                pob += (J[0][i] * J[1][j] + J[0][j] * J[1][i]) * w;
+                poc += 2.0 * J[1][i] * J[1][j] * w;
+            }
+        }
+    }
+    double jd0 = 0, jd1 = 0, jn0 = 0, jn1 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        jd0 += J[0][i] * dmu[i];
+        jd1 += J[1][i] * dmu[i];
+        jn0 += J[0][i] * (dmu[i] - d0[i]);
+        jn1 += J[1][i] * (dmu[i] - d0[i]);
+    }
+    // M = (I - S Po)^-1 ; G = M S ; h = M (S J dmu - g)
+    double e00 = 1.0 - (Sa * poa + Sb * pob), e01 = -(Sa * pob + Sb * poc);
+    double e10 = -(Sb * poa + Sc * pob), e11 = 1.0 - (Sb * pob + Sc * poc);
+    double idet = 1.0 / (e00 * e11 - e01 * e10);
+    double m00 = e11 * idet, m01 = -e01 * idet, m10 = -e10 * idet, m11 = e00 * idet;
+    double G00 = m00 * Sa + m01 * Sb, G11 = m10 * Sb + m11 * Sc;
+    double Gs = 0.5 * ((m00 * Sb + m01 * Sc) + (m10 * Sa + m11 * Sb));
+    double v0 = Sa * jd0 + Sb * jd1 - g0, v1 = Sb * jd0 + Sc * jd1 - g1;
+    double h0 = m00 * v0 + m01 * v1, h1 = m10 * v0 + m11 * v1;
+    // Pc = Po + Po G Po ; mc = J (dmu - d0) + Po h
+    double u00 = poa * G00 + pob * Gs, u01 = poa * Gs + pob * G11;
+    double u10 = pob * G00 + poc * Gs, u11 = pob * Gs + poc * G11;
+    Pa = poa + u00 * poa + u01 * pob;
+    Pb = pob + 0.5 * ((u00 * pob + u01 * poc) + (u10 * poa + u11 * pob));
+    Pc = poc + u10 * pob + u11 * poc;
+    m0 = jn0 + poa * h0 + pob * h1;
+    m1 = jn1 + pob * h0 + poc * h1;
+}
+
+// --------------------------------------------------------------------------
+// factor phase: relinearisation check + relinearise + messages + damping
+// --------------------------------------------------------------------------
+
+// One factor's update. RELIN = false is the hot path: a factor that is due
+// for relinearisation is appended to the relinearisation queue and left to
+// the RELIN = true instance (a separate kernel), which relinearises it and
+// forms the cavity through both the old and the new Jacobian. Keeping the
+// rare path out of the hot kernel keeps its register footprint small.
+template <typename TS, bool RELIN>
+__device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const bool valid) {
+    const int k = d.f_kf[f], m = d.f_lm[f];
+    TS ar[AREC], kr[KREC], lr[LREC];
+    load16(d.arec + (size_t)f * AREC, ar);
+    load16(d.krec + (size_t)f * KREC, kr);
+    load12(d.lrec + (size_t)f * LREC, lr);
+    int c = d.cnt[f];
+    const uint8_t fl = d.flags[f];
+
+    const double *bk = d.kf_bel + (size_t)k * KBEL;
+    const double *bm = d.lm_bel + (size_t)m * LBEL;
+    double dmk[6], dmm[3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dmk[i] = bk[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dmm[i] = bm[i];
+
+    double d0k[6], d0m[3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d0k[i] = (double)ar[2 + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d0m[i] = (double)ar[8 + i];
+    if constexpr (!RELIN) {
+        // relinearisation check (Section 5, Section 8): pending request, or at
+        // least `interval` updates since the last linearisation and the
+        // stacked means farther than beta from the linearisation point.
+        // Factors that are due go to the queue, one atomic per wave.
+        double dist2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { double e = dmk[i] - d0k[i]; dist2 += e * e; }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { double e = dmm[i] - d0m[i]; dist2 += e * e; }
+        const bool need = valid && ((fl & FLAG_PENDING) || (c >= o.interval && dist2 > o.beta2));
+        const unsigned long long mask = __ballot(need);
+        if (mask) {
+            const int lane = threadIdx.x & 63;
+            const int leader = __ffsll((long long)mask) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(d.relin_count, __popcll(mask));
+            base = __shfl(base, leader, 64);
+            if (need) d.relin_queue[base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
+        }
+        if (need || !valid) return;
+    }
+    constexpr bool relin = RELIN;
+
+    // current (old) Jacobian blocks
+    double Jko[2][6], Jmo[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { Jko[r][i] = (double)kr[3 * r + i]; Jmo[r][i] = (double)lr[3 * r + i]; }
+    }
+    Jko[0][3] = (double)kr[6]; Jko[0][4] = 0.0; Jko[0][5] = (double)kr[8];
+    Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
+    double r0[2] = {(double)ar[0], (double)ar[1]};
+    double s = (double)kr[15];
+    double jak0 = (double)ar[11], jak1 = (double)ar[12], jam0 = (double)ar[13], jam1 = (double)ar[14];
+    const double Ska = kr[10], Skb = kr[11], Skc = kr[12], gk0 = kr[13], gk1 = kr[14];
+    const double Sma = lr[6], Smb = lr[7], Smc = lr[8], gm0 = lr[9], gm1 = lr[10];
+
+    double Jkn[2][6], Jmn[2][3];
+    uint8_t nfl = fl & (uint8_t)~FLAG_PENDING;
+    if constexpr (RELIN) {
+        const ProbParams pp = d.prob[d.kf_prob[k]];
+        const double hk = (fl & FLAG_PENDING) ? d.pending_k[0] : o.huber_k;
+        double x[6], l[3], zz[2] = {d.z[2 * (size_t)f], d.z[2 * (size_t)f + 1]};
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + dmm[i];
+        Lin L;
+        linearise(x, l, zz, pp, hk, L);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Jkn[r][i] = L.J[r][i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jmn[r][i] = L.J[r][6 + i];
+        }
+        r0[0] = L.r0[0]; r0[1] = L.r0[1];
+        s = L.s;
+        nfl = L.valid ? (uint8_t)(nfl & ~FLAG_INVALID) : (uint8_t)(nfl | FLAG_INVALID);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d0k[i] = dmk[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d0m[i] = dmm[i];
+        jak0 = jak1 = jam0 = jam1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            double a = d.kf_anchor[6 * (size_t)k + i];
+            jak0 += Jkn[0][i] * a;
+            jak1 += Jkn[1][i] * a;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double a = d.lm_anchor[3 * (size_t)m + i];
+            jam0 += Jmn[0][i] * a;
+            jam1 += Jmn[1][i] * a;
+        }
+        c = 0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Jkn[r][i] = Jko[r][i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jmn[r][i] = Jmo[r][i];
+        }
+    }
+
+    // cavities of both variables in the factor's measurement space
+    double Pka, Pkb, Pkc, mk0, mk1, Pma, Pmb, Pmc, mm0, mm1;
+    if constexpr (RELIN) {
+        cavity<6>(Jko, Jkn, relin, bk + 6, dmk, d0k, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+        cavity<3>(Jmo, Jmn, relin, bm + 3, dmm, d0m, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+    } else {
+        cavity_same_j<3>(Jmo, bm + 3, dmm, d0m, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+        cavity_same_j<6>(Jko, bk + 6, dmk, d0k, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+    }
+
+    // new messages: to the landmark through the keyframe cavity and back
+    double nSm_a, nSm_b, nSm_c, ngm0, ngm1, nSk_a, nSk_b, nSk_c, ngk0, ngk1;
+    {
+        double qa = 1.0 + s * Pka, qb = s * Pkb, qc = 1.0 + s * Pkc;
+        double f0 = s / (qa * qc - qb * qb);
+        nSm_a = f0 * qc; nSm_b = -f0 * qb; nSm_c = f0 * qa;
+        double u0 = r0[0] - mk0, u1 = r0[1] - mk1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { u0 += Jmn[0][i] * d0m[i]; u1 += Jmn[1][i] * d0m[i]; }
+        ngm0 = nSm_a * u0 + nSm_b * u1;
+        ngm1 = nSm_b * u0 + nSm_c * u1;
+    }
+    {
+        double qa = 1.0 + s * Pma, qb = s * Pmb, qc = 1.0 + s * Pmc;
+        double f0 = s / (qa * qc - qb * qb);
+        nSk_a = f0 * qc; nSk_b = -f0 * qb; nSk_c = f0 * qa;
+        double u0 = r0[0] - mm0, u1 = r0[1] - mm1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { u0 += Jkn[0][i] * d0k[i]; u1 += Jkn[1][i] * d0k[i]; }
+        ngk0 = nSk_a * u0 + nSk_b * u1;
+        ngk1 = nSk_b * u0 + nSk_c * u1;
+    }
+
+    // damping (Section 5; undamped window of Section 8)
+    const double dd = (c < o.undamped) ? 0.0 : (d.fdamp ? (double)d.fdamp[f] : o.damping);
+    double oSk_a, oSk_b, oSk_c, ogk0, ogk1, oSm_a, oSm_b, oSm_c, ogm0, ogm1;
+    if (o.damp_mode == 1) {
+        oSk_a = (1 - dd) * nSk_a + dd * Ska; oSk_b = (1 - dd) * nSk_b + dd * Skb; oSk_c = (1 - dd) * nSk_c + dd * Skc;
+        oSm_a = (1 - dd) * nSm_a + dd * Sma; oSm_b = (1 - dd) * nSm_b + dd * Smb; oSm_c = (1 - dd) * nSm_c + dd * Smc;
+        ogk0 = (1 - dd) * ngk0 + dd * gk0; ogk1 = (1 - dd) * ngk1 + dd * gk1;
+        ogm0 = (1 - dd) * ngm0 + dd * gm0; ogm1 = (1 - dd) * ngm1 + dd * gm1;
+    } else {
+        oSk_a = nSk_a; oSk_b = nSk_b; oSk_c = nSk_c;
+        oSm_a = nSm_a; oSm_b = nSm_b; oSm_c = nSm_c;
+        // absolute eta damped, Lambda not: anchor-relative correction
+        ogk0 = (1 - dd) * ngk0 + dd * gk0 + dd * ((Ska - nSk_a) * jak0 + (Skb - nSk_b) * jak1);
+        ogk1 = (1 - dd) * ngk1 + dd * gk1 + dd * ((Skb - nSk_b) * jak0 + (Skc - nSk_c) * jak1);
+        ogm0 = (1 - dd) * ngm0 + dd * gm0 + dd * ((Sma - nSm_a) * jam0 + (Smb - nSm_b) * jam1);
+        ogm1 = (1 - dd) * ngm1 + dd * gm1 + dd * ((Smb - nSm_b) * jam0 + (Smc - nSm_c) * jam1);
+    }
+
+    TS *kw = d.krec + (size_t)f * KREC;
+    TS *lw = d.lrec + (size_t)f * LREC;
+    kw[10] = (TS)oSk_a; kw[11] = (TS)oSk_b; kw[12] = (TS)oSk_c; kw[13] = (TS)ogk0; kw[14] = (TS)ogk1;
+    lw[6] = (TS)oSm_a; lw[7] = (TS)oSm_b; lw[8] = (TS)oSm_c; lw[9] = (TS)ogm0; lw[10] = (TS)ogm1;
+    if constexpr (RELIN) {
+        TS *aw = d.arec + (size_t)f * AREC;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)Jkn[r][i]; lw[3 * r + i] = (TS)Jmn[r][i]; }
+        kw[6] = (TS)Jkn[0][3]; kw[7] = (TS)Jkn[1][4]; kw[8] = (TS)Jkn[0][5]; kw[9] = (TS)Jkn[1][5];
+        kw[15] = (TS)s;
+        aw[0] = (TS)r0[0]; aw[1] = (TS)r0[1];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) aw[2 + i] = (TS)d0k[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) aw[8 + i] = (TS)d0m[i];
+        aw[11] = (TS)jak0; aw[12] = (TS)jak1; aw[13] = (TS)jam0; aw[14] = (TS)jam1;
+    }
+    d.cnt[f] = (uint8_t)(c + 1 > 255 ? 255 : c + 1);
+    if (nfl != fl) d.flags[f] = nfl;
+}
+
+// Hot factor kernel; WPE > 0 asks the compiler for at least WPE waves per
+// SIMD (trading registers for occupancy). The variant is chosen at run time.
+template <typename TS, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
+void k_factor(Dev<TS> d, IterOpts o) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
+    if (d.nf == 0) return;
+    // lanes past the end load a valid factor's data and discard it, so the
+    // wave reaches the queue ballot together
+    const bool valid = f < d.nf;
+    factor_body<TS, false>(d, o, valid ? f : d.nf - 1, valid);
+}
+
+// factors queued for relinearisation by k_factor in this iteration
+template <typename TS>
+__global__ __launch_bounds__(256) void k_factor_relin(Dev<TS> d, IterOpts o) {
+    const int n = d.relin_count[0];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        factor_body<TS, true>(d, o, d.relin_queue[i], true);
+}
+
+// --------------------------------------------------------------------------
+// linearise new factors at the current means (creation / growth)
+// --------------------------------------------------------------------------
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, double huber_k) {
+    const int f = f0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= f1) return;
+    const int k = d.f_kf[f], m = d.f_lm[f];
+    const ProbParams pp = d.prob[d.kf_prob[k]];
+    double x[6], l[3], dmk[6], dmm[3], zz[2] = {d.z[2 * (size_t)f], d.z[2 * (size_t)f + 1]};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { dmk[i] = d.kf_bel[(size_t)k * KBEL + i]; x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i]; }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { dmm[i] = d.lm_bel[(size_t)m * LBEL + i]; l[i] = d.lm_anchor[3 * (size_t)m + i] + dmm[i]; }
+    Lin L;
+    linearise(x, l, zz, pp, huber_k, L);
+    TS *kw = d.krec + (size_t)f * KREC, *lw = d.lrec + (size_t)f * LREC, *aw = d.arec + (size_t)f * AREC;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)L.J[r][i]; lw[3 * r + i] = (TS)L.J[r][6 + i]; }
+    kw[6] = (TS)L.J[0][3]; kw[7] = (TS)L.J[1][4]; kw[8] = (TS)L.J[0][5]; kw[9] = (TS)L.J[1][5];
+#pragma unroll
+    for (int i = 10; i < 15; ++i) kw[i] = (TS)0;
+    kw[15] = (TS)L.s;
+#pragma unroll
+    for (int i = 6; i < 12; ++i) lw[i] = (TS)0;
+    aw[0] = (TS)L.r0[0]; aw[1] = (TS)L.r0[1];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) aw[2 + i] = (TS)dmk[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) aw[8 + i] = (TS)dmm[i];
+    double jak0 = 0, jak1 = 0, jam0 = 0, jam1 = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double a = d.kf_anchor[6 * (size_t)k + i];
+        jak0 += L.J[0][i] * a;
+        jak1 += L.J[1][i] * a;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double a = d.lm_anchor[3 * (size_t)m + i];
+        jam0 += L.J[0][6 + i] * a;
+        jam1 += L.J[1][6 + i] * a;
+    }
+    aw[11] = (TS)jak0; aw[12] = (TS)jak1; aw[13] = (TS)jam0; aw[14] = (TS)jam1; aw[15] = (TS)0;
+    d.cnt[f] = 0;
+    d.flags[f] = L.valid ? 0 : FLAG_INVALID;
+}
+
+// --------------------------------------------------------------------------
+// automatic priors: diag(sum_f J_v^T Sigma^-1 J_v) at the initial
+// linearisation (Section 4), floored so that every belief is proper
+// --------------------------------------------------------------------------
+
+constexpr double PRIOR_FLOOR = 1e-8;
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_prior_kf(Dev<TS> d, int k0) {
+    const int k = k0 + ((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= d.nk) return;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int e = d.kf_row[k] + lane; e < d.kf_row[k + 1]; e += 64) {
+        const TS *r = d.krec + (size_t)d.kf_edge[e] * KREC;
+        double j00 = r[0], j01 = r[1], j02 = r[2], j10 = r[3], j11 = r[4], j12 = r[5];
+        double a0 = r[6], a1 = r[7], b0 = r[8], b1 = r[9];
+        acc[0] += j00 * j00 + j10 * j10;
+        acc[1] += j01 * j01 + j11 * j11;
+        acc[2] += j02 * j02 + j12 * j12;
+        acc[3] += a0 * a0;
+        acc[4] += a1 * a1;
+        acc[5] += b0 * b0 + b1 * b1;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (lane == 0) {
+        const double is2 = d.prob[d.kf_prob[k]].inv_s2;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            double v = acc[i] * is2;
+            d.kf_pbase[6 * (size_t)k + i] = v < PRIOR_FLOOR ? PRIOR_FLOOR : v;
+        }
+    }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
+    const int m = m0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= d.nl) return;
+    double acc[3] = {0, 0, 0};
+    for (int f = d.lm_row[m]; f < d.lm_row[m + 1]; ++f) {
+        const TS *r = d.lrec + (size_t)f * LREC;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] += (double)r[i] * (double)r[i] + (double)r[3 + i] * (double)r[3 + i];
+    }
+    const double is2 = d.prob[d.lm_prob[m]].inv_s2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double v = acc[i] * is2;
+        d.lm_pbase[3 * (size_t)m + i] = v < PRIOR_FLOOR ? PRIOR_FLOOR : v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// belief phase (eqs. (beliefeta), (belieflambda)): prior at the current
+// clock plus the sum of incoming messages, then covariance and mean offset
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ double prior_scale(const IterOpts &o, int age) {
+    int a = age < 0 ? 0 : (age > o.anneal_iters ? o.anneal_iters : age);
+    return o.scale[a];
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= d.nl) return;
+    const int t = d.t_dev[0];
+    const double sc = prior_scale(o, t - d.lm_t0[m]);
+    double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
+    A[pidx<3>(0, 0)] = d.lm_pbase[3 * (size_t)m] * sc;
+    A[pidx<3>(1, 1)] = d.lm_pbase[3 * (size_t)m + 1] * sc;
+    A[pidx<3>(2, 2)] = d.lm_pbase[3 * (size_t)m + 2] * sc;
+    for (int f = d.lm_row[m]; f < d.lm_row[m + 1]; ++f) {
+        TS r[LREC];
+        load12(d.lrec + (size_t)f * LREC, r);
+        double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
+        double Sa = r[6], Sb = r[7], Sc = r[8], g0 = r[9], g1 = r[10];
+        double SJ0[3], SJ1[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = i; j < 3; ++j) A[pidx<3>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
+            e[i] += J0[i] * g0 + J1[i] * g1;
+        }
+    }
+    if (readout) {
+        double *out = d.lm_info + 9 * (size_t)m;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) out[3 * i + j] = A[pidx<3>(i, j)];
+    }
+    double L[6], inv[6], x[3];
+    if (!chol<3>(A, L)) { atomicOr(d.status, 1u); return; }
+    chol_inverse_solve<3>(L, e, inv, x);
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fin = fin && isfinite(x[i]);
+    if (!fin) { atomicOr(d.status, 2u); return; }
+    double *b = d.lm_bel + (size_t)m * LBEL;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b[i] = x[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b[3 + i] = inv[i];
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_belief_kf(Dev<TS> d, IterOpts o, int readout) {
+    const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // queue consumed
+        d.relin_total[0] += (unsigned long long)d.relin_count[0];
+        d.relin_count[0] = 0;
+    }
+    if (k >= d.nk) return;
+    double A[21], e[6];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) A[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = 0.0;
+    for (int ei = d.kf_row[k] + lane; ei < d.kf_row[k + 1]; ei += 64) {
+        TS r[KREC];
+        load16(d.krec + (size_t)d.kf_edge[ei] * KREC, r);
+        double J0[6] = {r[0], r[1], r[2], r[6], 0.0, r[8]};
+        double J1[6] = {r[3], r[4], r[5], 0.0, r[7], r[9]};
+        double Sa = r[10], Sb = r[11], Sc = r[12], g0 = r[13], g1 = r[14];
+        double SJ0[6], SJ1[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+#pragma unroll
+            for (int j = i; j < 6; ++j) A[pidx<6>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
+            e[i] += J0[i] * g0 + J1[i] * g1;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 21; ++i) A[i] += __shfl_xor(A[i], off, 64);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) e[i] += __shfl_xor(e[i], off, 64);
+    }
+    if (lane != 0) return;
+    const double pinfo = d.kf_pinfo[k];
+    if (pinfo > 0.0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += pinfo;
+    } else {
+        const double sc = prior_scale(o, d.t_dev[0] - d.kf_t0[k]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += d.kf_pbase[6 * (size_t)k + i] * sc;
+    }
+    if (readout) {
+        double *out = d.kf_info + 36 * (size_t)k;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) out[6 * i + j] = A[pidx<6>(i, j)];
+    }
+    double L[21], inv[21], x[6];
+    if (!chol<6>(A, L)) { atomicOr(d.status, 1u); return; }
+    chol_inverse_solve<6>(L, e, inv, x);
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) fin = fin && isfinite(x[i]);
+    if (!fin) { atomicOr(d.status, 2u); return; }
+    double *b = d.kf_bel + (size_t)k * KBEL;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b[i] = x[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) b[6 + i] = inv[i];
+    // absolute pose of the new mean, consumed by the residual phase
+    double w[6], R[9];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) w[i] = d.kf_anchor[6 * (size_t)k + i] + x[i];
+    so3_exp_d(w, R);
+    double *ps = d.kf_pose + 12 * (size_t)k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ps[i] = R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ps[9 + i] = w[3 + i];
+}
+
+// --------------------------------------------------------------------------
+// relinearisation requests (explicit call): mark and count
+// --------------------------------------------------------------------------
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int *count) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.nf) return;
+    bool sel = beta < 0.0;
+    // a factor already marked takes the current means as its linearisation
+    // point, so its distance is zero: only beta < 0 selects it again
+    if (!sel && !(d.flags[f] & FLAG_PENDING)) {
+        const int k = d.f_kf[f], m = d.f_lm[f];
+        const TS *ar = d.arec + (size_t)f * AREC;
+        double dist2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { double e = d.kf_bel[(size_t)k * KBEL + i] - (double)ar[2 + i]; dist2 += e * e; }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { double e = d.lm_bel[(size_t)m * LBEL + i] - (double)ar[8 + i]; dist2 += e * e; }
+        sel = sqrt(dist2) > beta;
+    }
+    if (sel) {
+        d.flags[f] = d.flags[f] | FLAG_PENDING;
+        atomicAdd(count, 1);
+    }
+}
+
+// --------------------------------------------------------------------------
+// reprojection statistics (Section 9.1, Section 9.4 outlier classes)
+// --------------------------------------------------------------------------
+
+// Per-block partial statistics over the factor range of one block (blocks
+// never straddle problems): {sum_all, sum_quad, sum_ref, n_valid, n_quad,
+// n_lin, n_inv, n_ref}, tree-reduced in a fixed order.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
+                                                      const uint8_t *mask) {
+    const int b = blockIdx.x;
+    const int f0 = d.rblk_start[b], f1 = d.rblk_start[b + 1];
+    const ProbParams pp = d.prob[d.rblk_prob[b]];
+    const double N = huber_k / pp.sigma;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
+        const int k = d.f_kf[f], m = d.f_lm[f];
+        const double *ps = d.kf_pose + 12 * (size_t)k;
+        double l[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + d.lm_bel[(size_t)m * LBEL + i];
+        double p[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p[i] = ps[3 * i] * l[0] + ps[3 * i + 1] * l[1] + ps[3 * i + 2] * l[2] + ps[9 + i];
+        if (!(p[2] > pp.zmin)) { acc[6] += 1.0; continue; }
+        const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
+        const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
+        acc[0] += e;
+        acc[3] += 1.0;
+        if (N > 0.0 && e / pp.sigma > N) acc[5] += 1.0;
+        else { acc[1] += e; acc[4] += 1.0; }
+        if (zref && mask[f]) {
+            acc[2] += hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
+            acc[7] += 1.0;
+        }
+    }
+    __shared__ double sh[8][256];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sh[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) d.rblk_part[8 * (size_t)b + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// one thread per problem: sums its blocks' partials in block order
+__global__ __launch_bounds__(256) void k_reproj_reduce(const double *part, const int *prob_blk, int np,
+                                                       double *out, double *log_row, const int *t_dev) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = prob_blk[p]; b < prob_blk[p + 1]; ++b)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += part[8 * (size_t)b + i];
+    if (out)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[8 * (size_t)p + i] = acc[i];
+    if (log_row) {
+        log_row[4 * (size_t)p + 0] = (double)t_dev[0];
+        log_row[4 * (size_t)p + 1] = acc[3] > 0 ? acc[0] / acc[3] : 0.0;
+        log_row[4 * (size_t)p + 2] = acc[7] > 0 ? acc[2] / acc[7] : 0.0;
+        log_row[4 * (size_t)p + 3] = acc[5];
+    }
+}
+
+__global__ void k_tick(int *t_dev) { t_dev[0] = t_dev[0] + 1; }
+
+// --------------------------------------------------------------------------
+// factor-state permutation (incremental growth keeps factors landmark-sorted)
+// --------------------------------------------------------------------------
+
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_gather(const T *src, T *dst, const int *perm, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = perm[i];
+    if (j < 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[(size_t)i * W + w] = T(0);
+        return;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) dst[(size_t)i * W + w] = src[(size_t)j * W + w];
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+
+static inline int blocks(long n, int b) { return (int)((n + b - 1) / b); }
+
+template <typename TS>
+void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, hipStream_t s) {
+    if (f1 > f0) hipLaunchKernelGGL(k_linearise<TS>, dim3(blocks(f1 - f0, 256)), dim3(256), 0, s, d, f0, f1, huber_k);
+}
+
+template <typename TS>
+void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
+    if (d.nk > k0) hipLaunchKernelGGL(k_prior_kf<TS>, dim3(blocks((long)(d.nk - k0) * 64, 256)), dim3(256), 0, s, d, k0);
+    if (d.nl > m0) hipLaunchKernelGGL(k_prior_lm<TS>, dim3(blocks(d.nl - m0, 256)), dim3(256), 0, s, d, m0);
+}
+
+template <typename TS>
+void launch_factor(const Dev<TS> &d, const IterOpts &o, int block, int variant, hipStream_t s) {
+    const dim3 g(blocks(d.nf > 0 ? d.nf : 1, block)), b(block);
+    switch (variant) {
+        case 1: hipLaunchKernelGGL((k_factor<TS, 3>), g, b, 0, s, d, o); break;
+        case 2: hipLaunchKernelGGL((k_factor<TS, 4>), g, b, 0, s, d, o); break;
+        default: hipLaunchKernelGGL((k_factor<TS, 0>), g, b, 0, s, d, o); break;
+    }
+    const int rb = std::min(blocks(d.nf > 0 ? d.nf : 1, 256), 2048);
+    hipLaunchKernelGGL(k_factor_relin<TS>, dim3(rb), dim3(256), 0, s, d, o);
+}
+
+template <typename TS>
+void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
+    if (d.nl > 0) hipLaunchKernelGGL(k_belief_lm<TS>, dim3(blocks(d.nl, block)), dim3(block), 0, s, d, o, readout);
+}
+
+template <typename TS>
+void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
+    if (d.nk > 0) hipLaunchKernelGGL(k_belief_kf<TS>, dim3(blocks((long)d.nk * 64, block)), dim3(block), 0, s, d, o, readout);
+}
+
+template <typename TS>
+void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s) {
+    if (d.nf > 0) hipLaunchKernelGGL(k_flag_relin<TS>, dim3(blocks(d.nf, 256)), dim3(256), 0, s, d, beta, count);
+}
+
+template <typename TS>
+void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref, const uint8_t *mask, double *log_row,
+                   hipStream_t s) {
+    if (d.n_rblk > 0)
+        hipLaunchKernelGGL(k_reproj_block<TS>, dim3(d.n_rblk), dim3(256), 0, s, d, huber_k, zref, mask);
+    hipLaunchKernelGGL(k_reproj_reduce, dim3(blocks(d.np, 256)), dim3(256), 0, s, (const double *)d.rblk_part,
+                       d.prob_rblk, d.np, log_row ? (double *)nullptr : d.are_out, log_row, (const int *)d.t_dev);
+}
+
+template <typename TS>
+void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scratch, hipStream_t s) {
+    // gather every per-factor array through `perm` (new index -> old index,
+    // -1 for a fresh slot) via the scratch buffer, then copy back
+    const int b = blocks(nf > 0 ? nf : 1, 256);
+    auto run = [&](auto *arr, auto tag, int w) {
+        using T = decltype(tag);
+        T *tmp = (T *)scratch;
+        switch (w) {
+            case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
+            case 2: hipLaunchKernelGGL((k_gather<T, 2>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
+            case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
+            case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
+        }
+        (void)hipMemcpyAsync(arr, tmp, sizeof(T) * (size_t)w * nf, hipMemcpyDeviceToDevice, s);
+    };
+    run(d.krec, TS(0), KREC);
+    run(d.lrec, TS(0), LREC);
+    run(d.arec, TS(0), AREC);
+    run(const_cast<double *>(d.z), double(0), 2);
+    run(d.cnt, uint8_t(0), 1);
+    run(d.flags, uint8_t(0), 1);
+}
+
+void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, t_dev); }
+
+#define GBP_INSTANTIATE(TS)                                                                                        \
+    template void launch_linearise<TS>(const Dev<TS> &, int, int, double, hipStream_t);                            \
+    template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
+    template void launch_factor<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                     \
+    template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
+    template void launch_belief_kf<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
+    template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
+    template void launch_reproj<TS>(const Dev<TS> &, double, const double *, const uint8_t *, double *,            \
+                                    hipStream_t);                                                                 \
+    template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, hipStream_t);
+
+GBP_INSTANTIATE(float)
+GBP_INSTANTIATE(double)
+
+}  // namespace gbp

@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point declared in include/gbp.h, and rejects bad input before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2003_03134_amd import _capi
+    return _capi
+
+
+def test_header_declarations_are_exported(capi):
+    text = open(os.path.join(ROOT, "include", "gbp.h")).read()
+    declared = set(re.findall(r"\b(gbp_[a-z_]+)\s*\(", text))
+    lib = capi.load()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(capi.EXPORTS)
+
+
+def test_default_options_are_the_papers(capi):
+    lib = capi.load()
+    o = capi.gbp_options()
+    lib.gbp_default_options(C.byref(o))
+    assert o.beta == 0.01 and o.relin_min_interval == 10 and o.undamped_after_relin == 8
+    assert o.prior_anneal_iters == 10 and o.prior_weaken == 0.01
+    assert o.precision == capi.GBP_FP32 and o.damp_mode == capi.GBP_DAMP_ETA
+
+
+def _graph(capi, fkf, flm, nk=2, nl=2):
+    fkf = np.ascontiguousarray(fkf, dtype=np.int32)
+    flm = np.ascontiguousarray(flm, dtype=np.int32)
+    kf = np.zeros((nk, 6))
+    lm = np.ones((nl, 3))
+    z = np.full((len(fkf), 2), 100.0)
+    keep = [fkf, flm, kf, lm, z]
+    g = capi.gbp_graph(nk, nl, len(fkf), fkf.ctypes.data_as(C.POINTER(C.c_int32)),
+                       flm.ctypes.data_as(C.POINTER(C.c_int32)),
+                       kf.ctypes.data_as(C.POINTER(C.c_double)),
+                       lm.ctypes.data_as(C.POINTER(C.c_double)), None)
+    m = capi.gbp_measurements(z.ctypes.data_as(C.POINTER(C.c_double)))
+    return g, m, keep
+
+
+@pytest.mark.parametrize("fkf,flm", [([0, 2], [0, 1]), ([0, 1], [0, 5]), ([-1, 0], [0, 0])])
+def test_out_of_range_indices_are_rejected(capi, fkf, flm):
+    lib = capi.load()
+    g, m, keep = _graph(capi, fkf, flm)
+    cam = capi.gbp_camera(500, 500, 320, 240, 1.0)
+    h = C.c_void_p()
+    st = lib.gbp_create(C.byref(g), C.byref(cam), C.byref(m), None, C.byref(h))
+    assert st == capi.GBP_EINVAL
+    assert b"out-of-range" in lib.gbp_last_error(h)
+    # a failed problem refuses further work
+    assert lib.gbp_iterate(h, 1, 0.4, 2.0) == capi.GBP_ESTATE
+    lib.gbp_destroy(h)
+
+
+def test_bad_options_are_rejected(capi):
+    lib = capi.load()
+    g, m, keep = _graph(capi, [0, 1], [0, 1])
+    cam = capi.gbp_camera(500, 500, 320, 240, 1.0)
+    o = capi.gbp_options()
+    lib.gbp_default_options(C.byref(o))
+    o.undamped_after_relin = 0
+    h = C.c_void_p()
+    assert lib.gbp_create(C.byref(g), C.byref(cam), C.byref(m), C.byref(o), C.byref(h)) == capi.GBP_EINVAL
+    lib.gbp_destroy(h)
+    o.undamped_after_relin = 8
+    o.prior_anneal_iters = 65
+    assert lib.gbp_create(C.byref(g), C.byref(cam), C.byref(m), C.byref(o), C.byref(h)) == capi.GBP_EINVAL
+    lib.gbp_destroy(h)
+
+
+def test_workspace_size_scales_with_factors(capi):
+    lib = capi.load()
+    g1, _, k1 = _graph(capi, [0, 1], [0, 1])
+    n = C.c_size_t()
+    assert lib.gbp_workspace_bytes(1, C.byref(g1), None, C.byref(n)) == 0
+    small = n.value
+    g2, _, k2 = _graph(capi, np.zeros(10000), np.zeros(10000))
+    assert lib.gbp_workspace_bytes(1, C.byref(g2), None, C.byref(n)) == 0
+    assert n.value > small + 10000 * 150

@@ -1,0 +1,256 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 storage agrees with the oracle to rounding (means 1e-8
+relative, ARE 1e-8 px); FP32 storage within 1e-4 relative on every mean
+(|dmu|_inf <= 1e-4 max(|mu|_inf, 1) per variable) and 1e-3 px on the
+reprojection error. Checked under forced relinearisation schedules (same
+linearisation points on both sides) at every checkpoint, and at convergence
+under the beta rule.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gbp():
+    import paper_2003_03134_amd as g
+    g.load_library()
+    return g
+
+
+def rel_mean_err(a, b):
+    """max over variables of |a - b|_inf / max(|b|_inf, 1)"""
+    d = np.abs(a - b).max(axis=1)
+    s = np.maximum(np.abs(b).max(axis=1), 1.0)
+    return float((d / s).max()) if len(d) else 0.0
+
+
+def mean_errs(g, o):
+    return max(rel_mean_err(g["kf_mu"], o["kf_mu"]), rel_mean_err(g["lm_mu"], o["lm_mu"]))
+
+
+def info_err(g, o):
+    e = 0.0
+    for key in ("kf_lam", "lm_lam"):
+        n = np.abs(o[key]).max(axis=(1, 2))
+        e = max(e, float((np.abs(g[key] - o[key]).max(axis=(1, 2)) / n).max()))
+    return e
+
+
+def pair(gbp, prob, precision, **kw):
+    import oracle
+    anneal = kw.pop("anneal", precision == gbp.GBP_FP32)
+    damp_lambda = kw.pop("damp_lambda", False)
+    s = gbp.GBPSolver(prob, precision=precision, anneal=anneal,
+                      damp_mode=gbp.GBP_DAMP_ETA_LAMBDA if damp_lambda else gbp.GBP_DAMP_ETA, **kw)
+    o = oracle.Oracle(prob, anneal=anneal, damp_lambda=damp_lambda, **kw)
+    return s, o
+
+
+# --------------------------------------------------------------------------
+# FP64 storage: agreement to rounding
+# --------------------------------------------------------------------------
+
+def test_fp64_config0_forced_schedule_every_checkpoint(gbp):
+    """Config 0: 200 iterations, damping 0.4, Huber 2 px, relinearising
+    every 10 iterations; beliefs and ARE compared at every checkpoint."""
+    prob = synth.make_config0(seed=0)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    for it in range(20):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        g, r = s.beliefs(info=True), o.beliefs()
+        assert mean_errs(g, r) < 1e-8, it
+        assert info_err(g, r) < 1e-8, it
+        assert abs(s.reproj()["are_all"] - o.reproj()["are_all"]) < 1e-8
+        assert s.relinearise(-1) == o.relinearise(-1) == prob.n_factors
+    s.close()
+
+
+def test_fp64_beta_rule(gbp):
+    prob = synth.make_config0(seed=3)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    for it in range(6):
+        s.iterate(25, 0.4, 2.0)
+        o.iterate(25, 0.4, 2.0)
+        assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8, it
+    s.close()
+
+
+@pytest.mark.parametrize("damp_lambda", [False, True])
+def test_fp64_random_walk_both_damping_modes(gbp, damp_lambda):
+    prob = synth.make_random_walk("rw", 11, 20, 300, "poisson", 0.05)
+    s, o = pair(gbp, prob, gbp.GBP_FP64, damp_lambda=damp_lambda)
+    for it in range(4):
+        s.iterate(15, 0.4, 2.0)
+        o.iterate(15, 0.4, 2.0)
+        assert mean_errs(s.beliefs(), o.beliefs()) < 1e-7, it
+    rg, ro = s.reproj(), o.reproj()
+    assert abs(rg["are_all"] - ro["are_all"]) < 1e-7
+    assert rg["n_linear"] == ro["n_linear"]
+    s.close()
+
+
+def test_fp64_tree_exact(gbp):
+    prob = synth.make_tree_chain(4, 2)
+    s, o = pair(gbp, prob, gbp.GBP_FP64, beta=1e30, relin_interval=250)
+    s.iterate(30, 0.0, 2.0)
+    o.iterate(30, 0.0, 2.0)
+    g, r = s.beliefs(info=True), o.beliefs()
+    assert mean_errs(g, r) < 1e-9
+    assert info_err(g, r) < 1e-9
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# FP32 storage against the FP64 oracle
+# --------------------------------------------------------------------------
+
+def test_fp32_config1_forced_schedule(gbp):
+    """Paper-scale problem (125 kf, 1919 lm), FP32 factor state with annealed
+    priors; same linearisation schedule on both sides."""
+    prob = synth.make_config1()
+    s, o = pair(gbp, prob, gbp.GBP_FP32)
+    worst = 0.0
+    for it in range(8):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        e = mean_errs(s.beliefs(), o.beliefs())
+        worst = max(worst, e)
+        assert e < 1e-4, (it, e)
+        assert abs(s.reproj()["are_all"] - o.reproj()["are_all"]) < 1e-3
+        s.relinearise(-1)
+        o.relinearise(-1)
+    print(f"config1 FP32 forced schedule: worst relative mean error {worst:.2e}")
+    s.close()
+
+
+def test_fp32_config1_converged_beta_rule(gbp):
+    """beta rule, eta and Lambda damped (the run converges); compared at
+    convergence."""
+    prob = synth.make_config1()
+    s, o = pair(gbp, prob, gbp.GBP_FP32, damp_lambda=True)
+    s.iterate(300, 0.4, 2.0)
+    o.iterate(300, 0.4, 2.0)
+    e = mean_errs(s.beliefs(), o.beliefs())
+    rg, ro = s.reproj(), o.reproj()
+    print(f"config1 FP32 converged: rel mean err {e:.2e}, ARE gpu {rg['are_all']:.6f} oracle {ro['are_all']:.6f}")
+    assert e < 1e-4
+    assert abs(rg["are_all"] - ro["are_all"]) < 1e-3
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# structure: determinism, batching, ordering, edge cases
+# --------------------------------------------------------------------------
+
+def test_bitwise_deterministic(gbp):
+    prob = synth.make_config1()
+    out = []
+    for _ in range(2):
+        s = gbp.GBPSolver(prob)
+        s.iterate(40, 0.4, 2.0)
+        out.append(s.beliefs(info=True))
+        s.close()
+    for key in out[0]:
+        assert np.array_equal(out[0][key], out[1][key]), key
+
+
+def test_batch_equals_single_and_oracle(gbp):
+    import oracle
+    probs = [synth.make_config3_problem(p) for p in range(6)]
+    b = gbp.GBPSolver(probs)
+    b.iterate(30, 0.4, 2.0)
+    gb = b.beliefs()
+    ko, lo = np.cumsum([0] + [p.n_keyframes for p in probs]), np.cumsum([0] + [p.n_landmarks for p in probs])
+    for i, p in enumerate(probs):
+        s = gbp.GBPSolver(p)
+        s.iterate(30, 0.4, 2.0)
+        gs = s.beliefs()
+        assert np.array_equal(gb["kf_mu"][ko[i]:ko[i + 1]], gs["kf_mu"])
+        assert np.array_equal(gb["lm_mu"][lo[i]:lo[i + 1]], gs["lm_mu"])
+        assert b.reproj(i)["are_all"] == s.reproj()["are_all"]
+        s.close()
+        o = oracle.Oracle(p, anneal=True)
+        o.iterate(30, 0.4, 2.0)
+        assert mean_errs(gs, o.beliefs()) < 1e-4
+    b.close()
+
+
+def test_caller_factor_order_does_not_matter(gbp):
+    prob = synth.make_config0(seed=4)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(prob.n_factors)
+    shuffled = synth.BAProblem("shuf", prob.cam, prob.kf_true, prob.lm_true, prob.kf_init,
+                               prob.lm_init, prob.factor_kf[perm], prob.factor_lm[perm],
+                               prob.z[perm], prob.z_true[perm], prob.inlier[perm],
+                               prob.kf_anchor_info)
+    a = gbp.GBPSolver(prob, precision=gbp.GBP_FP64)
+    b = gbp.GBPSolver(shuffled, precision=gbp.GBP_FP64)
+    a.iterate(50, 0.4, 2.0)
+    b.iterate(50, 0.4, 2.0)
+    ga, gb_ = a.beliefs(), b.beliefs()
+    assert np.array_equal(ga["kf_mu"], gb_["kf_mu"]) and np.array_equal(ga["lm_mu"], gb_["lm_mu"])
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("n_lm", [1, 7, 300])
+def test_ragged_sizes_and_single_observations(gbp, n_lm):
+    prob = synth.make_random_walk("rag", 5 + n_lm, 6, n_lm, "poisson", 0.0, min_obs=1)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    s.iterate(20, 0.4, 2.0)
+    o.iterate(20, 0.4, 2.0)
+    assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
+    s.close()
+
+
+def test_point_behind_camera_and_huber_off(gbp):
+    from scipy.spatial.transform import Rotation
+    prob = synth.make_config0(seed=7)
+    k = int(prob.factor_kf[np.flatnonzero(prob.factor_lm == 0)[0]])
+    R = Rotation.from_rotvec(prob.kf_init[k, :3]).as_matrix()
+    prob.lm_init[0] = R.T @ (np.array([0.1, 0.1, -1.0]) - prob.kf_init[k, 3:])
+    s, o = pair(gbp, prob, gbp.GBP_FP64, huber_k=0.0)
+    assert s.reproj()["n_invalid"] == o.reproj()["n_invalid"] >= 1
+    s.iterate(30, 0.4, 0.0)
+    o.iterate(30, 0.4, 0.0)
+    assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
+    s.close()
+
+
+def test_relinearise_threshold_counts(gbp):
+    prob = synth.make_config0(seed=1)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    s.iterate(12, 0.4, 2.0)
+    o.iterate(12, 0.4, 2.0)
+    for beta in (0.05, 0.01, 0.002):
+        assert s.relinearise(beta) == o.relinearise(beta)
+    s.iterate(5, 0.4, 2.0)
+    o.iterate(5, 0.4, 2.0)
+    assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
+    s.close()
+
+
+def test_reproj_stats_and_log(gbp):
+    prob = synth.make_random_walk("rp", 21, 15, 200, "poisson", 0.05)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    s.set_reference(prob.z_true, prob.inlier)
+    log = s.iterate_logged(20, 0.4, 2.0, log_every=5)
+    assert log.shape == (4, 1, 4)
+    for row in log[:, 0]:
+        o.iterate(5, 0.4, 2.0)
+        r = o.reproj(prob.z_true, prob.inlier)
+        assert int(row[0]) == o.t
+        assert abs(row[1] - r["are_all"]) < 1e-8 and abs(row[2] - r["are_ref"]) < 1e-8
+        assert int(row[3]) == r["n_linear"]
+    rg, ro = s.reproj(), o.reproj(prob.z_true, prob.inlier)
+    for key in ("n_valid", "n_quadratic", "n_linear", "n_invalid", "n_ref"):
+        assert rg[key] == ro[key], key
+    for key in ("are_all", "are_quadratic", "are_ref"):
+        assert abs(rg[key] - ro[key]) < 1e-8, key
+    s.close()
