@@ -25,16 +25,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# Algorithmic bytes of one factor-phase update of one factor with FP32
-# factor state (the layout in paper_2003_03134_amd/csrc/gbp_internal.h):
-#   read  keyframe-side record 16 x 4 B, landmark-side J + message 11 x 4 B,
-#         factor-private record 15 x 4 B (r0, lin. offset, J*anchor),
-#         keyframe and landmark index 2 x 4 B, counter + flags 2 x 1 B;
-#   write messages to keyframe and landmark 2 x 5 x 4 B, counter 1 B.
-FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 15 * 4 + 2 * 4 + 2 + 2 * 5 * 4 + 1  # 219
-# plus, once per launch, every belief the factors gather (FP64 mean offset +
-# packed covariance): 27 doubles per keyframe, 9 per landmark.
-KF_BELIEF_BYTES = 27 * 8
+# Algorithmic bytes of the dominant kernel, k_factor_kf (one workgroup per
+# keyframe: every factor's two messages, then the keyframe's message sums),
+# with FP32 factor state (layout in paper_2003_03134_amd/csrc/gbp_internal.h):
+#   per factor: read the keyframe-side record 16 x 4 B, the landmark-side
+#     Jacobian + message 11 x 4 B, the factor-private record 15 x 4 B (r0,
+#     linearisation offset, J*anchor), the landmark index 4 B, counter and
+#     flags 2 x 1 B; write both new messages 2 x 5 x 4 B and the counter 1 B;
+#   per keyframe: read its belief (27 doubles), write its 27 message sums;
+#   per landmark: read its belief once (9 doubles; gathered by its factors).
+FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 15 * 4 + 4 + 2 + 2 * 5 * 4 + 1  # 215
+KF_BELIEF_BYTES = 27 * 8 + 27 * 8
 LM_BELIEF_BYTES = 9 * 8
 
 
@@ -204,18 +205,17 @@ def main():
     log(f"{ms_per_step:.4f} ms/step wall ({ev_ms / K:.4f} ms/step by events), "
         f"{value / 1e9:.3f} G factor-updates/s")
 
-    relin0 = solver.relinearisations
     ph = solver.phase_times(args.phase_iters, 0.4, 2.0)
-    relin_frac = (solver.relinearisations - relin0) / (nf * args.phase_iters)
+    relin_frac = solver.last_relinearised / nf
     log(f"relinearised per iteration: {100 * relin_frac:.2f}% of factors")
     log("phase ms/launch: " + ", ".join(f"{k} {v:.4f}" for k, v in ph.items()))
     fbytes = factor_launch_bytes(nf, nk, nl)
-    achieved = fbytes / (ph["factor"] * 1e-3) / 1e9
+    achieved = fbytes / (ph["factor_kf"] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_factor", algorithmic_bytes_per_launch=int(fbytes),
-                    kernel_ms=round(ph["factor"], 5),
+                    kernel="k_factor_kf", algorithmic_bytes_per_launch=int(fbytes),
+                    kernel_ms=round(ph["factor_kf"], 5),
                     phases_ms={k: round(v, 5) for k, v in ph.items()},
                     relinearised_fraction=round(relin_frac, 5))
     are = last[-1] if last is not None else None

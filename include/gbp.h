@@ -201,16 +201,16 @@ gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
 /* Per-phase timing (the compute phases of one iteration, Section 7 and
  * Fig. 3): runs n iterations with each phase launched separately and
  * bracketed by HIP events on the problem's stream, then writes the average
- * milliseconds per launch of {factor phase (relinearisation check,
- * relinearisation, messages), landmark beliefs, keyframe beliefs,
- * reprojection statistics} to ms_out[4]. The iterations are real: the
- * state advances by n. Synchronises. */
+ * milliseconds per launch of {relinearisation check, relinearisation of the
+ * due factors, factor messages + keyframe beliefs, landmark beliefs,
+ * reprojection statistics} to ms_out[5]. The iterations are real: the state
+ * advances by n. Synchronises. */
 gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping,
                            double huber_k, double *ms_out);
 
-/* Number of factor relinearisations performed since creation (the subset
- * of factors that relinearise each iteration, Section 7, Fig. 3), counting
- * the initial linearisation as none. Synchronises. */
+/* Number of factors relinearised in the most recent iteration (the subset
+ * of factors that relinearise each iteration, Section 7, Fig. 3).
+ * Synchronises. */
 gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations);
 
 /* Sizes: keyframes, landmarks, factors, problems, completed iterations. */

@@ -152,7 +152,8 @@ class GBPSolver:
         return tuple(x.value for x in v)
 
     @property
-    def relinearisations(self) -> int:
+    def last_relinearised(self) -> int:
+        """Factors relinearised in the most recent iteration."""
         v = C.c_int64(0)
         self._check(self._lib.gbp_counters(self.h, C.byref(v)), self.h)
         return v.value
@@ -187,10 +188,10 @@ class GBPSolver:
         """Average ms per launch of each phase over n real iterations."""
         if huber_k is not None:
             self.huber_k = huber_k
-        ms = np.zeros(4)
+        ms = np.zeros(5)
         self._check(self._lib.gbp_phase_times(self.h, int(n), float(damping), float(self.huber_k),
                                               _ptr(ms, C.c_double)), self.h)
-        return dict(factor=ms[0], belief_lm=ms[1], belief_kf=ms[2], reproj=ms[3])
+        return dict(check=ms[0], relin=ms[1], factor_kf=ms[2], belief_lm=ms[3], reproj=ms[4])
 
     def synchronize(self):
         self.stream.synchronize()

@@ -2,9 +2,9 @@
 //
 // Graph build (the paper's "predetermined" exchange schedule, Section 7,
 // becomes a fixed memory layout): within each problem, landmarks are ordered
-// by their first observing keyframe, factors by landmark (so a landmark's
-// incoming messages are contiguous) and each keyframe gets a CSR list of its
-// factors in increasing factor order. A batch is the block-diagonal
+// by their first observing keyframe, factors by keyframe and then landmark
+// (so a keyframe's factors are contiguous and one workgroup owns them), and
+// each landmark gets a CSR list of its factors in increasing factor order. A batch is the block-diagonal
 // concatenation of its problems. Every buffer is carved from one device
 // workspace (caller-provided, e.g. a torch allocation, or allocated here).
 // Iterations are recorded once per (n, damping, Huber threshold) into a HIP
@@ -48,7 +48,7 @@ struct gbp_problem {
     std::vector<int> lm_int2user, f_int2user;
     std::vector<int> kf_off, lm_off, f_off;  // internal offsets per problem
     // host mirrors needed to rebuild the layout on growth
-    std::vector<int> h_fkf, h_flm, h_kf_row, h_kf_edge, h_lm_row;
+    std::vector<int> h_fkf, h_flm, h_kf_row, h_lm_row, h_lm_edge;
     std::vector<double> h_z, h_kf_anchor, h_lm_anchor;
     std::vector<int> h_first_obs;  // first observing keyframe of each internal landmark
     // device
@@ -60,6 +60,7 @@ struct gbp_problem {
     Dev<float> df{};
     Dev<double> dd{};
     int *d_count = nullptr;
+    unsigned long long *d_total = nullptr;
     double *d_zref = nullptr;
     uint8_t *d_mask = nullptr;
     bool has_ref = false;
@@ -72,7 +73,7 @@ struct gbp_problem {
     int t = 0;
     std::vector<GraphEntry> graphs;
     bool use_graph = true;
-    int blk_factor = 256, blk_lm = 256, blk_kf = 256, factor_variant = 0;
+    int blk_lm = 256, blk_kf = 128;
     std::string err;
     bool broken = false;
 };
@@ -120,7 +121,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.f_kf, F * 4);
     L.add((void **)&d.f_lm, F * 4);
     L.add((void **)&d.kf_row, (K + 1) * 4);
-    L.add((void **)&d.kf_edge, F * 4);
+    L.add((void **)&d.lm_edge, F * 4);
     L.add((void **)&d.lm_row, (M + 1) * 4);
     L.add((void **)&d.f_row_prob, (P + 1) * 4);
     L.add((void **)&d.z, F * 2 * 8);
@@ -134,9 +135,11 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.t_dev, 4);
     L.add((void **)&d.status, 4);
     L.add((void **)&d.pending_k, 8);
-    L.add((void **)&d.relin_queue, F * 4);
-    L.add((void **)&d.relin_count, 4);
-    L.add((void **)&d.relin_total, 8);
+    const size_t QB = (F + 255) / 256 + 1;
+    L.add((void **)&d.relin_queue, QB * 256 * 4);
+    L.add((void **)&d.relin_qcount, QB * 4);
+    L.add((void **)&d.kf_sums, K * 32 * 8);
+    L.add((void **)&p->d_total, 8);
     L.add((void **)&d.kf_pose, K * 12 * 8);
     const size_t RB = F / RBLK + P + 1;
     L.add((void **)&d.rblk_start, (RB + 1) * 4);
@@ -258,9 +261,8 @@ void build_order(gbp_problem *p, int n, const gbp_graph *gs, const gbp_measureme
         std::vector<int> forder(g.n_factors);
         std::iota(forder.begin(), forder.end(), 0);
         std::stable_sort(forder.begin(), forder.end(), [&](int a, int b) {
-            int la = lrank[g.factor_lm[a]], lb = lrank[g.factor_lm[b]];
-            if (la != lb) return la < lb;
-            return g.factor_kf[a] < g.factor_kf[b];
+            if (g.factor_kf[a] != g.factor_kf[b]) return g.factor_kf[a] < g.factor_kf[b];
+            return lrank[g.factor_lm[a]] < lrank[g.factor_lm[b]];
         });
         for (int r = 0; r < g.n_factors; ++r) {
             int f = forder[r];
@@ -283,11 +285,11 @@ void build_csr(gbp_problem *p) {
     }
     for (int k = 0; k < nk; ++k) p->h_kf_row[k + 1] += p->h_kf_row[k];
     for (int m = 0; m < nl; ++m) p->h_lm_row[m + 1] += p->h_lm_row[m];
-    p->h_kf_edge.assign(nf, 0);
-    std::vector<int> fill(nk, 0);
+    p->h_lm_edge.assign(nf, 0);
+    std::vector<int> fill(nl, 0);
     for (int f = 0; f < nf; ++f) {
-        int k = p->h_fkf[f];
-        p->h_kf_edge[p->h_kf_row[k] + fill[k]++] = f;
+        int m = p->h_flm[f];
+        p->h_lm_edge[p->h_lm_row[m] + fill[m]++] = f;
     }
 }
 
@@ -337,7 +339,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     UP(d.f_kf, p->h_fkf.data(), (size_t)nf * 4);
     UP(d.f_lm, p->h_flm.data(), (size_t)nf * 4);
     UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk + 1) * 4);
-    UP(d.kf_edge, p->h_kf_edge.data(), (size_t)nf * 4);
+    UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf * 4);
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl + 1) * 4);
     std::vector<int> frp(p->f_off.begin(), p->f_off.end());
     UP(d.f_row_prob, frp.data(), frp.size() * 4);
@@ -363,8 +365,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
-    HIP_TRY(p, hipMemsetAsync(d.relin_count, 0, 4, s));
-    HIP_TRY(p, hipMemsetAsync(d.relin_total, 0, 8, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)(p->cap_f + 255) / 256 + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
 #undef UP
     d.fdamp = nullptr;
@@ -405,8 +406,7 @@ gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const
     p->np = n;
     p->huber_k = opt.huber_k;
     if (const char *e = std::getenv("GBP_NO_GRAPH")) p->use_graph = !(e[0] == '1');
-    if (const char *e = std::getenv("GBP_FACTOR_VARIANT")) p->factor_variant = std::atoi(e);
-    if (const char *e = std::getenv("GBP_FACTOR_BLOCK")) p->blk_factor = std::atoi(e);
+    if (const char *e = std::getenv("GBP_KF_BLOCK")) p->blk_kf = std::atoi(e);
     fill_iopt(p);
     build_order(p, n, gs, ms, p->h_fkf, p->h_flm, p->h_z);
     build_csr(p);
@@ -446,9 +446,10 @@ gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_b
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
     for (int i = 0; i < n; ++i) {
-        launch_factor<TS>(d, p->iopt, p->blk_factor, p->factor_variant, s);
+        launch_check<TS>(d, p->iopt, s);
+        launch_relin<TS>(d, p->iopt, s);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
-        launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
         if (log_every > 0 && (i + 1) % log_every == 0)
             launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
                               log_base + (size_t)((i + 1) / log_every - 1) * p->np * 4, s);
@@ -501,31 +502,34 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
     p->huber_k = huber_k;
     // all events are recorded back to back on the stream and read after one
     // synchronisation, so queue-empty launch latency is not counted
-    std::vector<hipEvent_t> ev(4 * (size_t)n + 1);
+    constexpr int NPH = 5;
+    std::vector<hipEvent_t> ev(NPH * (size_t)n + 1);
     for (auto &e : ev) HIP_TRY(p, hipEventCreate(&e));
     HIP_TRY(p, hipEventRecord(ev[0], s));
     for (int i = 0; i < n; ++i) {
-        launch_factor<TS>(d, p->iopt, p->blk_factor, p->factor_variant, s);
-        HIP_TRY(p, hipEventRecord(ev[4 * i + 1], s));
+        launch_check<TS>(d, p->iopt, s);
+        HIP_TRY(p, hipEventRecord(ev[NPH * i + 1], s));
+        launch_relin<TS>(d, p->iopt, s);
+        HIP_TRY(p, hipEventRecord(ev[NPH * i + 2], s));
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
+        HIP_TRY(p, hipEventRecord(ev[NPH * i + 3], s));
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
-        HIP_TRY(p, hipEventRecord(ev[4 * i + 2], s));
-        launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
-        HIP_TRY(p, hipEventRecord(ev[4 * i + 3], s));
+        HIP_TRY(p, hipEventRecord(ev[NPH * i + 4], s));
         launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
                           nullptr, s);
-        HIP_TRY(p, hipEventRecord(ev[4 * i + 4], s));
+        HIP_TRY(p, hipEventRecord(ev[NPH * i + 5], s));
     }
     HIP_TRY(p, hipGetLastError());
     HIP_TRY(p, hipEventSynchronize(ev.back()));
-    double acc[4] = {0, 0, 0, 0};
+    double acc[NPH] = {0, 0, 0, 0, 0};
     for (int i = 0; i < n; ++i)
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NPH; ++q) {
             float t = 0.f;
-            HIP_TRY(p, hipEventElapsedTime(&t, ev[4 * i + q], ev[4 * i + q + 1]));
+            HIP_TRY(p, hipEventElapsedTime(&t, ev[NPH * i + q], ev[NPH * i + q + 1]));
             acc[q] += t;
         }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    for (int q = 0; q < 4; ++q) ms[q] = acc[q] / n;
+    for (int q = 0; q < NPH; ++q) ms[q] = acc[q] / n;
     p->t += n;
     return GBP_OK;
 }
@@ -776,9 +780,11 @@ gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping, double hub
 gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
+    const int *qc = p->precision == GBP_FP32 ? p->df.relin_qcount : p->dd.relin_qcount;
+    launch_relin_total(qc, (p->nf + 255) / 256, p->d_total, p->stream);
+    HIP_TRY(p, hipGetLastError());
     unsigned long long v = 0;
-    const unsigned long long *src = p->precision == GBP_FP32 ? p->df.relin_total : p->dd.relin_total;
-    HIP_TRY(p, hipMemcpyAsync(&v, src, 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(&v, p->d_total, 8, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     if (relinearisations) *relinearisations = (int64_t)v;
     return GBP_OK;

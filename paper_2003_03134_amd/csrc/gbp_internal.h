@@ -11,7 +11,7 @@ constexpr int KREC = 16;  // keyframe-side record per factor (see layout below)
 constexpr int LREC = 12;  // landmark-side record per factor
 constexpr int AREC = 16;  // factor-private record
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
-constexpr int LBEL = 12;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad
+constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
 constexpr int RBLK = 1024;  // factors per residual-phase block
 
@@ -47,8 +47,8 @@ struct Dev {
     double *kf_info, *lm_info;            // full information for read-out
     // graph
     const int *f_kf, *f_lm;
-    const int *kf_row, *kf_edge;          // factors of each keyframe (CSR)
-    const int *lm_row;                    // factors of landmark m: [lm_row[m], lm_row[m+1])
+    const int *kf_row;                    // factors of keyframe k: [kf_row[k], kf_row[k+1])
+    const int *lm_row, *lm_edge;          // factors of each landmark (CSR, increasing)
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state
     const double *z;
@@ -60,9 +60,9 @@ struct Dev {
     int *t_dev;                           // iteration clock
     unsigned *status;                     // bit 0: non-PD belief, bit 1: non-finite
     double *pending_k;                    // Huber threshold for requested relinearisations
-    int *relin_queue;                     // factors due for relinearisation this iteration
-    int *relin_count;
-    unsigned long long *relin_total;      // relinearisations since creation
+    int *relin_queue;                     // factors due for relinearisation, 256 per check block
+    int *relin_qcount;                    // queue entries of each check block
+    double *kf_sums;                      // per keyframe: 21 information + 6 vector sums (32)
     double *kf_pose;                      // absolute R (9) and t (3) of each keyframe mean
     // residual phase: blocks of at most RBLK factors inside one problem
     int n_rblk;
@@ -80,12 +80,15 @@ struct IterOpts {
     double scale[MAX_ANNEAL + 1];  // prior scale by age 0..anneal_iters (last = steady)
 };
 
-enum : uint8_t { FLAG_PENDING = 1, FLAG_INVALID = 2 };
+enum : uint8_t { FLAG_PENDING = 1, FLAG_INVALID = 2, FLAG_DONE = 4 };
 
 // launchers (gbp_kernels.hip); all asynchronous on `s`
 template <typename TS> void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, hipStream_t s);
 template <typename TS> void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s);
-template <typename TS> void launch_factor(const Dev<TS> &d, const IterOpts &o, int block, int variant, hipStream_t s);
+template <typename TS> void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
+template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
+void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s);
+template <typename TS> void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s);
 template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s);

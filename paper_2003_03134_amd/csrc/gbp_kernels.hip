@@ -147,6 +147,19 @@ __device__ __forceinline__ void chol_inverse_solve(const double (&L)[D * (D + 1)
 }
 
 // --------------------------------------------------------------------------
+// XCD-aware work mapping: workgroups are dispatched round-robin over the
+// eight XCDs (each with its own L2); this bijection on [0, n) gives XCD x a
+// contiguous range of work items, so neighbouring keyframes, factors and
+// landmarks (which share beliefs) meet in the same L2.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    constexpr int NX = 8;
+    const int q = n / NX, r = n % NX;
+    const int x = b % NX, i = b / NX;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// --------------------------------------------------------------------------
 // measurement model h = pi(R(omega) l + t) and its 2x9 Jacobian (FP64)
 // --------------------------------------------------------------------------
 
@@ -392,17 +405,26 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 }
 
 // --------------------------------------------------------------------------
-// factor phase: relinearisation check + relinearise + messages + damping
+// factor phase
 // --------------------------------------------------------------------------
+//
+// One iteration runs k_check (relinearisation check; due factors go to a
+// queue), k_relin (queued factors relinearise and send their messages),
+// k_factor_kf (one workgroup per keyframe: every other factor of the
+// keyframe sends its messages, then the keyframe's new belief is formed from
+// all of its factors' messages in the same kernel) and k_belief_lm.
+// Factors are stored sorted by keyframe, so a workgroup's keyframe belief is
+// a uniform (scalar) load and its factor records are contiguous.
 
-// One factor's update. RELIN = false is the hot path: a factor that is due
-// for relinearisation is appended to the relinearisation queue and left to
-// the RELIN = true instance (a separate kernel), which relinearises it and
-// forms the cavity through both the old and the new Jacobian. Keeping the
-// rare path out of the hot kernel keeps its register footprint small.
+// One factor's message update (Section 5). RELIN = true relinearises first
+// (Section 4) and forms the cavity through both the old and the new
+// Jacobian. k and bk are the factor's keyframe and its current belief.
+// `stage` (may be null) receives the keyframe-side Jacobian and the new
+// stored message for the keyframe belief reduction.
 template <typename TS, bool RELIN>
-__device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const bool valid) {
-    const int k = d.f_kf[f], m = d.f_lm[f];
+__device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
+                                            const double *__restrict__ bk, TS *__restrict__ stage) {
+    const int m = d.f_lm[f];
     TS ar[AREC], kr[KREC], lr[LREC];
     load16(d.arec + (size_t)f * AREC, ar);
     load16(d.krec + (size_t)f * KREC, kr);
@@ -410,7 +432,6 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     int c = d.cnt[f];
     const uint8_t fl = d.flags[f];
 
-    const double *bk = d.kf_bel + (size_t)k * KBEL;
     const double *bm = d.lm_bel + (size_t)m * LBEL;
     double dmk[6], dmm[3];
 #pragma unroll
@@ -423,28 +444,6 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     for (int i = 0; i < 6; ++i) d0k[i] = (double)ar[2 + i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) d0m[i] = (double)ar[8 + i];
-    if constexpr (!RELIN) {
-        // relinearisation check (Section 5, Section 8): pending request, or at
-        // least `interval` updates since the last linearisation and the
-        // stacked means farther than beta from the linearisation point.
-        // Factors that are due go to the queue, one atomic per wave.
-        double dist2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) { double e = dmk[i] - d0k[i]; dist2 += e * e; }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { double e = dmm[i] - d0m[i]; dist2 += e * e; }
-        const bool need = valid && ((fl & FLAG_PENDING) || (c >= o.interval && dist2 > o.beta2));
-        const unsigned long long mask = __ballot(need);
-        if (mask) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(d.relin_count, __popcll(mask));
-            base = __shfl(base, leader, 64);
-            if (need) d.relin_queue[base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
-        }
-        if (need || !valid) return;
-    }
     constexpr bool relin = RELIN;
 
     // current (old) Jacobian blocks
@@ -463,7 +462,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     const double Sma = lr[6], Smb = lr[7], Smc = lr[8], gm0 = lr[9], gm1 = lr[10];
 
     double Jkn[2][6], Jmn[2][3];
-    uint8_t nfl = fl & (uint8_t)~FLAG_PENDING;
+    uint8_t nfl = (uint8_t)((fl & ~FLAG_PENDING) | (RELIN ? FLAG_DONE : 0));
     if constexpr (RELIN) {
         const ProbParams pp = d.prob[d.kf_prob[k]];
         const double hk = (fl & FLAG_PENDING) ? d.pending_k[0] : o.huber_k;
@@ -583,29 +582,218 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         aw[11] = (TS)jak0; aw[12] = (TS)jak1; aw[13] = (TS)jam0; aw[14] = (TS)jam1;
     }
     d.cnt[f] = (uint8_t)(c + 1 > 255 ? 255 : c + 1);
-    if (nfl != fl) d.flags[f] = nfl;
+    if constexpr (RELIN) d.flags[f] = nfl;
+    if (stage) {
+        // keyframe-side Jacobian and the stored (rounded) message, for the
+        // keyframe belief reduction
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { stage[i] = (TS)Jkn[0][i]; stage[6 + i] = (TS)Jkn[1][i]; }
+        stage[12] = (TS)oSk_a; stage[13] = (TS)oSk_b; stage[14] = (TS)oSk_c;
+        stage[15] = (TS)ogk0; stage[16] = (TS)ogk1; stage[17] = (TS)0;
+    }
 }
 
-// Hot factor kernel; WPE > 0 asks the compiler for at least WPE waves per
-// SIMD (trading registers for occupancy). The variant is chosen at run time.
-template <typename TS, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, 8)))
-void k_factor(Dev<TS> d, IterOpts o) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
-    if (d.nf == 0) return;
-    // lanes past the end load a valid factor's data and discard it, so the
-    // wave reaches the queue ballot together
-    const bool valid = f < d.nf;
-    factor_body<TS, false>(d, o, valid ? f : d.nf - 1, valid);
-}
-
-// factors queued for relinearisation by k_factor in this iteration
+// Relinearisation check (Section 5, Section 8): a pending request, or at
+// least `interval` updates since the last linearisation and the stacked means
+// farther than beta from the linearisation point. Each workgroup compacts
+// its due factors into its own queue segment (wave ballots and a prefix over
+// the workgroup's waves), so no atomics are needed. Also advances the clock.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_factor_relin(Dev<TS> d, IterOpts o) {
-    const int n = d.relin_count[0];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        factor_body<TS, true>(d, o, d.relin_queue[i], true);
+__global__ __launch_bounds__(256) void k_check(Dev<TS> d, IterOpts o) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = blk * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
+    bool need = false;
+    if (f < d.nf) {
+        const uint8_t fl = d.flags[f];
+        if (fl & FLAG_PENDING) {
+            need = true;
+        } else if (d.cnt[f] >= o.interval) {
+            const int k = d.f_kf[f], m = d.f_lm[f];
+            const TS *ar = d.arec + (size_t)f * AREC;
+            const double *bk = d.kf_bel + (size_t)k * KBEL;
+            const double *bm = d.lm_bel + (size_t)m * LBEL;
+            double dist2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)ar[2 + i]; dist2 += e * e; }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)ar[8 + i]; dist2 += e * e; }
+            need = dist2 > o.beta2;
+        }
+    }
+    __shared__ int wcount[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long mask = __ballot(need);
+    if (lane == 0) wcount[wave] = __popcll(mask);
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wcount[w];
+    if (need) d.relin_queue[(size_t)blk * 256 + base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
+    if (threadIdx.x == 0) d.relin_qcount[blk] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+}
+
+// queue segment of check-workgroup b: relinearise and send (marks done)
+template <typename TS>
+__global__ __launch_bounds__(256) void k_relin(Dev<TS> d, IterOpts o) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int n = d.relin_qcount[blk];
+    if ((int)threadIdx.x >= n) return;
+    const int f = d.relin_queue[(size_t)blk * 256 + threadIdx.x];
+    const int k = d.f_kf[f];
+    factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
+}
+
+// factors relinearised in the last iteration: sum of the queue segments
+__global__ __launch_bounds__(256) void k_relin_total(const int *qcount, int nb, unsigned long long *out) {
+    __shared__ unsigned long long sh[256];
+    unsigned long long s = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += (unsigned long long)qcount[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__device__ __forceinline__ double prior_scale(const IterOpts &o, int age) {
+    int a = age < 0 ? 0 : (age > o.anneal_iters ? o.anneal_iters : age);
+    return o.scale[a];
+}
+
+// Keyframe belief (eqs. (beliefeta), (belieflambda)) from the summed
+// messages (21 packed information entries, 6 information-vector entries,
+// anchor-relative) plus the prior at the current clock; FP64 Cholesky,
+// covariance and mean offset; absolute pose for the residual phase.
+template <typename TS>
+__device__ void kf_solve(const Dev<TS> &d, const IterOpts &o, const int k, const double *sums, const int readout) {
+    double A[21], e[6];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) A[i] = sums[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = sums[21 + i];
+    const double pinfo = d.kf_pinfo[k];
+    if (pinfo > 0.0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += pinfo;
+    } else {
+        const double sc = prior_scale(o, d.t_dev[0] - d.kf_t0[k]);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += d.kf_pbase[6 * (size_t)k + i] * sc;
+    }
+    if (readout) {
+        double *out = d.kf_info + 36 * (size_t)k;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) out[6 * i + j] = A[pidx<6>(i, j)];
+    }
+    double L[21], inv[21], x[6];
+    if (!chol<6>(A, L)) { atomicOr(d.status, 1u); return; }
+    chol_inverse_solve<6>(L, e, inv, x);
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) fin = fin && isfinite(x[i]);
+    if (!fin) { atomicOr(d.status, 2u); return; }
+    double *b = d.kf_bel + (size_t)k * KBEL;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) b[i] = x[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) b[6 + i] = inv[i];
+    double w[6], R[9];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) w[i] = d.kf_anchor[6 * (size_t)k + i] + x[i];
+    so3_exp_d(w, R);
+    double *ps = d.kf_pose + 12 * (size_t)k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ps[i] = R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ps[9 + i] = w[3 + i];
+}
+
+// Contribution of one factor's keyframe-side message to the keyframe belief
+// (eqs. (beliefeta), (belieflambda)): J^T S J (21 packed) and J^T g (6).
+template <typename TS>
+__device__ __forceinline__ void kf_contrib(const TS *row, double *c) {
+    double J0[6], J1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { J0[i] = (double)row[i]; J1[i] = (double)row[6 + i]; }
+    const double Sa = row[12], Sb = row[13], Sc = row[14], g0 = row[15], g1 = row[16];
+    double SJ0[6], SJ1[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = i; j < 6; ++j) c[pidx<6>(i, j)] = J0[i] * SJ0[j] + J1[i] * SJ1[j];
+        c[21 + i] = J0[i] * g0 + J1[i] * g1;
+    }
+}
+
+// One workgroup per keyframe. MODE 0: every factor of the keyframe not
+// relinearised this iteration sends its messages, then the keyframe's
+// message sums (information and information vector) are formed; MODE 1:
+// sums only (creation, read-out). k_kf_solve turns the sums into beliefs.
+// Each lane forms its factor's 27 contributions and writes them to a padded
+// LDS row; 27 x G lanes then add interleaved rows column by column and the G
+// partials are added in group order (fixed order, no cross-lane shuffles).
+template <typename TS, int BS, int MODE>
+__global__ __launch_bounds__(BS) void k_factor_kf(Dev<TS> d, IterOpts o) {
+    constexpr int G = BS / 32;     // row groups in the column sums
+    constexpr int RS = 29;         // padded row stride (doubles) against bank conflicts
+    __shared__ double red[BS * RS];
+    __shared__ double part[G][28];
+    const int k = xcd_remap(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x;
+    const int e0 = d.kf_row[k], e1 = d.kf_row[k + 1];
+    const double *bk = d.kf_bel + (size_t)k * KBEL;
+    const int col = tid % 27, grp = tid / 27;
+    double acc = 0.0;
+    for (int base = e0; base < e1; base += BS) {
+        const int f = base + tid;
+        TS row[18];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) row[i] = (TS)0;
+        if (f < e1) {
+            const uint8_t fl = d.flags[f];
+            if (MODE == 0 && !(fl & FLAG_DONE)) {
+                factor_body<TS, false>(d, o, f, k, bk, row);
+            } else {
+                TS kr[KREC];
+                load16(d.krec + (size_t)f * KREC, kr);
+                row[0] = kr[0]; row[1] = kr[1]; row[2] = kr[2]; row[3] = kr[6]; row[5] = kr[8];
+                row[6] = kr[3]; row[7] = kr[4]; row[8] = kr[5]; row[10] = kr[7]; row[11] = kr[9];
+                row[12] = kr[10]; row[13] = kr[11]; row[14] = kr[12]; row[15] = kr[13]; row[16] = kr[14];
+                if (MODE == 0) d.flags[f] = (uint8_t)(fl & ~FLAG_DONE);
+            }
+        }
+        kf_contrib<TS>(row, red + tid * RS);
+        __syncthreads();
+        if (grp < G) {
+            double s = 0.0;
+            for (int q = grp; q < BS; q += G) s += red[q * RS + col];
+            part[grp][col] = s;
+        }
+        __syncthreads();
+        if (tid < 27)
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc += part[g][tid];
+        __syncthreads();
+    }
+    if (tid < 27) d.kf_sums[32 * (size_t)k + tid] = acc;
+}
+
+// one thread per keyframe: belief from the summed messages (k_factor_kf)
+template <typename TS>
+__global__ __launch_bounds__(64) void k_kf_solve(Dev<TS> d, IterOpts o, int readout) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.nk) return;
+    double s[27];
+    const double *src = d.kf_sums + 32 * (size_t)k;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) s[i] = src[i];
+    kf_solve<TS>(d, o, k, s, readout);
 }
 
 // --------------------------------------------------------------------------
@@ -672,8 +860,8 @@ __global__ __launch_bounds__(256) void k_prior_kf(Dev<TS> d, int k0) {
     const int lane = threadIdx.x & 63;
     if (k >= d.nk) return;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int e = d.kf_row[k] + lane; e < d.kf_row[k + 1]; e += 64) {
-        const TS *r = d.krec + (size_t)d.kf_edge[e] * KREC;
+    for (int f = d.kf_row[k] + lane; f < d.kf_row[k + 1]; f += 64) {
+        const TS *r = d.krec + (size_t)f * KREC;
         double j00 = r[0], j01 = r[1], j02 = r[2], j10 = r[3], j11 = r[4], j12 = r[5];
         double a0 = r[6], a1 = r[7], b0 = r[8], b1 = r[9];
         acc[0] += j00 * j00 + j10 * j10;
@@ -702,8 +890,8 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
     const int m = m0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.nl) return;
     double acc[3] = {0, 0, 0};
-    for (int f = d.lm_row[m]; f < d.lm_row[m + 1]; ++f) {
-        const TS *r = d.lrec + (size_t)f * LREC;
+    for (int e = d.lm_row[m]; e < d.lm_row[m + 1]; ++e) {
+        const TS *r = d.lrec + (size_t)d.lm_edge[e] * LREC;
 #pragma unroll
         for (int i = 0; i < 3; ++i) acc[i] += (double)r[i] * (double)r[i] + (double)r[3 + i] * (double)r[3 + i];
     }
@@ -720,14 +908,10 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
 // clock plus the sum of incoming messages, then covariance and mean offset
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ double prior_scale(const IterOpts &o, int age) {
-    int a = age < 0 ? 0 : (age > o.anneal_iters ? o.anneal_iters : age);
-    return o.scale[a];
-}
 
 template <typename TS>
 __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (m >= d.nl) return;
     const int t = d.t_dev[0];
     const double sc = prior_scale(o, t - d.lm_t0[m]);
@@ -735,9 +919,9 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
     A[pidx<3>(0, 0)] = d.lm_pbase[3 * (size_t)m] * sc;
     A[pidx<3>(1, 1)] = d.lm_pbase[3 * (size_t)m + 1] * sc;
     A[pidx<3>(2, 2)] = d.lm_pbase[3 * (size_t)m + 2] * sc;
-    for (int f = d.lm_row[m]; f < d.lm_row[m + 1]; ++f) {
+    for (int ei = d.lm_row[m]; ei < d.lm_row[m + 1]; ++ei) {
         TS r[LREC];
-        load12(d.lrec + (size_t)f * LREC, r);
+        load12(d.lrec + (size_t)d.lm_edge[ei] * LREC, r);
         double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
         double Sa = r[6], Sb = r[7], Sc = r[8], g0 = r[9], g1 = r[10];
         double SJ0[3], SJ1[3];
@@ -769,84 +953,6 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
     for (int i = 0; i < 3; ++i) b[i] = x[i];
 #pragma unroll
     for (int i = 0; i < 6; ++i) b[3 + i] = inv[i];
-}
-
-template <typename TS>
-__global__ __launch_bounds__(256) void k_belief_kf(Dev<TS> d, IterOpts o, int readout) {
-    const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {  // queue consumed
-        d.relin_total[0] += (unsigned long long)d.relin_count[0];
-        d.relin_count[0] = 0;
-    }
-    if (k >= d.nk) return;
-    double A[21], e[6];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) A[i] = 0.0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) e[i] = 0.0;
-    for (int ei = d.kf_row[k] + lane; ei < d.kf_row[k + 1]; ei += 64) {
-        TS r[KREC];
-        load16(d.krec + (size_t)d.kf_edge[ei] * KREC, r);
-        double J0[6] = {r[0], r[1], r[2], r[6], 0.0, r[8]};
-        double J1[6] = {r[3], r[4], r[5], 0.0, r[7], r[9]};
-        double Sa = r[10], Sb = r[11], Sc = r[12], g0 = r[13], g1 = r[14];
-        double SJ0[6], SJ1[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-#pragma unroll
-            for (int j = i; j < 6; ++j) A[pidx<6>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
-            e[i] += J0[i] * g0 + J1[i] * g1;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < 21; ++i) A[i] += __shfl_xor(A[i], off, 64);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) e[i] += __shfl_xor(e[i], off, 64);
-    }
-    if (lane != 0) return;
-    const double pinfo = d.kf_pinfo[k];
-    if (pinfo > 0.0) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += pinfo;
-    } else {
-        const double sc = prior_scale(o, d.t_dev[0] - d.kf_t0[k]);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += d.kf_pbase[6 * (size_t)k + i] * sc;
-    }
-    if (readout) {
-        double *out = d.kf_info + 36 * (size_t)k;
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-            for (int j = 0; j < 6; ++j) out[6 * i + j] = A[pidx<6>(i, j)];
-    }
-    double L[21], inv[21], x[6];
-    if (!chol<6>(A, L)) { atomicOr(d.status, 1u); return; }
-    chol_inverse_solve<6>(L, e, inv, x);
-    bool fin = true;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) fin = fin && isfinite(x[i]);
-    if (!fin) { atomicOr(d.status, 2u); return; }
-    double *b = d.kf_bel + (size_t)k * KBEL;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) b[i] = x[i];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) b[6 + i] = inv[i];
-    // absolute pose of the new mean, consumed by the residual phase
-    double w[6], R[9];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) w[i] = d.kf_anchor[6 * (size_t)k + i] + x[i];
-    so3_exp_d(w, R);
-    double *ps = d.kf_pose + 12 * (size_t)k;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) ps[i] = R[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) ps[9 + i] = w[3 + i];
 }
 
 // --------------------------------------------------------------------------
@@ -886,7 +992,7 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
 template <typename TS>
 __global__ __launch_bounds__(256) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
                                                       const uint8_t *mask) {
-    const int b = blockIdx.x;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int f0 = d.rblk_start[b], f1 = d.rblk_start[b + 1];
     const ProbParams pp = d.prob[d.rblk_prob[b]];
     const double N = huber_k / pp.sigma;
@@ -982,16 +1088,34 @@ void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
     if (d.nl > m0) hipLaunchKernelGGL(k_prior_lm<TS>, dim3(blocks(d.nl - m0, 256)), dim3(256), 0, s, d, m0);
 }
 
-template <typename TS>
-void launch_factor(const Dev<TS> &d, const IterOpts &o, int block, int variant, hipStream_t s) {
-    const dim3 g(blocks(d.nf > 0 ? d.nf : 1, block)), b(block);
-    switch (variant) {
-        case 1: hipLaunchKernelGGL((k_factor<TS, 3>), g, b, 0, s, d, o); break;
-        case 2: hipLaunchKernelGGL((k_factor<TS, 4>), g, b, 0, s, d, o); break;
-        default: hipLaunchKernelGGL((k_factor<TS, 0>), g, b, 0, s, d, o); break;
+template <typename TS, int MODE>
+static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s) {
+    const dim3 g(d.nk);
+    switch (block) {
+        case 64: hipLaunchKernelGGL((k_factor_kf<TS, 64, MODE>), g, dim3(64), 0, s, d, o); break;
+        case 256: hipLaunchKernelGGL((k_factor_kf<TS, 256, MODE>), g, dim3(256), 0, s, d, o); break;
+        default: hipLaunchKernelGGL((k_factor_kf<TS, 128, MODE>), g, dim3(128), 0, s, d, o); break;
     }
-    const int rb = std::min(blocks(d.nf > 0 ? d.nf : 1, 256), 2048);
-    hipLaunchKernelGGL(k_factor_relin<TS>, dim3(rb), dim3(256), 0, s, d, o);
+    hipLaunchKernelGGL(k_kf_solve<TS>, dim3(blocks(d.nk, 64)), dim3(64), 0, s, d, o, readout);
+}
+
+template <typename TS>
+void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
+    hipLaunchKernelGGL(k_check<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(256), 0, s, d, o);
+}
+
+template <typename TS>
+void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
+    hipLaunchKernelGGL(k_relin<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(256), 0, s, d, o);
+}
+
+void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_relin_total, dim3(1), dim3(256), 0, s, qcount, nb, out);
+}
+
+template <typename TS>
+void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s) {
+    launch_kf<TS, 0>(d, o, block, 0, s);
 }
 
 template <typename TS>
@@ -1001,7 +1125,7 @@ void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int bloc
 
 template <typename TS>
 void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
-    if (d.nk > 0) hipLaunchKernelGGL(k_belief_kf<TS>, dim3(blocks((long)d.nk * 64, block)), dim3(block), 0, s, d, o, readout);
+    launch_kf<TS, 1>(d, o, block, readout, s);
 }
 
 template <typename TS>
@@ -1047,7 +1171,9 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
 #define GBP_INSTANTIATE(TS)                                                                                        \
     template void launch_linearise<TS>(const Dev<TS> &, int, int, double, hipStream_t);                            \
     template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
-    template void launch_factor<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                     \
+    template void launch_check<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
+    template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
+    template void launch_factor_kf<TS>(const Dev<TS> &, const IterOpts &, int, hipStream_t);                       \
     template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_belief_kf<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
