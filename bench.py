@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--no-tune-cache", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -171,6 +172,8 @@ def main():
     zt = np.concatenate([p.z_true for p in probs])
     inl = np.concatenate([p.inlier for p in probs])
     solver.set_reference(zt, inl)
+    tuned = solver.autotune(5, None if args.no_tune_cache else os.path.join(ROOT, "profiles", "autotune_cache.txt"))
+    log(f"autotuned workgroup sizes: keyframe kernel {tuned[0]}, landmark kernel {tuned[1]}")
 
     K, W = args.steps, args.warmup
     c = max(1, min(args.chunk, K))
@@ -251,7 +254,8 @@ def main():
                    "n_keyframes": nk, "n_landmarks": nl, "n_factors": nf,
                    "factor_state": "f32", "beliefs": "f64",
                    "step": "relinearisation check + factor messages + beliefs + per-problem reprojection error",
-                   "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU"},
+                   "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU",
+                   "autotuned_blocks": {"keyframe_kernel": tuned[0], "landmark_kernel": tuned[1]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

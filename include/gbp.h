@@ -213,6 +213,17 @@ gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping,
  * Synchronises. */
 gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations);
 
+/* Autotuner: picks the workgroup sizes of the keyframe factor kernel and of
+ * the landmark belief kernel (64/128/256 each) by timing n_iters iterations
+ * of every candidate with HIP events on this problem, restoring the device
+ * state after each candidate (the problem's results are unchanged). The
+ * choice is cached in the text file cache_path (may be NULL: no cache),
+ * keyed by GPU architecture, precision and size bucket; a cached entry is
+ * used without timing. chosen[2] (may be NULL) receives the two sizes.
+ * Allocates a temporary copy of the workspace. Synchronises. */
+gbp_status gbp_autotune(gbp_problem *p, int32_t n_iters, const char *cache_path,
+                        int32_t *chosen);
+
 /* Sizes: keyframes, landmarks, factors, problems, completed iterations. */
 gbp_status gbp_sizes(const gbp_problem *p, int32_t *n_keyframes,
                      int32_t *n_landmarks, int32_t *n_factors,

@@ -193,6 +193,13 @@ class GBPSolver:
                                               _ptr(ms, C.c_double)), self.h)
         return dict(check=ms[0], relin=ms[1], factor_kf=ms[2], belief_lm=ms[3], reproj=ms[4])
 
+    def autotune(self, n_iters: int = 5, cache_path: str | None = None) -> tuple:
+        """Pick workgroup sizes by timing (state restored); returns (kf, lm)."""
+        chosen = (C.c_int32 * 2)()
+        path = cache_path.encode() if cache_path else None
+        self._check(self._lib.gbp_autotune(self.h, int(n_iters), path, chosen), self.h)
+        return chosen[0], chosen[1]
+
     def synchronize(self):
         self.stream.synchronize()
 

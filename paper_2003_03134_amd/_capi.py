@@ -58,7 +58,7 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_create_batch", "gbp_relinearise", "gbp_iterate", "gbp_beliefs",
            "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
-           "gbp_phase_times", "gbp_counters", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
+           "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
 
 _LIB = None
 
@@ -100,6 +100,7 @@ def load():
     lib.gbp_set_damping_model.argtypes = [P, _u16p, C.c_int32]
     lib.gbp_phase_times.argtypes = [P, C.c_int32, C.c_double, C.c_double, _dp]
     lib.gbp_counters.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.gbp_autotune.argtypes = [P, C.c_int32, C.c_char_p, _ip]
     lib.gbp_sizes.argtypes = [P, _ip, _ip, _ip, _ip, _ip]
     lib.gbp_last_error.argtypes = [P]
     lib.gbp_last_error.restype = C.c_char_p

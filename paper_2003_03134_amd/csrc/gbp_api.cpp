@@ -17,7 +17,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <numeric>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -298,8 +300,33 @@ void destroy_graphs(gbp_problem *p) {
     p->graphs.clear();
 }
 
+// residual-phase blocks: chunks of RBLK factors that stay inside a problem
+template <typename TS>
+gbp_status upload_rblk(gbp_problem *p) {
+    Dev<TS> &d = dev<TS>(p);
+    const int n = p->np;
+    std::vector<int> bstart, bprob, pblk(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        pblk[i] = (int)bprob.size();
+        for (int f = p->f_off[i]; f < p->f_off[i + 1]; f += RBLK) {
+            bstart.push_back(f);
+            bprob.push_back(i);
+        }
+    }
+    pblk[n] = (int)bprob.size();
+    bstart.push_back(p->nf);
+    d.n_rblk = (int)bprob.size();
+    HIP_TRY(p, hipMemcpyAsync((void *)d.rblk_start, bstart.data(), bstart.size() * 4, hipMemcpyHostToDevice, p->stream));
+    if (!bprob.empty())
+        HIP_TRY(p, hipMemcpyAsync((void *)d.rblk_prob, bprob.data(), bprob.size() * 4, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipMemcpyAsync((void *)d.prob_rblk, pblk.data(), pblk.size() * 4, hipMemcpyHostToDevice, p->stream));
+    // rblk arrays are sized for the capacity: F / RBLK + P + 1 blocks
+    return GBP_OK;
+}
+
 template <typename TS>
 gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera *cams, int n) {
+    gbp_status st_rb;
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
     const int nk = p->nk, nl = p->nl, nf = p->nf;
@@ -343,23 +370,8 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl + 1) * 4);
     std::vector<int> frp(p->f_off.begin(), p->f_off.end());
     UP(d.f_row_prob, frp.data(), frp.size() * 4);
-    {
-        // residual-phase blocks: chunks of RBLK factors that stay inside a problem
-        std::vector<int> bstart, bprob, pblk(n + 1, 0);
-        for (int i = 0; i < n; ++i) {
-            pblk[i] = (int)bprob.size();
-            for (int f = p->f_off[i]; f < p->f_off[i + 1]; f += RBLK) {
-                bstart.push_back(f);
-                bprob.push_back(i);
-            }
-        }
-        pblk[n] = (int)bprob.size();
-        bstart.push_back(nf);
-        d.n_rblk = (int)bprob.size();
-        UP(d.rblk_start, bstart.data(), bstart.size() * 4);
-        if (!bprob.empty()) UP(d.rblk_prob, bprob.data(), bprob.size() * 4);
-        UP(d.prob_rblk, pblk.data(), pblk.size() * 4);
-    }
+    st_rb = upload_rblk<TS>(p);
+    if (st_rb != GBP_OK) return st_rb;
     UP(d.z, p->h_z.data(), (size_t)nf * 2 * 8);
     HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
@@ -371,7 +383,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     d.fdamp = nullptr;
     // initial linearisation at the initial estimate, automatic priors,
     // beliefs = priors at clock 0
-    launch_linearise<TS>(d, 0, nf, p->huber_k, s);
+    launch_linearise<TS>(d, 0, nf, p->huber_k, nullptr, s);
     launch_prior_base<TS>(d, 0, 0, s);
     launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
     launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
@@ -531,6 +543,210 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
     for (auto &e : ev) (void)hipEventDestroy(e);
     for (int q = 0; q < NPH; ++q) ms[q] = acc[q] / n;
     p->t += n;
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status time_config(gbp_problem *p, int n, double *ms) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    hipEvent_t a, b;
+    HIP_TRY(p, hipEventCreate(&a));
+    HIP_TRY(p, hipEventCreate(&b));
+    HIP_TRY(p, hipEventRecord(a, s));
+    for (int i = 0; i < n; ++i) {
+        launch_check<TS>(d, p->iopt, s);
+        launch_relin<TS>(d, p->iopt, s);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    }
+    HIP_TRY(p, hipEventRecord(b, s));
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / n;
+    return GBP_OK;
+}
+
+std::string tune_key(gbp_problem *p) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    auto lg = [](long v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
+    std::ostringstream os;
+    os << arch.substr(0, arch.find(':')) << "/p" << p->precision << "/f" << lg(p->nf) << "/k" << lg(p->nk) << "/l"
+       << lg(p->nl);
+    return os.str();
+}
+
+// tiny cache: one line per key, "key kf_block lm_block ms"
+bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb) {
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string k2;
+    int a = 0, b = 0;
+    double ms = 0;
+    while (in >> k2 >> a >> b >> ms)
+        if (k2 == key) { kb = a; lb = b; return true; }
+    return false;
+}
+
+void cache_store(const char *path, const std::string &key, int kb, int lb, double ms) {
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << kb << " " << lb << " " << ms << "\n";
+}
+
+template <typename TS>
+gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t *chosen) {
+    const std::string key = tune_key(p);
+    int kb = 0, lb = 0;
+    if (cache_lookup(cache_path, key, kb, lb)) {
+        p->blk_kf = kb;
+        p->blk_lm = lb;
+    } else {
+        // snapshot the whole workspace, time every candidate, restore
+        void *snap = nullptr;
+        HIP_TRY(p, hipMalloc(&snap, p->ws_bytes));
+        HIP_TRY(p, hipMemcpyAsync(snap, p->ws, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+        const int kbs[3] = {64, 128, 256}, lbs[3] = {64, 128, 256};
+        double best = 1e30;
+        int bk = p->blk_kf, bl = p->blk_lm;
+        for (int x : kbs)
+            for (int y : lbs) {
+                p->blk_kf = x;
+                p->blk_lm = y;
+                double ms = 0;
+                gbp_status st = time_config<TS>(p, n, &ms);
+                if (st != GBP_OK) { (void)hipFree(snap); return st; }
+                HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+                if (ms < best) { best = ms; bk = x; bl = y; }
+            }
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+        (void)hipFree(snap);
+        p->blk_kf = bk;
+        p->blk_lm = bl;
+        cache_store(cache_path, key, bk, bl, best);
+    }
+    destroy_graphs(p);
+    if (chosen) { chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; }
+    return GBP_OK;
+}
+
+// Incremental growth (Section 9.2) of a single problem. Factor state is kept
+// keyframe-major, so the factor arrays are permuted on the device (old slots
+// gathered, new slots zeroed) and the index arrays rebuilt; new factors are
+// linearised at the current means, new variables get automatic priors from
+// their factors and their own annealing clock, and beliefs are re-formed
+// (existing ones only gain the new factors' zero messages).
+template <typename TS>
+gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const double *lm_init, int n_new_f,
+                    const int32_t *f_kf, const int32_t *f_lm, const double *z) {
+    if (p->np != 1) return fail(p, GBP_ESTATE, "incremental growth needs a single (non-batched) problem");
+    if (n_new_lm < 0 || n_new_f < 0 || (n_new_lm > 0 && !lm_init) || (n_new_f > 0 && (!f_kf || !f_lm || !z)))
+        return fail(p, GBP_EINVAL, "bad growth arguments");
+    const int nk0 = p->nk, nl0 = p->nl, nf0 = p->nf;
+    const int nk1 = nk0 + (pose ? 1 : 0), nl1 = nl0 + n_new_lm, nf1 = nf0 + n_new_f;
+    if (nk1 > p->cap_k || nl1 > p->cap_l || nf1 > p->cap_f)
+        return fail(p, GBP_ENOMEM, "growth exceeds the capacity set at creation (max_keyframes/landmarks/factors)");
+    for (int i = 0; i < n_new_f; ++i) {
+        if (f_kf[i] < 0 || f_kf[i] >= nk1 || f_lm[i] < 0 || f_lm[i] >= nl1)
+            return fail(p, GBP_EINVAL, "new factor " + std::to_string(i) + " has an out-of-range variable index");
+        if (!std::isfinite(z[2 * i]) || !std::isfinite(z[2 * i + 1]))
+            return fail(p, GBP_EINVAL, "new factor " + std::to_string(i) + " has a non-finite measurement");
+    }
+    if (pose)
+        for (int c = 0; c < 6; ++c)
+            if (!std::isfinite(pose[c])) return fail(p, GBP_EINVAL, "non-finite keyframe pose");
+    for (long i = 0; i < 3L * n_new_lm; ++i)
+        if (!std::isfinite(lm_init[i])) return fail(p, GBP_EINVAL, "non-finite landmark position");
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    // caller landmark index -> internal index (new landmarks are appended)
+    std::vector<int> lm_user2int(nl1);
+    for (int m = 0; m < nl0; ++m) lm_user2int[p->lm_int2user[m]] = m;
+    for (int j = 0; j < n_new_lm; ++j) lm_user2int[nl0 + j] = nl0 + j;
+    // all factors (old: internal order; new appended), then keyframe-major order
+    std::vector<int> fk(nf1), fl(nf1), src(nf1), user(nf1);
+    std::vector<double> zz(2 * (size_t)nf1);
+    for (int f = 0; f < nf0; ++f) {
+        fk[f] = p->h_fkf[f]; fl[f] = p->h_flm[f]; src[f] = f; user[f] = p->f_int2user[f];
+        zz[2 * f] = p->h_z[2 * f]; zz[2 * f + 1] = p->h_z[2 * f + 1];
+    }
+    for (int i = 0; i < n_new_f; ++i) {
+        const int f = nf0 + i;
+        fk[f] = f_kf[i]; fl[f] = lm_user2int[f_lm[i]]; src[f] = -1; user[f] = nf0 + i;
+        zz[2 * (size_t)f] = z[2 * i]; zz[2 * (size_t)f + 1] = z[2 * i + 1];
+    }
+    std::vector<int> order(nf1);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (fk[x] != fk[y]) return fk[x] < fk[y];
+        return fl[x] < fl[y];
+    });
+    std::vector<int> perm(nf1), fresh;
+    p->h_fkf.resize(nf1); p->h_flm.resize(nf1); p->h_z.resize(2 * (size_t)nf1); p->f_int2user.resize(nf1);
+    for (int r = 0; r < nf1; ++r) {
+        const int f = order[r];
+        perm[r] = src[f];
+        if (src[f] < 0) fresh.push_back(r);
+        p->h_fkf[r] = fk[f]; p->h_flm[r] = fl[f]; p->f_int2user[r] = user[f];
+        p->h_z[2 * (size_t)r] = zz[2 * (size_t)f]; p->h_z[2 * (size_t)r + 1] = zz[2 * (size_t)f + 1];
+    }
+    p->nk = nk1; p->nl = nl1; p->nf = nf1;
+    p->kf_off = {0, nk1}; p->lm_off = {0, nl1}; p->f_off = {0, nf1};
+    for (int j = 0; j < n_new_lm; ++j) p->lm_int2user.push_back(nl0 + j);
+    build_csr(p);
+    // new variables: anchors (initial estimates), clocks, problem index
+    if (pose) p->h_kf_anchor.insert(p->h_kf_anchor.end(), pose, pose + 6);
+    p->h_lm_anchor.insert(p->h_lm_anchor.end(), lm_init, lm_init + 3 * (size_t)n_new_lm);
+#define UP(dst, srcp, bytes) HIP_TRY(p, hipMemcpyAsync((void *)(dst), (const void *)(srcp), (bytes), hipMemcpyHostToDevice, s))
+    std::vector<int> tk(nk1 - nk0, p->t), tl(n_new_lm, p->t), zk(nk1 - nk0, 0), zl(n_new_lm, 0);
+    std::vector<double> pk(nk1 - nk0, 0.0);
+    if (pose) {
+        UP(d.kf_anchor + 6 * (size_t)nk0, pose, 6 * 8);
+        UP(d.kf_pinfo + nk0, pk.data(), 8);
+        UP(d.kf_t0 + nk0, tk.data(), 4);
+        UP(d.kf_prob + nk0, zk.data(), 4);
+        HIP_TRY(p, hipMemsetAsync(d.kf_bel + (size_t)nk0 * KBEL, 0, KBEL * 8, s));
+    }
+    if (n_new_lm) {
+        UP(d.lm_anchor + 3 * (size_t)nl0, lm_init, 3 * 8 * (size_t)n_new_lm);
+        UP(d.lm_t0 + nl0, tl.data(), 4 * (size_t)n_new_lm);
+        UP(d.lm_prob + nl0, zl.data(), 4 * (size_t)n_new_lm);
+        HIP_TRY(p, hipMemsetAsync(d.lm_bel + (size_t)nl0 * LBEL, 0, (size_t)n_new_lm * LBEL * 8, s));
+    }
+    // permute the device factor state into the new order
+    UP(p->d_perm, perm.data(), (size_t)nf1 * 4);
+    launch_permute_factors<TS>(d, p->d_perm, nf1, p->d_scratch, s);
+    UP(d.f_kf, p->h_fkf.data(), (size_t)nf1 * 4);
+    UP(d.f_lm, p->h_flm.data(), (size_t)nf1 * 4);
+    UP(d.z, p->h_z.data(), (size_t)nf1 * 2 * 8);
+    UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk1 + 1) * 4);
+    UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl1 + 1) * 4);
+    UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf1 * 4);
+    std::vector<int> frp = {0, nf1};
+    UP(d.f_row_prob, frp.data(), 8);
+    d.nk = nk1; d.nl = nl1; d.nf = nf1;
+    gbp_status st = upload_rblk<TS>(p);
+    if (st != GBP_OK) return st;
+    // new factors: linearise at the current means (their slots are scattered)
+    if (!fresh.empty()) {
+        UP(p->d_perm, fresh.data(), fresh.size() * 4);
+        launch_linearise<TS>(d, 0, (int)fresh.size(), p->huber_k, p->d_perm, s);
+    }
+#undef UP
+    launch_prior_base<TS>(d, nk0, nl0, s);
+    launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(s));
+    destroy_graphs(p);
     return GBP_OK;
 }
 
@@ -759,7 +975,8 @@ gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6], int32_t n_new_
                             int32_t n_new_f, const int32_t *f_kf, const int32_t *f_lm, const double *z) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
-    return fail(p, GBP_ESTATE, "incremental growth is not available in this build");
+    return p->precision == GBP_FP32 ? add_impl<float>(p, pose, n_new_lm, lm_init, n_new_f, f_kf, f_lm, z)
+                                    : add_impl<double>(p, pose, n_new_lm, lm_init, n_new_f, f_kf, f_lm, z);
 }
 
 gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_t every_k) {
@@ -788,6 +1005,14 @@ gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations) {
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     if (relinearisations) *relinearisations = (int64_t)v;
     return GBP_OK;
+}
+
+gbp_status gbp_autotune(gbp_problem *p, int32_t n_iters, const char *cache_path, int32_t *chosen) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n_iters < 1) return fail(p, GBP_EINVAL, "need n_iters >= 1");
+    return p->precision == GBP_FP32 ? autotune_impl<float>(p, n_iters, cache_path, chosen)
+                                    : autotune_impl<double>(p, n_iters, cache_path, chosen);
 }
 
 gbp_status gbp_sizes(const gbp_problem *p, int32_t *nk, int32_t *nl, int32_t *nf, int32_t *np, int32_t *t) {

@@ -83,7 +83,8 @@ struct IterOpts {
 enum : uint8_t { FLAG_PENDING = 1, FLAG_INVALID = 2, FLAG_DONE = 4 };
 
 // launchers (gbp_kernels.hip); all asynchronous on `s`
-template <typename TS> void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, hipStream_t s);
+template <typename TS> void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, const int *list,
+                                             hipStream_t s);
 template <typename TS> void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s);
 template <typename TS> void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
 template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s);

@@ -801,9 +801,10 @@ __global__ __launch_bounds__(64) void k_kf_solve(Dev<TS> d, IterOpts o, int read
 // --------------------------------------------------------------------------
 
 template <typename TS>
-__global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, double huber_k) {
-    const int f = f0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= f1) return;
+__global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, double huber_k, const int *list) {
+    const int i = f0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= f1) return;
+    const int f = list ? list[i] : i;
     const int k = d.f_kf[f], m = d.f_lm[f];
     const ProbParams pp = d.prob[d.kf_prob[k]];
     double x[6], l[3], dmk[6], dmm[3], zz[2] = {d.z[2 * (size_t)f], d.z[2 * (size_t)f + 1]};
@@ -1078,8 +1079,9 @@ __global__ __launch_bounds__(256) void k_gather(const T *src, T *dst, const int 
 static inline int blocks(long n, int b) { return (int)((n + b - 1) / b); }
 
 template <typename TS>
-void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, hipStream_t s) {
-    if (f1 > f0) hipLaunchKernelGGL(k_linearise<TS>, dim3(blocks(f1 - f0, 256)), dim3(256), 0, s, d, f0, f1, huber_k);
+void launch_linearise(const Dev<TS> &d, int f0, int f1, double huber_k, const int *list, hipStream_t s) {
+    if (f1 > f0)
+        hipLaunchKernelGGL(k_linearise<TS>, dim3(blocks(f1 - f0, 256)), dim3(256), 0, s, d, f0, f1, huber_k, list);
 }
 
 template <typename TS>
@@ -1152,7 +1154,6 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         T *tmp = (T *)scratch;
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
-            case 2: hipLaunchKernelGGL((k_gather<T, 2>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
             case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
         }
@@ -1161,7 +1162,6 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
     run(d.krec, TS(0), KREC);
     run(d.lrec, TS(0), LREC);
     run(d.arec, TS(0), AREC);
-    run(const_cast<double *>(d.z), double(0), 2);
     run(d.cnt, uint8_t(0), 1);
     run(d.flags, uint8_t(0), 1);
 }
@@ -1169,7 +1169,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
 void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, t_dev); }
 
 #define GBP_INSTANTIATE(TS)                                                                                        \
-    template void launch_linearise<TS>(const Dev<TS> &, int, int, double, hipStream_t);                            \
+    template void launch_linearise<TS>(const Dev<TS> &, int, int, double, const int *, hipStream_t);               \
     template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
     template void launch_check<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
     template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \

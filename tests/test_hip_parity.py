@@ -254,3 +254,89 @@ def test_reproj_stats_and_log(gbp):
     for key in ("are_all", "are_quadratic", "are_ref"):
         assert abs(rg[key] - ro[key]) < 1e-8, key
     s.close()
+
+
+# --------------------------------------------------------------------------
+# autotuner and incremental growth
+# --------------------------------------------------------------------------
+
+def test_autotune_leaves_state_unchanged(gbp, tmp_path):
+    import oracle
+    prob = synth.make_config1()
+    s = gbp.GBPSolver(prob)
+    s.iterate(15, 0.4, 2.0)
+    before = s.beliefs()          # stored beliefs (no recomputation)
+    cache = str(tmp_path / "tune.txt")
+    kb, lb = s.autotune(3, cache)
+    assert kb in (64, 128, 256) and lb in (64, 128, 256)
+    after = s.beliefs()
+    for key in before:            # the device state was restored exactly
+        assert np.array_equal(before[key], after[key]), key
+    # a second problem of the same size bucket takes the cached choice
+    s2 = gbp.GBPSolver(prob)
+    assert s2.autotune(3, cache) == (kb, lb)
+    assert open(cache).read().count("\n") == 1
+    o = oracle.Oracle(prob, anneal=True)
+    o.iterate(15, 0.4, 2.0)
+    s.iterate(20, 0.4, 2.0)
+    o.iterate(20, 0.4, 2.0)
+    assert mean_errs(s.beliefs(), o.beliefs()) < 1e-4
+    s.close()
+    s2.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_incremental_growth_matches_oracle(gbp, precision):
+    """Section 9.2 protocol: every 20 iterations one keyframe (initialised at
+    the previous keyframe's current estimate) and its new landmarks (1 m
+    along the ray) join with all their factors."""
+    import oracle
+    st = synth.make_incremental_stream(seed=20001, n_kf=12, n0=5, new_lm_per_kf=15)
+    full, base = st.full, st.base
+    prec = gbp.GBP_FP64 if precision == "fp64" else gbp.GBP_FP32
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    cap = (full.n_keyframes, full.n_landmarks, full.n_factors)
+    s = gbp.GBPSolver(base, precision=prec, capacity=cap)
+    o = oracle.Oracle(base, anneal=(precision == "fp32"))
+    user_of = {}
+    nb = base.n_landmarks
+    step_lms = [s_["lm"] for s_ in st.steps]
+    base_ids = sorted(set(range(full.n_landmarks)) - set(np.concatenate(step_lms)))
+    assert len(base_ids) == nb
+    for i, j in enumerate(base_ids):
+        user_of[int(j)] = i
+    n_lm = nb
+    for step in st.steps:
+        for _ in range(2):
+            s.iterate(10, 0.4, 2.0)
+            o.iterate(10, 0.4, 2.0)
+        ob = o.beliefs()
+        k = step["kf"]
+        pose = ob["kf_mu"][k - 1].copy()
+        new_lm = step["lm"]
+        for j in new_lm:
+            user_of[int(j)] = n_lm
+            n_lm += 1
+        fs = step["factors"]
+        fkf = full.factor_kf[fs]
+        flm = np.array([user_of[int(j)] for j in full.factor_lm[fs]], dtype=np.int32)
+        s.add_keyframe(pose, full.lm_init[new_lm], fkf, flm, full.z[fs])
+        o.add(pose, full.lm_init[new_lm], fkf, flm, full.z[fs])
+        g, r = s.beliefs(), o.beliefs()
+        assert g["kf_mu"].shape == r["kf_mu"].shape and g["lm_mu"].shape == r["lm_mu"].shape
+        assert mean_errs(g, r) < tol
+    for _ in range(3):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        assert mean_errs(s.beliefs(), o.beliefs()) < tol
+    assert abs(s.reproj()["are_all"] - o.reproj()["are_all"]) < (1e-8 if precision == "fp64" else 1e-3)
+    s.close()
+
+
+def test_growth_beyond_capacity_is_rejected(gbp):
+    prob = synth.make_config0(seed=1)
+    s = gbp.GBPSolver(prob)
+    with pytest.raises(gbp.GBPError) as e:
+        s.add_keyframe(prob.kf_init[1], np.zeros((1, 3)), [5], [prob.n_landmarks], [[300.0, 200.0]])
+    assert "capacity" in str(e.value)
+    s.close()
