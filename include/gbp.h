@@ -191,12 +191,103 @@ gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6],
                             int32_t n_new_f, const int32_t *f_kf,
                             const int32_t *f_lm, const double *z);
 
-/* Per-factor damping model: NULL restores the constant damping passed to
- * gbp_iterate. `weights` is the BF16 parameter blob of the damping MLP
- * (layout in gbp_mlp_param_count); it is evaluated every `every_k`
- * iterations inside gbp_iterate. */
+/* ---- learned damping ------------------------------------------------------
+ * The paper damps every message with one constant (Section 5, Section 8)
+ * and names learned components as future work (Section 10). This library
+ * replaces the constant by a per-factor value predicted by a small network
+ * (16 features -> 64 -> 64 -> 2, ReLU) evaluated on the GPU every few
+ * iterations; the network leaves the fixed points unchanged, since damping
+ * does (Section 5). Parameter blob (GBP_MLP_PARAMS values): W1[64][16],
+ * b1[64], W2[64][64], b2[64], W3[2][64], b3[2], row-major, output j of a
+ * layer = b[j] + sum_i W[j][i] in[i]. Heads: damping d = 0.9 sigmoid(o0),
+ * log-depth correction delta = 2.5 tanh(o1). Inference uses BF16 weights,
+ * inputs and hidden activations (round to nearest even) with FP32 sums. */
+#define GBP_MLP_PARAMS 5378
+#define GBP_MLP_FEATURES 16
+
+/* Per-factor damping model. `weights` (host, GBP_MLP_PARAMS BF16 bit
+ * patterns, copied) switches it on; NULL restores the constant damping
+ * passed to gbp_iterate. While on, every iteration whose clock t satisfies
+ * t % every_k == 0 first evaluates the per-problem mean reprojection error,
+ * the fallback monitor, the features (gbp_factor_features) and the network,
+ * whose damping head replaces the constant damping of each factor outside
+ * its undamped window. Fallback: a problem whose mean reprojection error
+ * exceeds (1 + fallback_rise) x the best value seen since the model was set
+ * (or since its last growth), or is not finite, or any failed belief, goes
+ * back to the constant damping for good (fallback_rise <= -1: never; a
+ * value in (-1, 0) switches every problem at the second evaluation). The
+ * first call allocates about 116 bytes of device memory per factor of
+ * capacity, owned by the problem. Errors: GBP_EINVAL for every_k outside
+ * [1, 1000] or a NaN fallback_rise. Synchronises. */
 gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
-                                 int32_t every_k);
+                                 int32_t every_k, double fallback_rise);
+
+/* Per-problem fallback state of the damping model (flags[n_problems]: 1 =
+ * switched back to the constant damping). Synchronises. */
+gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags);
+
+/* Features of the damping model, in the caller's factor order: computes the
+ * 16 features of every factor from the current state, advances their
+ * history (the message changes are taken since the previous evaluation)
+ * and writes row i of out (device, [n][16] float) for factor idx[i]
+ * (device int32). Rows of indices outside [0, n_factors) are NaN.
+ * Features: 0 residual at the linearisation point / Huber threshold,
+ * 1 Huber weight, 2 log(1 + residual / sigma), 3 updates since the last
+ * linearisation / 10, 4 log(1 + distance from the linearisation point /
+ * beta), 5-6 relative change of the keyframe- and landmark-side message
+ * vectors, 7 relative change of the landmark-side message information,
+ * 8 and 13 cosine of consecutive landmark- and keyframe-side message
+ * changes, 9 log(depth / 5 m), 10-11 log degrees of landmark and keyframe,
+ * 12 log trace of the landmark covariance / 10, 14 iteration / 300,
+ * 15 log(1 + pixel shift of the landmark since its linearisation).
+ * Synchronises. */
+gbp_status gbp_factor_features(gbp_problem *p, const int32_t *idx, int32_t n,
+                               float *out);
+
+/* Messages of factors idx[i] (device int32, caller order) into out (device,
+ * [n][16] float): S and g of the message to the keyframe (S = [[a b][b c]]
+ * as a, b, c; g in the factor's 2-D measurement space), the same for the
+ * landmark, the updates since the last linearisation, the factor's flags,
+ * then J_k a_k and J_m a_m (2 each). The message to variable v in variable
+ * space is information J_v^T S J_v and information vector
+ * J_v^T (g + S J_v a_v), with J_v the factor's Jacobian block and a_v the
+ * variable's initial estimate. Rows of indices outside [0, n_factors) are
+ * NaN. Synchronises. */
+gbp_status gbp_factor_messages(gbp_problem *p, const int32_t *idx, int32_t n,
+                               float *out);
+
+/* Network inference on caller buffers (all device pointers): x [n][16]
+ * float, weights GBP_MLP_PARAMS BF16, d_out [n] damping head, delta_out [n]
+ * log-depth head (may be NULL). Asynchronous on `stream` (hipStream_t, NULL
+ * = default stream). Errors (GBP_EINVAL, GBP_EDEVICE) leave their text in
+ * gbp_last_error(NULL). */
+gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n,
+                         float *d_out, float *delta_out, void *stream);
+
+/* Device workspace bytes of gbp_mlp_train_step for batches up to max_batch. */
+gbp_status gbp_mlp_train_workspace_bytes(int32_t max_batch, size_t *bytes);
+
+/* One training step of the network on caller buffers (all device pointers).
+ * Data: x [n_rows][16], targets y [n_rows][2] (damping, log-depth), sample
+ * weights mask [n_rows][2]; the batch is rows batch_idx[0..n_batch) (an
+ * index outside [0, n_rows) counts as a zero-weight sample). Loss
+ * (written to loss_out[0]): (1/n_batch) sum over the batch of
+ * mask0 (d - y0)^2 + mask1 (delta - y1)^2, with the forward pass of
+ * gbp_mlp_infer evaluated at the BF16 rounding of theta (FP32 master
+ * weights, GBP_MLP_PARAMS) and back-propagated in FP32; its gradient goes to
+ * grad_out [GBP_MLP_PARAMS]. step >= 1: then one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias correction for step `step`, learning rate lr)
+ * updates theta, adam_m, adam_v and writes the BF16 copy weights_bf16.
+ * step == 0: gradient and loss only (adam_m, adam_v, weights_bf16 may be
+ * NULL). Sums are in a fixed order: the result is deterministic.
+ * Asynchronous on `stream`. */
+gbp_status gbp_mlp_train_step(const float *x, const float *y, const float *mask,
+                              int32_t n_rows, const int32_t *batch_idx,
+                              int32_t n_batch, float *theta, float *adam_m,
+                              float *adam_v, uint16_t *weights_bf16, float lr,
+                              int32_t step, float *grad_out, float *loss_out,
+                              void *workspace, size_t workspace_bytes,
+                              void *stream);
 
 /* Per-phase timing (the compute phases of one iteration, Section 7 and
  * Fig. 3): runs n iterations with each phase launched separately and

@@ -18,7 +18,11 @@ from ._capi import (GBP_FP32, GBP_FP64, GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA,
                     HipLibraryMissing, gbp_reproj)
 
 __all__ = ["GBPSolver", "GBPError", "GBP_FP32", "GBP_FP64", "GBP_DAMP_ETA",
-           "GBP_DAMP_ETA_LAMBDA", "HipLibraryMissing", "load_library"]
+           "GBP_DAMP_ETA_LAMBDA", "HipLibraryMissing", "load_library", "mlp_infer",
+           "MLPTrainer", "MLP_PARAMS", "MLP_FEATURES"]
+
+MLP_PARAMS = _capi.MLP_PARAMS
+MLP_FEATURES = _capi.MLP_FEATURES
 
 
 class GBPError(RuntimeError):
@@ -251,10 +255,157 @@ class GBPSolver:
         self.lm_counts[-1] += lmi.shape[0]
         self.f_counts[-1] += fk.shape[0]
 
-    def set_damping_model(self, weights_bf16: np.ndarray | None, every_k: int = 5) -> None:
+    def set_damping_model(self, weights_bf16: np.ndarray | None, every_k: int = 5,
+                          fallback_rise: float = 0.1) -> None:
+        """Switch the learned per-factor damping on (BF16 bit patterns of
+        the network parameters) or off (None)."""
         if weights_bf16 is None:
-            self._check(self._lib.gbp_set_damping_model(self.h, None, 0), self.h)
+            self._check(self._lib.gbp_set_damping_model(self.h, None, 0, 0.0), self.h)
             return
         w = np.ascontiguousarray(weights_bf16, dtype=np.uint16)
+        if w.shape != (_capi.MLP_PARAMS,):
+            raise ValueError(f"weights must have {_capi.MLP_PARAMS} entries")
         self._keep_w = w
-        self._check(self._lib.gbp_set_damping_model(self.h, _ptr(w, C.c_uint16), int(every_k)), self.h)
+        self._check(self._lib.gbp_set_damping_model(self.h, _ptr(w, C.c_uint16), int(every_k),
+                                                     float(fallback_rise)), self.h)
+
+    def fallback_flags(self) -> np.ndarray:
+        out = np.zeros(self.n_problems, dtype=np.int32)
+        self._check(self._lib.gbp_fallback_flags(self.h, _ptr(out, C.c_int32)), self.h)
+        return out
+
+    def _device_rows(self, fn, idx, width):
+        torch = self._torch
+        with torch.cuda.stream(self.stream):
+            di = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32)).to(self.device)
+            out = torch.empty((di.numel(), width), dtype=torch.float32, device=self.device)
+        self._check(fn(self.h, C.c_void_p(di.data_ptr()), int(di.numel()), C.c_void_p(out.data_ptr())),
+                    self.h)
+        return out
+
+    def factor_features(self, idx) -> "torch.Tensor":
+        """Features (n x 16, device) of factors idx (caller order); advances
+        the feature history."""
+        return self._device_rows(self._lib.gbp_factor_features, idx, _capi.MLP_FEATURES)
+
+    def factor_messages(self, idx) -> "torch.Tensor":
+        """Message rows (n x 16, device) of factors idx (caller order)."""
+        return self._device_rows(self._lib.gbp_factor_messages, idx, 16)
+
+
+# ----------------------------------------------------------------------------
+# learned damping network (stateless C entry points on caller device buffers)
+# ----------------------------------------------------------------------------
+
+def _check_plain(st):
+    if st != 0:
+        raise GBPError(st, _capi.load().gbp_last_error(None).decode())
+
+
+def mlp_infer(weights_bf16, x, stream=None):
+    """Damping and log-depth heads of the network for feature rows x
+    (n x 16 float32 CUDA tensor); weights_bf16 is a CUDA tensor holding the
+    BF16 bit patterns (int16 or uint16, MLP_PARAMS entries)."""
+    import torch
+    lib = _capi.load()
+    if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 2 or x.shape[1] != MLP_FEATURES:
+        raise ValueError("x must be a CUDA float32 tensor of shape (n, 16)")
+    if weights_bf16.numel() != MLP_PARAMS or weights_bf16.element_size() != 2 or not weights_bf16.is_cuda:
+        raise ValueError("weights must be a CUDA tensor of MLP_PARAMS 16-bit values")
+    x = x.contiguous()
+    weights_bf16 = weights_bf16.contiguous()
+    n = x.shape[0]
+    d = torch.empty(n, dtype=torch.float32, device=x.device)
+    delta = torch.empty(n, dtype=torch.float32, device=x.device)
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check_plain(lib.gbp_mlp_infer(C.c_void_p(weights_bf16.data_ptr()), C.c_void_p(x.data_ptr()), n,
+                                   C.c_void_p(d.data_ptr()), C.c_void_p(delta.data_ptr()),
+                                   C.c_void_p(s.cuda_stream)))
+    return d, delta
+
+
+def init_mlp_params(seed: int = 0) -> np.ndarray:
+    """He-uniform weights and zero biases in the parameter-blob layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for rows, cols in ((64, 16), (64, 64), (2, 64)):
+        lim = np.sqrt(6.0 / cols)
+        parts.append(rng.uniform(-lim, lim, rows * cols))
+        parts.append(np.zeros(rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def bf16_bits(theta) -> np.ndarray:
+    """Round-to-nearest-even BF16 bit patterns of float32 values."""
+    u = np.ascontiguousarray(theta, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+class MLPTrainer:
+    """FP32 master weights, Adam moments and the BF16 copy of the network on
+    the GPU; each step calls gbp_mlp_train_step on a batch of rows of the
+    data set held on the device."""
+
+    def __init__(self, theta0=None, *, max_batch: int = 8192, seed: int = 0, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("MLPTrainer needs a ROCm GPU")
+        self._lib = _capi.load()
+        self.device = torch.device("cuda", device)
+        th = init_mlp_params(seed) if theta0 is None else np.asarray(theta0, dtype=np.float32)
+        if th.shape != (MLP_PARAMS,):
+            raise ValueError(f"theta must have {MLP_PARAMS} entries")
+        self.theta = torch.as_tensor(th.copy()).to(self.device)
+        self.m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros_like(self.m)
+        self.grad = torch.zeros_like(self.m)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.w = torch.as_tensor(bf16_bits(th).view(np.int16).copy()).to(self.device)
+        nbytes = C.c_size_t(0)
+        _check_plain(self._lib.gbp_mlp_train_workspace_bytes(int(max_batch), C.byref(nbytes)))
+        self.max_batch = int(max_batch)
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.steps = 0
+        self.x = self.y = self.mask = None
+
+    def set_data(self, x, y, mask) -> None:
+        import torch
+        self.x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
+        self.y = torch.as_tensor(y, dtype=torch.float32).to(self.device).contiguous()
+        self.mask = torch.as_tensor(mask, dtype=torch.float32).to(self.device).contiguous()
+        if self.x.shape[1:] != (MLP_FEATURES,) or self.y.shape != (self.x.shape[0], 2) or \
+                self.mask.shape != self.y.shape:
+            raise ValueError("data shapes must be (n, 16), (n, 2), (n, 2)")
+
+    def _call(self, idx, lr, step):
+        import torch
+        if self.x is None:
+            raise RuntimeError("set_data first")
+        idx = torch.as_tensor(idx, dtype=torch.int32).to(self.device).contiguous()
+        if not 1 <= idx.numel() <= self.max_batch:
+            raise ValueError("batch size must be in [1, max_batch]")
+        s = torch.cuda.current_stream(self.device)
+        P = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        _check_plain(self._lib.gbp_mlp_train_step(
+            P(self.x), P(self.y), P(self.mask), int(self.x.shape[0]), P(idx), int(idx.numel()),
+            P(self.theta), P(self.m), P(self.v), P(self.w), float(lr), int(step), P(self.grad),
+            P(self.loss), P(self.ws), self.ws.numel(), C.c_void_p(s.cuda_stream)))
+        self._last_idx = idx  # keep the index buffer alive until the stream has used it
+
+    def step(self, idx, lr: float = 1e-3):
+        """One Adam step on rows idx; returns the batch loss tensor (device)."""
+        self.steps += 1
+        self._call(idx, lr, self.steps)
+        return self.loss
+
+    def gradient(self, idx):
+        """(gradient, loss) on rows idx without updating anything."""
+        self._call(idx, 0.0, 0)
+        return self.grad.clone(), float(self.loss.item())
+
+    def theta_host(self) -> np.ndarray:
+        return self.theta.cpu().numpy().astype(np.float32)
+
+    def weights_bf16(self) -> np.ndarray:
+        """BF16 bit patterns of the current master weights."""
+        return self.w.cpu().numpy().view(np.uint16).copy()

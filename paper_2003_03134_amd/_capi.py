@@ -58,7 +58,12 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_create_batch", "gbp_relinearise", "gbp_iterate", "gbp_beliefs",
            "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
+           "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
+           "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step",
            "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
+
+MLP_PARAMS = 5378
+MLP_FEATURES = 16
 
 _LIB = None
 
@@ -97,7 +102,14 @@ def load():
     lib.gbp_reproj_stats.argtypes = [P, C.c_int32, C.POINTER(gbp_reproj)]
     lib.gbp_set_reference.argtypes = [P, _dp, _u8p]
     lib.gbp_add_keyframe.argtypes = [P, _dp, C.c_int32, _dp, C.c_int32, _ip, _ip, _dp]
-    lib.gbp_set_damping_model.argtypes = [P, _u16p, C.c_int32]
+    lib.gbp_set_damping_model.argtypes = [P, _u16p, C.c_int32, C.c_double]
+    lib.gbp_fallback_flags.argtypes = [P, _ip]
+    lib.gbp_factor_features.argtypes = [P, P, C.c_int32, P]
+    lib.gbp_factor_messages.argtypes = [P, P, C.c_int32, P]
+    lib.gbp_mlp_infer.argtypes = [P, P, C.c_int32, P, P, P]
+    lib.gbp_mlp_train_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.gbp_mlp_train_step.argtypes = [P, P, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_float, C.c_int32,
+                                       P, P, P, C.c_size_t, P]
     lib.gbp_phase_times.argtypes = [P, C.c_int32, C.c_double, C.c_double, _dp]
     lib.gbp_counters.argtypes = [P, C.POINTER(C.c_int64)]
     lib.gbp_autotune.argtypes = [P, C.c_int32, C.c_char_p, _ip]

@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 def build(verbose: bool = False) -> str:
     objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in ("gbp_kernels.hip", "gbp_api.cpp"):
+    for src in ("gbp_kernels.hip", "gbp_mlp.hip", "gbp_api.cpp"):
         obj = os.path.join(HERE, "_build", src + ".o")
         cmd = ["hipcc", "-c", *HIP_FLAGS]
         if src.endswith(".cpp"):

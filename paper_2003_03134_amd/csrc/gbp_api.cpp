@@ -25,6 +25,7 @@
 
 #include "../../include/gbp.h"
 #include "gbp_internal.h"
+#include "gbp_mlp.h"
 
 using namespace gbp;
 
@@ -34,8 +35,12 @@ struct GraphEntry {
     int n;
     double damping, huber;
     int log_every;
+    int phase;  // clock modulo the model period (learned damping), else -1
     hipGraphExec_t exec;
 };
+
+// error text of calls that have no problem handle (the MLP entry points)
+thread_local std::string g_err;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -76,6 +81,19 @@ struct gbp_problem {
     std::vector<GraphEntry> graphs;
     bool use_graph = true;
     int blk_lm = 256, blk_kf = 128;
+    // learned damping (one allocation, made on first use)
+    float *fdamp_buf = nullptr;    // per-factor damping, in the workspace
+    void *learn_mem = nullptr;
+    float *d_feat = nullptr;       // [cap_f][16] features
+    float *d_hist = nullptr;       // [cap_f][12] feature history
+    float *d_delta = nullptr;      // [cap_f] log-depth head
+    uint16_t *d_w = nullptr;       // network weights (BF16 bits)
+    int *d_u2i = nullptr;          // caller factor index -> internal slot
+    int *d_fallback = nullptr;     // [np]
+    double *d_best = nullptr;      // [np] best mean reprojection error seen
+    bool learned = false;
+    int every_k = 5;
+    double fb_rise = 0.1;
     std::string err;
     bool broken = false;
 };
@@ -380,7 +398,9 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)(p->cap_f + 255) / 256 + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
 #undef UP
+    p->fdamp_buf = d.fdamp;
     d.fdamp = nullptr;
+    d.fallback = nullptr;
     // initial linearisation at the initial estimate, automatic priors,
     // beliefs = priors at clock 0
     launch_linearise<TS>(d, 0, nf, p->huber_k, nullptr, s);
@@ -453,11 +473,25 @@ gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const
     return st;
 }
 
+// Model evaluation of the learned damping (every `every_k` iterations of the
+// clock, before the iteration): per-problem reprojection error and the
+// fallback monitor, then features and the network, which writes the
+// per-factor damping used by the next factor phases.
+template <typename TS>
+void record_model(gbp_problem *p, hipStream_t s) {
+    Dev<TS> &d = dev<TS>(p);
+    launch_reproj<TS>(d, p->huber_k, nullptr, nullptr, nullptr, s);
+    launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.status, s);
+    launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
+    launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
+}
+
 template <typename TS>
 gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_base) {
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
     for (int i = 0; i < n; ++i) {
+        if (p->learned && (p->t + i) % p->every_k == 0) record_model<TS>(p, s);
         launch_check<TS>(d, p->iopt, s);
         launch_relin<TS>(d, p->iopt, s);
         launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
@@ -477,9 +511,11 @@ gbp_status iterate_impl(gbp_problem *p, int n, double damping, double huber_k, i
     if (n <= 0) return GBP_OK;
     hipStream_t s = p->stream;
     if (p->use_graph) {
+        const int phase = p->learned ? p->t % p->every_k : -1;
         GraphEntry *hit = nullptr;
         for (auto &g : p->graphs)
-            if (g.n == n && g.damping == damping && g.huber == huber_k && g.log_every == log_every) hit = &g;
+            if (g.n == n && g.damping == damping && g.huber == huber_k && g.log_every == log_every && g.phase == phase)
+                hit = &g;
         if (!hit) {
             if (p->graphs.size() >= 8) destroy_graphs(p);
             hipGraph_t graph;
@@ -493,7 +529,7 @@ gbp_status iterate_impl(gbp_problem *p, int n, double damping, double huber_k, i
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (ie != hipSuccess) return fail(p, GBP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-            p->graphs.push_back(GraphEntry{n, damping, huber_k, log_every, exec});
+            p->graphs.push_back(GraphEntry{n, damping, huber_k, log_every, phase, exec});
             hit = &p->graphs.back();
         }
         HIP_TRY(p, hipGraphLaunch(hit->exec, s));
@@ -638,6 +674,43 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
     return GBP_OK;
 }
 
+// caller factor index -> internal slot, on the device
+gbp_status upload_u2i(gbp_problem *p) {
+    std::vector<int> u2i(p->nf);
+    for (int i = 0; i < p->nf; ++i) u2i[p->f_int2user[i]] = i;
+    HIP_TRY(p, hipMemcpyAsync(p->d_u2i, u2i.data(), (size_t)p->nf * 4, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
+// Buffers of the learned damping (features, history, heads, weights, index
+// map, monitor state), sized by the factor capacity: one device allocation
+// of about 116 bytes per factor, owned by the problem.
+gbp_status ensure_learn_mem(gbp_problem *p) {
+    if (p->learn_mem) return GBP_OK;
+    Layout L;
+    const size_t F = p->cap_f, P = p->np;
+    L.add((void **)&p->d_feat, F * NFEAT * 4);
+    L.add((void **)&p->d_hist, F * FHIST * 4);
+    L.add((void **)&p->d_delta, F * 4);
+    L.add((void **)&p->d_w, MLP_NPARAMS * 2);
+    L.add((void **)&p->d_u2i, F * 4);
+    L.add((void **)&p->d_fallback, P * 4);
+    L.add((void **)&p->d_best, P * 8);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, L.total) != hipSuccess) return fail(p, GBP_ENOMEM, "cannot allocate the learned-model buffers");
+    p->learn_mem = mem;
+    for (auto &it : L.items) *it.first = (char *)mem + it.second;
+    hipStream_t s = p->stream;
+    HIP_TRY(p, hipMemsetAsync(p->d_hist, 0, F * FHIST * 4, s));
+    HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, P * 4, s));
+    std::vector<double> inf(P, HUGE_VAL);
+    HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), P * 8, hipMemcpyHostToDevice, s));
+    launch_fill_f32(p->fdamp_buf, -1.f, (int)F, s);
+    HIP_TRY(p, hipGetLastError());
+    return upload_u2i(p);
+}
+
 // Incremental growth (Section 9.2) of a single problem. Factor state is kept
 // keyframe-major, so the factor arrays are permuted on the device (old slots
 // gathered, new slots zeroed) and the index arrays rebuilt; new factors are
@@ -723,7 +796,8 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     }
     // permute the device factor state into the new order
     UP(p->d_perm, perm.data(), (size_t)nf1 * 4);
-    launch_permute_factors<TS>(d, p->d_perm, nf1, p->d_scratch, s);
+    launch_permute_factors<TS>(d, p->d_perm, nf1, p->d_scratch, p->learn_mem ? p->fdamp_buf : nullptr,
+                               p->d_hist, s);
     UP(d.f_kf, p->h_fkf.data(), (size_t)nf1 * 4);
     UP(d.f_lm, p->h_flm.data(), (size_t)nf1 * 4);
     UP(d.z, p->h_z.data(), (size_t)nf1 * 2 * 8);
@@ -745,8 +819,63 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
     launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
     HIP_TRY(p, hipGetLastError());
+    if (p->learn_mem) {
+        // the fallback monitor restarts: the new factors raise the error
+        st = upload_u2i(p);
+        if (st != GBP_OK) return st;
+        const double inf = HUGE_VAL;
+        HIP_TRY(p, hipMemcpyAsync(p->d_best, &inf, 8, hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(p, hipStreamSynchronize(s));
     destroy_graphs(p);
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status features_impl(gbp_problem *p, const int32_t *idx, int n, float *out) {
+    gbp_status st = ensure_learn_mem(p);
+    if (st != GBP_OK) return st;
+    Dev<TS> &d = dev<TS>(p);
+    launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, p->stream);
+    launch_gather_rows(p->d_feat, out, idx, p->d_u2i, p->nf, n, NFEAT, p->stream);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
+template <typename TS>
+gbp_status messages_impl(gbp_problem *p, const int32_t *idx, int n, float *out) {
+    gbp_status st = ensure_learn_mem(p);
+    if (st != GBP_OK) return st;
+    launch_export_messages<TS>(dev<TS>(p), idx, p->d_u2i, n, out, p->stream);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
+gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double rise) {
+    destroy_graphs(p);
+    if (!w) {
+        p->learned = false;
+        p->df.fdamp = nullptr; p->dd.fdamp = nullptr;
+        p->df.fallback = nullptr; p->dd.fallback = nullptr;
+        return GBP_OK;
+    }
+    gbp_status st = ensure_learn_mem(p);
+    if (st != GBP_OK) return st;
+    hipStream_t s = p->stream;
+    HIP_TRY(p, hipMemcpyAsync(p->d_w, w, MLP_NPARAMS * 2, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, (size_t)p->np * 4, s));
+    std::vector<double> inf(p->np, HUGE_VAL);
+    HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), (size_t)p->np * 8, hipMemcpyHostToDevice, s));
+    launch_fill_f32(p->fdamp_buf, -1.f, p->cap_f, s);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(s));
+    p->learned = true;
+    p->every_k = every_k;
+    p->fb_rise = rise > -1.0 ? rise : HUGE_VAL;
+    p->df.fdamp = p->fdamp_buf; p->dd.fdamp = p->fdamp_buf;
+    p->df.fallback = p->d_fallback; p->dd.fallback = p->d_fallback;
     return GBP_OK;
 }
 
@@ -979,11 +1108,82 @@ gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6], int32_t n_new_
                                     : add_impl<double>(p, pose, n_new_lm, lm_init, n_new_f, f_kf, f_lm, z);
 }
 
-gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_t every_k) {
+gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_t every_k, double fallback_rise) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
-    if (!weights) return GBP_OK;
-    return fail(p, GBP_ESTATE, "learned damping is not available in this build");
+    if (weights && (every_k < 1 || every_k > 1000 || std::isnan(fallback_rise)))
+        return fail(p, GBP_EINVAL, "need 1 <= every_k <= 1000 and a fallback_rise that is not NaN");
+    return set_model_impl(p, weights, every_k, fallback_rise);
+}
+
+gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!flags) return fail(p, GBP_EINVAL, "flags is null");
+    if (!p->learn_mem) {
+        for (int i = 0; i < p->np; ++i) flags[i] = 0;
+        return GBP_OK;
+    }
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    HIP_TRY(p, hipMemcpy(flags, p->d_fallback, (size_t)p->np * 4, hipMemcpyDeviceToHost));
+    return GBP_OK;
+}
+
+gbp_status gbp_factor_features(gbp_problem *p, const int32_t *idx, int32_t n, float *out) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n < 0 || (n > 0 && (!idx || !out))) return fail(p, GBP_EINVAL, "need n >= 0 and device idx/out");
+    return p->precision == GBP_FP32 ? features_impl<float>(p, idx, n, out) : features_impl<double>(p, idx, n, out);
+}
+
+gbp_status gbp_factor_messages(gbp_problem *p, const int32_t *idx, int32_t n, float *out) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (n < 0 || (n > 0 && (!idx || !out))) return fail(p, GBP_EINVAL, "need n >= 0 and device idx/out");
+    return p->precision == GBP_FP32 ? messages_impl<float>(p, idx, n, out) : messages_impl<double>(p, idx, n, out);
+}
+
+gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n, float *d_out, float *delta_out,
+                         void *stream) {
+    if (n < 0 || (n > 0 && (!weights || !x || !d_out))) {
+        g_err = "gbp_mlp_infer: need n >= 0 and device weights, x and d_out";
+        return GBP_EINVAL;
+    }
+    launch_mlp_infer(x, n, weights, d_out, delta_out, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { g_err = std::string("gbp_mlp_infer: ") + hipGetErrorString(e); return GBP_EDEVICE; }
+    return GBP_OK;
+}
+
+gbp_status gbp_mlp_train_workspace_bytes(int32_t max_batch, size_t *bytes) {
+    if (max_batch < 1 || !bytes) { g_err = "gbp_mlp_train_workspace_bytes: need max_batch >= 1"; return GBP_EINVAL; }
+    *bytes = (size_t)mlp_partial_blocks(max_batch) * (MLP_NPARAMS + 1) * 4 + 256;
+    return GBP_OK;
+}
+
+gbp_status gbp_mlp_train_step(const float *x, const float *y, const float *mask, int32_t n_rows,
+                              const int32_t *batch_idx, int32_t n_batch, float *theta, float *adam_m, float *adam_v,
+                              uint16_t *weights_bf16, float lr, int32_t step, float *grad_out, float *loss_out,
+                              void *workspace, size_t workspace_bytes, void *stream) {
+    size_t need = 0;
+    if (n_batch < 1 || n_rows < 0 || !x || !y || !mask || !batch_idx || !theta || !grad_out || !loss_out ||
+        !workspace || step < 0 || (step > 0 && (!adam_m || !adam_v || !weights_bf16 || !(lr > 0.f)))) {
+        g_err = "gbp_mlp_train_step: bad arguments";
+        return GBP_EINVAL;
+    }
+    gbp_mlp_train_workspace_bytes(n_batch, &need);
+    if (workspace_bytes < need) {
+        g_err = "gbp_mlp_train_step: workspace too small (" + std::to_string(need) + " bytes needed)";
+        return GBP_EINVAL;
+    }
+    const int nb = mlp_partial_blocks(n_batch);
+    float *part_grad = (float *)workspace;
+    float *part_loss = part_grad + (size_t)nb * MLP_NPARAMS;
+    launch_mlp_train_step(x, y, mask, n_rows, batch_idx, n_batch, theta, adam_m, adam_v, grad_out, part_grad,
+                          part_loss, loss_out, weights_bf16, lr, step, step > 0, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { g_err = std::string("gbp_mlp_train_step: ") + hipGetErrorString(e); return GBP_EDEVICE; }
+    return GBP_OK;
 }
 
 gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping, double huber_k, double *ms_out) {
@@ -1026,7 +1226,7 @@ gbp_status gbp_sizes(const gbp_problem *p, int32_t *nk, int32_t *nl, int32_t *nf
 }
 
 const char *gbp_last_error(const gbp_problem *p) {
-    if (!p) return "null problem";
+    if (!p) return g_err.empty() ? "null problem" : g_err.c_str();
     return p->err.c_str();
 }
 
@@ -1035,6 +1235,7 @@ void gbp_destroy(gbp_problem *p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     destroy_graphs(p);
     if (p->d_log) (void)hipFree(p->d_log);
+    if (p->learn_mem) (void)hipFree(p->learn_mem);
     if (p->own_ws && p->ws) (void)hipFree(p->ws);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;

@@ -14,6 +14,9 @@ constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed)
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
 constexpr int RBLK = 1024;  // factors per residual-phase block
+constexpr int NFEAT = 16;   // learned-model features per factor
+constexpr int FHIST = 12;   // floats of per-factor feature history
+constexpr int MSG_W = 16;   // floats per exported factor-message row
 
 // keyframe-side record (TS = float | double), one per factor:
 //   [0..5]  d h / d omega (2x3, row-major)
@@ -55,6 +58,7 @@ struct Dev {
     TS *krec, *lrec, *arec;
     uint8_t *cnt, *flags;
     float *fdamp;                         // per-factor damping (learned model) or null
+    const int *fallback;                  // per problem: 1 = learned damping switched off
     // parameters
     const ProbParams *prob;
     int *t_dev;                           // iteration clock
@@ -96,7 +100,16 @@ template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int
 template <typename TS> void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref,
                                           const uint8_t *mask, double *log_row, hipStream_t s);
 template <typename TS> void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf,
-                                                   void *scratch, hipStream_t s);
+                                                   void *scratch, float *fdamp, float *hist, hipStream_t s);
+template <typename TS> void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist,
+                                            double huber_k, hipStream_t s);
+template <typename TS> void launch_export_messages(const Dev<TS> &d, const int *idx, const int *u2i, int n, float *out,
+                                                   hipStream_t s);
+void launch_fill_f32(float *p, float v, int n, hipStream_t s);
+void launch_gather_rows(const float *src, float *dst, const int *idx, const int *u2i, int nf, int n, int w,
+                        hipStream_t s);
+void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
+                    hipStream_t s);
 void launch_tick(int *t_dev, hipStream_t s);
 
 }  // namespace gbp

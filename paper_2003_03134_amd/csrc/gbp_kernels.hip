@@ -545,7 +545,15 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     }
 
     // damping (Section 5; undamped window of Section 8)
-    const double dd = (c < o.undamped) ? 0.0 : (d.fdamp ? (double)d.fdamp[f] : o.damping);
+    // (per-factor value from the learned model unless its problem fell back;
+    // a negative value means none has been evaluated yet)
+    double dd = o.damping;
+    if (c < o.undamped) {
+        dd = 0.0;
+    } else if (d.fdamp && !d.fallback[d.kf_prob[k]]) {
+        const float fd = d.fdamp[f];
+        if (fd >= 0.f) dd = (double)fd;
+    }
     double oSk_a, oSk_b, oSk_c, ogk0, ogk1, oSm_a, oSm_b, oSm_c, ogm0, ogm1;
     if (o.damp_mode == 1) {
         oSk_a = (1 - dd) * nSk_a + dd * Ska; oSk_b = (1 - dd) * nSk_b + dd * Skb; oSk_c = (1 - dd) * nSk_c + dd * Skc;
@@ -794,6 +802,120 @@ __global__ __launch_bounds__(64) void k_kf_solve(Dev<TS> d, IterOpts o, int read
 #pragma unroll
     for (int i = 0; i < 27; ++i) s[i] = src[i];
     kf_solve<TS>(d, o, k, s, readout);
+}
+
+// --------------------------------------------------------------------------
+// features of the learned damping / depth network (one row of 16 per factor)
+// --------------------------------------------------------------------------
+//
+// 0 residual at the linearisation point / Huber threshold, 1 Huber weight,
+// 2 log(1 + residual / sigma), 3 updates since the last linearisation / 10,
+// 4 log(1 + distance from the linearisation point / beta), 5-6 relative
+// change of the keyframe- and landmark-side message vectors since the last
+// evaluation, 7 relative change of the landmark-side message information,
+// 8 cosine between the last two landmark-side message changes, 9 log(depth /
+// 5 m), 10-11 log degrees of landmark and keyframe, 12 log trace of the
+// landmark covariance / 10, 13 cosine between the last two keyframe-side
+// message changes, 14 iteration / 300, 15 log(1 + predicted pixel shift of
+// the landmark since linearisation). `hist` keeps FHIST values per factor
+// between evaluations: g_k (2), g_m (2), tr S_m, last change of g_m (2),
+// valid flag, last change of g_k (2), pad (2).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *__restrict__ feat,
+                                                  float *__restrict__ hist, double huber_k) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.nf) return;
+    const int k = d.f_kf[f], m = d.f_lm[f];
+    TS kr[KREC], lr[LREC], ar[AREC];
+    load16(d.krec + (size_t)f * KREC, kr);
+    load12(d.lrec + (size_t)f * LREC, lr);
+    load16(d.arec + (size_t)f * AREC, ar);
+    const ProbParams pp = d.prob[d.kf_prob[k]];
+    const double *bk = d.kf_bel + (size_t)k * KBEL, *bm = d.lm_bel + (size_t)m * LBEL;
+    const double M0 = sqrt((double)ar[0] * ar[0] + (double)ar[1] * ar[1]) / pp.sigma;
+    const double N = huber_k / pp.sigma;
+    double dist2 = 0.0;
+    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)ar[2 + i]; dist2 += e * e; }
+    for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)ar[8 + i]; dist2 += e * e; }
+    double ju0 = 0, ju1 = 0;
+    for (int i = 0; i < 3; ++i) {
+        const double e = bm[i] - (double)ar[8 + i];
+        ju0 += (double)lr[i] * e;
+        ju1 += (double)lr[3 + i] * e;
+    }
+    const float gk0 = kr[13], gk1 = kr[14], gm0 = lr[9], gm1 = lr[10], trS = (float)lr[6] + (float)lr[8];
+    float *h = hist + FHIST * (size_t)f;
+    const bool have = h[7] > 0.5f;
+    const float dk0 = gk0 - h[0], dk1 = gk1 - h[1], dm0 = gm0 - h[2], dm1 = gm1 - h[3];
+    const float nk = sqrtf(gk0 * gk0 + gk1 * gk1), nkp = sqrtf(h[0] * h[0] + h[1] * h[1]);
+    const float nm = sqrtf(gm0 * gm0 + gm1 * gm1), nmp = sqrtf(h[2] * h[2] + h[3] * h[3]);
+    const float ndm = sqrtf(dm0 * dm0 + dm1 * dm1), ndmp = sqrtf(h[5] * h[5] + h[6] * h[6]);
+    const float ndk = sqrtf(dk0 * dk0 + dk1 * dk1), ndkp = sqrtf(h[8] * h[8] + h[9] * h[9]);
+    float *x = feat + 16 * (size_t)f;
+    x[0] = N > 0.0 ? (float)fmin(M0 / N, 10.0) : 0.f;
+    x[1] = (float)((double)kr[15] / pp.inv_s2);
+    x[2] = (float)log1p(M0);
+    x[3] = fminf((float)d.cnt[f], 30.f) / 10.f;
+    x[4] = (float)log1p(sqrt(dist2) / sqrt(o.beta2 > 0.0 ? o.beta2 : 1e-4));
+    x[5] = have ? sqrtf(dk0 * dk0 + dk1 * dk1) / (nk + nkp + 1e-6f) : 0.f;
+    x[6] = have ? ndm / (nm + nmp + 1e-6f) : 0.f;
+    x[7] = have ? fabsf(trS - h[4]) / (fabsf(trS) + fabsf(h[4]) + 1e-12f) : 0.f;
+    x[8] = have ? (dm0 * h[5] + dm1 * h[6]) / (ndm * ndmp + 1e-12f) : 0.f;
+    const double a0 = (double)kr[6];
+    x[9] = a0 > 0.0 ? (float)log(pp.fx / a0 / 5.0) : 0.f;
+    x[10] = logf((float)(d.lm_row[m + 1] - d.lm_row[m]));
+    x[11] = logf((float)(d.kf_row[k + 1] - d.kf_row[k]));
+    const double trc = bm[3 + pidx<3>(0, 0)] + bm[3 + pidx<3>(1, 1)] + bm[3 + pidx<3>(2, 2)];
+    x[12] = (float)fmin(fmax(log(trc > 0.0 ? trc : 1e-30), -30.0), 10.0) / 10.f;
+    x[13] = have ? (dk0 * h[8] + dk1 * h[9]) / (ndk * ndkp + 1e-12f) : 0.f;
+    x[14] = fminf((float)d.t_dev[0], 300.f) / 300.f;
+    x[15] = (float)log1p(sqrt(ju0 * ju0 + ju1 * ju1));
+    h[0] = gk0; h[1] = gk1; h[2] = gm0; h[3] = gm1; h[4] = trS;
+    h[5] = have ? dm0 : 0.f; h[6] = have ? dm1 : 0.f; h[7] = 1.f;
+    h[8] = have ? dk0 : 0.f; h[9] = have ? dk1 : 0.f;
+}
+
+__global__ void k_fill_f32(float *p, float v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// dst row i = src row u2i[idx[i]] (width w); an index outside [0, nf) gives a
+// row of NaN
+__global__ void k_gather_rows(const float *__restrict__ src, float *__restrict__ dst, const int *__restrict__ idx,
+                              const int *__restrict__ u2i, int nf, int n, int w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int u = idx[i];
+    if (u < 0 || u >= nf) {
+        for (int c = 0; c < w; ++c) dst[(size_t)i * w + c] = __int_as_float(0x7fc00000);
+        return;
+    }
+    const int j = u2i[u];
+    for (int c = 0; c < w; ++c) dst[(size_t)i * w + c] = src[(size_t)j * w + c];
+}
+
+// per-factor messages and counters: S_k (3), g_k (2), S_m (3), g_m (2),
+// updates since linearisation, flags, J_k a_k (2), J_m a_m (2)
+template <typename TS>
+__global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const int *__restrict__ u2i, int n,
+                                  float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float *o = out + MSG_W * (size_t)i;
+    const int u = idx[i];
+    if (u < 0 || u >= d.nf) {
+        for (int c = 0; c < MSG_W; ++c) o[c] = __int_as_float(0x7fc00000);
+        return;
+    }
+    const int f = u2i[u];
+    const TS *kr = d.krec + (size_t)f * KREC, *lr = d.lrec + (size_t)f * LREC;
+    for (int c = 0; c < 5; ++c) o[c] = (float)kr[10 + c];
+    for (int c = 0; c < 5; ++c) o[5 + c] = (float)lr[6 + c];
+    o[10] = (float)d.cnt[f];
+    o[11] = (float)d.flags[f];
+    const TS *ar = d.arec + (size_t)f * AREC;
+    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[11 + c];
 }
 
 // --------------------------------------------------------------------------
@@ -1054,18 +1176,32 @@ __global__ __launch_bounds__(256) void k_reproj_reduce(const double *part, const
 
 __global__ void k_tick(int *t_dev) { t_dev[0] = t_dev[0] + 1; }
 
+// Fallback monitor of the learned damping, one thread per problem: the
+// problem switches to the plain constant damping for good once its mean
+// reprojection error exceeds (1 + rise) times the best seen so far, or is not
+// finite, or a belief failed.
+__global__ void k_monitor(const double *are_out, int np, double rise, double *best, int *fallback,
+                          const unsigned *status) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const double n = are_out[8 * (size_t)p + 3];
+    const double are = n > 0.0 ? are_out[8 * (size_t)p] / n : 0.0;
+    if (!isfinite(are) || status[0] != 0u || are > (1.0 + rise) * best[p]) fallback[p] = 1;
+    if (are < best[p]) best[p] = are;
+}
+
 // --------------------------------------------------------------------------
 // factor-state permutation (incremental growth keeps factors landmark-sorted)
 // --------------------------------------------------------------------------
 
 template <typename T, int W>
-__global__ __launch_bounds__(256) void k_gather(const T *src, T *dst, const int *perm, int n) {
+__global__ __launch_bounds__(256) void k_gather(const T *src, T *dst, const int *perm, int n, T fresh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int j = perm[i];
     if (j < 0) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) dst[(size_t)i * W + w] = T(0);
+        for (int w = 0; w < W; ++w) dst[(size_t)i * W + w] = fresh;
         return;
     }
 #pragma unroll
@@ -1145,17 +1281,19 @@ void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref, const u
 }
 
 template <typename TS>
-void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scratch, hipStream_t s) {
+void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scratch, float *fdamp, float *hist,
+                            hipStream_t s) {
     // gather every per-factor array through `perm` (new index -> old index,
     // -1 for a fresh slot) via the scratch buffer, then copy back
     const int b = blocks(nf > 0 ? nf : 1, 256);
-    auto run = [&](auto *arr, auto tag, int w) {
-        using T = decltype(tag);
+    auto run = [&](auto *arr, auto fresh, int w) {
+        using T = decltype(fresh);
         T *tmp = (T *)scratch;
         switch (w) {
-            case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
-            case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
-            case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf); break;
+            case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            default: return;
         }
         (void)hipMemcpyAsync(arr, tmp, sizeof(T) * (size_t)w * nf, hipMemcpyDeviceToDevice, s);
     };
@@ -1164,6 +1302,34 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
     run(d.arec, TS(0), AREC);
     run(d.cnt, uint8_t(0), 1);
     run(d.flags, uint8_t(0), 1);
+    if (fdamp) run(fdamp, -1.f, 1);  // fresh factors: constant damping until the next evaluation
+    static_assert(FHIST == 12, "history rows are gathered with the width-12 gather");
+    if (hist) run(hist, 0.f, FHIST);
+}
+
+template <typename TS>
+void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist, double huber_k, hipStream_t s) {
+    if (d.nf > 0) hipLaunchKernelGGL(k_features<TS>, dim3(blocks(d.nf, 256)), dim3(256), 0, s, d, o, feat, hist, huber_k);
+}
+
+template <typename TS>
+void launch_export_messages(const Dev<TS> &d, const int *idx, const int *u2i, int n, float *out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_export_messages<TS>, dim3(blocks(n, 256)), dim3(256), 0, s, d, idx, u2i, n, out);
+}
+
+void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
+                    hipStream_t s) {
+    if (np > 0)
+        hipLaunchKernelGGL(k_monitor, dim3(blocks(np, 256)), dim3(256), 0, s, are_out, np, rise, best, fallback, status);
+}
+
+void launch_fill_f32(float *p, float v, int n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(blocks(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_gather_rows(const float *src, float *dst, const int *idx, const int *u2i, int nf, int n, int w,
+                        hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_rows, dim3(blocks(n, 256)), dim3(256), 0, s, src, dst, idx, u2i, nf, n, w);
 }
 
 void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, t_dev); }
@@ -1179,7 +1345,10 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
     template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
     template void launch_reproj<TS>(const Dev<TS> &, double, const double *, const uint8_t *, double *,            \
                                     hipStream_t);                                                                 \
-    template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, hipStream_t);
+    template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, float *, float *,         \
+                                             hipStream_t);              \
+    template void launch_features<TS>(const Dev<TS> &, const IterOpts &, float *, float *, double, hipStream_t);  \
+    template void launch_export_messages<TS>(const Dev<TS> &, const int *, const int *, int, float *, hipStream_t);
 
 GBP_INSTANTIATE(float)
 GBP_INSTANTIATE(double)

@@ -1,0 +1,304 @@
+// Learned damping / depth network: 16 -> 64 (ReLU) -> 64 (ReLU) -> 2, BF16
+// weights and activations, FP32 accumulation.
+//
+// Heads: damping d = 0.9 sigmoid(o0) (per factor, used by the factor phase
+// in place of the constant damping), log-depth correction
+// delta = 2.5 tanh(o1). Parameter blob (5378 values, BF16 bits for inference,
+// FP32 for training): W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+//
+// Inference (k_mlp_infer) is the only dense contraction on the path: layers 1
+// and 2 run on the matrix cores with v_mfma_f32_32x32x8_bf16 (32 rows per
+// wave, 32-column output tiles); the 64 -> 2 head is a per-lane dot product.
+// Training (k_mlp_train_block, k_mlp_reduce, k_adam) evaluates the same
+// BF16-rounded forward pass per sample and back-propagates in FP32; block
+// partial gradients are summed in block order, so training is deterministic.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gbp_mlp.h"
+
+namespace gbp {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int O_W1 = 0, O_B1 = O_W1 + MLP_H * MLP_IN, O_W2 = O_B1 + MLP_H, O_B2 = O_W2 + MLP_H * MLP_H,
+              O_W3 = O_B2 + MLP_H, O_B3 = O_W3 + MLP_OUT * MLP_H;
+static_assert(O_B3 + MLP_OUT == MLP_NPARAMS, "parameter layout");
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
+
+__device__ __forceinline__ void heads(float o0, float o1, float &d, float &delta) {
+    d = MLP_DMAX / (1.0f + expf(-o0));
+    delta = MLP_CDELTA * tanhf(o1);
+}
+
+// --------------------------------------------------------------------------
+// inference: 4 waves x 32 rows per workgroup
+// --------------------------------------------------------------------------
+
+constexpr int HS = MLP_H + 4;  // padded LDS row (bf16 elements)
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ X, int n,
+                                                   const uint16_t *__restrict__ P, float *__restrict__ out_d,
+                                                   float *__restrict__ out_delta) {
+    __shared__ uint16_t sW1[MLP_H * MLP_IN], sW2[MLP_H * MLP_H], sW3[MLP_OUT * MLP_H];
+    __shared__ float sb1[MLP_H], sb2[MLP_H], sb3[MLP_OUT];
+    __shared__ uint16_t sH1[4][32 * HS], sH2[4][32 * HS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < MLP_H * MLP_IN; i += 256) sW1[i] = P[O_W1 + i];
+    for (int i = tid; i < MLP_H * MLP_H; i += 256) sW2[i] = P[O_W2 + i];
+    for (int i = tid; i < MLP_OUT * MLP_H; i += 256) sW3[i] = P[O_W3 + i];
+    for (int i = tid; i < MLP_H; i += 256) { sb1[i] = bf2f(P[O_B1 + i]); sb2[i] = bf2f(P[O_B2 + i]); }
+    if (tid < MLP_OUT) sb3[tid] = bf2f(P[O_B3 + tid]);
+    __syncthreads();
+    const int row0 = (blockIdx.x * 4 + wave) * 32;
+    const int r = lane & 31, kq = (lane >> 5) * 4;  // operand row / k offset of this lane
+    // layer 1: H1 = relu(X W1^T + b1)
+    {
+        const int xr = row0 + r;
+        bf16x4_t a[2];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a[kk][j] = (short)(xr < n ? f2bf(X[(size_t)xr * MLP_IN + kk * 8 + kq + j]) : 0);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16_t acc = {0};
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                bf16x4_t b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = (short)sW1[(nt * 32 + r) * MLP_IN + kk * 8 + kq + j];
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[kk], b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3), c = nt * 32 + r;
+                const float v = acc[q] + sb1[c];
+                sH1[wave][i * HS + c] = f2bf(v > 0.f ? v : 0.f);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2: H2 = relu(H1 W2^T + b2)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16_t acc = {0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            bf16x4_t a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a[j] = (short)sH1[wave][r * HS + kk * 8 + kq + j];
+                b[j] = (short)sW2[(nt * 32 + r) * MLP_H + kk * 8 + kq + j];
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3), c = nt * 32 + r;
+            const float v = acc[q] + sb2[c];
+            sH2[wave][i * HS + c] = f2bf(v > 0.f ? v : 0.f);
+        }
+    }
+    __syncthreads();
+    // head: lane (r, o) computes output o of row r
+    const int o = lane >> 5;
+    float s = sb3[o];
+#pragma unroll 8
+    for (int k = 0; k < MLP_H; ++k) s += bf2f(sH2[wave][r * HS + k]) * bf2f(sW3[o * MLP_H + k]);
+    const float other = __shfl_xor(s, 32, 64);
+    const int xr = row0 + r;
+    if (xr < n && o == 0) {
+        float d, delta;
+        heads(s, other, d, delta);
+        out_d[xr] = d;
+        if (out_delta) out_delta[xr] = delta;
+    }
+}
+
+// --------------------------------------------------------------------------
+// training
+// --------------------------------------------------------------------------
+
+constexpr int SB = 32;  // samples per training workgroup
+
+// Per workgroup: forward (BF16-rounded weights, inputs and hidden
+// activations, FP32 sums) and back-propagation for SB samples, then the
+// workgroup's partial gradient of every parameter (sum over its samples in
+// sample order) and its partial loss. Loss per sample: m0 (d - y0)^2 +
+// m1 (delta - y1)^2, divided by the batch size. Activations live in LDS; the
+// ReLU derivative is read from the stored activation (positive iff the
+// pre-activation is positive).
+__global__ __launch_bounds__(256) void k_mlp_train_block(const float *__restrict__ X, const float *__restrict__ Y,
+                                                         const float *__restrict__ M, int n_rows,
+                                                         const int *__restrict__ idx, int n_batch, const float *__restrict__ theta,
+                                                         float *__restrict__ part_grad, float *__restrict__ part_loss) {
+    __shared__ float w[MLP_NPARAMS];
+    // rows padded by one word: lane s walks row s, so unpadded rows of 64
+    // floats would put every lane on the same LDS bank
+    __shared__ float sx[SB][MLP_IN + 1], sh1[SB][MLP_H + 1], sh2[SB][MLP_H + 1], sd1[SB][MLP_H + 1],
+        sd2[SB][MLP_H + 1], sdo[SB][2];
+    __shared__ float sl[SB];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < MLP_NPARAMS; i += 256) w[i] = bfround(theta[i]);
+    __syncthreads();
+    const int s = tid;  // one sample per lane of the first wave
+    if (s < SB) {
+        // samples past the batch or with an index outside [0, n_rows) count
+        // as zero-weight samples
+        const int g = blockIdx.x * SB + s;
+        const int src0 = g < n_batch ? idx[g] : -1;
+        const bool live = src0 >= 0 && src0 < n_rows;
+        const int src = live ? src0 : 0;
+        float x[MLP_IN];
+#pragma unroll
+        for (int j = 0; j < MLP_IN; ++j) {
+            x[j] = live ? bfround(X[(size_t)src * MLP_IN + j]) : 0.f;
+            sx[s][j] = x[j];
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            float a = w[O_B1 + i];
+#pragma unroll
+            for (int j = 0; j < MLP_IN; ++j) a += w[O_W1 + i * MLP_IN + j] * x[j];
+            sh1[s][i] = bfround(a > 0.f ? a : 0.f);
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            float a = w[O_B2 + i];
+            for (int j = 0; j < MLP_H; ++j) a += w[O_W2 + i * MLP_H + j] * sh1[s][j];
+            sh2[s][i] = bfround(a > 0.f ? a : 0.f);
+        }
+        float o0 = w[O_B3], o1 = w[O_B3 + 1];
+        for (int j = 0; j < MLP_H; ++j) {
+            o0 += w[O_W3 + j] * sh2[s][j];
+            o1 += w[O_W3 + MLP_H + j] * sh2[s][j];
+        }
+        float d, delta;
+        heads(o0, o1, d, delta);
+        float m0 = 0.f, m1 = 0.f, y0 = 0.f, y1 = 0.f;
+        if (live) {
+            m0 = M[2 * (size_t)src]; m1 = M[2 * (size_t)src + 1];
+            y0 = Y[2 * (size_t)src]; y1 = Y[2 * (size_t)src + 1];
+        }
+        const float r0 = d - y0, r1 = delta - y1;
+        sl[s] = (m0 * r0 * r0 + m1 * r1 * r1) / (float)n_batch;
+        const float sig = d / MLP_DMAX, th = delta / MLP_CDELTA;
+        const float do0 = 2.f * m0 * r0 / (float)n_batch * MLP_DMAX * sig * (1.f - sig);
+        const float do1 = 2.f * m1 * r1 / (float)n_batch * MLP_CDELTA * (1.f - th * th);
+        sdo[s][0] = do0;
+        sdo[s][1] = do1;
+        for (int i = 0; i < MLP_H; ++i) {
+            const float dh = do0 * w[O_W3 + i] + do1 * w[O_W3 + MLP_H + i];
+            sd2[s][i] = sh2[s][i] > 0.f ? dh : 0.f;
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            float dh = 0.f;
+            for (int i = 0; i < MLP_H; ++i) dh += sd2[s][i] * w[O_W2 + i * MLP_H + j];
+            sd1[s][j] = sh1[s][j] > 0.f ? dh : 0.f;
+        }
+    }
+    __syncthreads();
+    float *pg = part_grad + (size_t)blockIdx.x * MLP_NPARAMS;
+    for (int e = tid; e < MLP_NPARAMS; e += 256) {
+        float a = 0.f;
+        if (e < O_B1) {
+            const int i = e / MLP_IN, j = e % MLP_IN;
+            for (int q = 0; q < SB; ++q) a += sd1[q][i] * sx[q][j];
+        } else if (e < O_W2) {
+            const int i = e - O_B1;
+            for (int q = 0; q < SB; ++q) a += sd1[q][i];
+        } else if (e < O_B2) {
+            const int i = (e - O_W2) / MLP_H, j = (e - O_W2) % MLP_H;
+            for (int q = 0; q < SB; ++q) a += sd2[q][i] * sh1[q][j];
+        } else if (e < O_W3) {
+            const int i = e - O_B2;
+            for (int q = 0; q < SB; ++q) a += sd2[q][i];
+        } else if (e < O_B3) {
+            const int i = (e - O_W3) / MLP_H, j = (e - O_W3) % MLP_H;
+            for (int q = 0; q < SB; ++q) a += sdo[q][i] * sh2[q][j];
+        } else {
+            const int i = e - O_B3;
+            for (int q = 0; q < SB; ++q) a += sdo[q][i];
+        }
+        pg[e] = a;
+    }
+    if (tid == 0) {
+        float a = 0.f;
+        for (int q = 0; q < SB; ++q) a += sl[q];
+        part_loss[blockIdx.x] = a;
+    }
+}
+
+// sum of the workgroups' partial gradients (and losses) in workgroup order
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part_grad,
+                                                    const float *__restrict__ part_loss, int nb,
+                                                    float *__restrict__ grad, float *__restrict__ loss) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < MLP_NPARAMS) {
+        float a = 0.f;
+        for (int b = 0; b < nb; ++b) a += part_grad[(size_t)b * MLP_NPARAMS + e];
+        grad[e] = a;
+    }
+    if (e == MLP_NPARAMS) {
+        float a = 0.f;
+        for (int b = 0; b < nb; ++b) a += part_loss[b];
+        loss[0] = a;
+    }
+}
+
+// Adam with bias correction on FP32 master weights; writes the BF16 copy
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ theta, float *__restrict__ m1,
+                                              float *__restrict__ m2, const float *__restrict__ g, float lr,
+                                              float beta1, float beta2, float eps, int step,
+                                              uint16_t *__restrict__ bf16) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= MLP_NPARAMS) return;
+    const float ge = g[e];
+    const float a = beta1 * m1[e] + (1.f - beta1) * ge;
+    const float b = beta2 * m2[e] + (1.f - beta2) * ge * ge;
+    m1[e] = a;
+    m2[e] = b;
+    const float ah = a / (1.f - powf(beta1, (float)step)), bh = b / (1.f - powf(beta2, (float)step));
+    const float t = theta[e] - lr * ah / (sqrtf(bh) + eps);
+    theta[e] = t;
+    bf16[e] = f2bf(t);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ theta, uint16_t *__restrict__ out, int n) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = f2bf(theta[e]);
+}
+
+void launch_mlp_infer(const float *X, int n, const uint16_t *P, float *out_d, float *out_delta, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_mlp_infer, dim3((n + 127) / 128), dim3(256), 0, s, X, n, P, out_d, out_delta);
+}
+
+void launch_mlp_train_step(const float *X, const float *Y, const float *M, int n_rows, const int *idx, int n_batch,
+                           float *theta, float *m1, float *m2, float *grad, float *part_grad, float *part_loss,
+                           float *loss, uint16_t *bf16, float lr, int step, bool update, hipStream_t s) {
+    const int nb = (n_batch + SB - 1) / SB;
+    hipLaunchKernelGGL(k_mlp_train_block, dim3(nb), dim3(256), 0, s, X, Y, M, n_rows, idx, n_batch, (const float *)theta,
+                       part_grad, part_loss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAMS + 256) / 256), dim3(256), 0, s, (const float *)part_grad,
+                       (const float *)part_loss, nb, grad, loss);
+    if (update)
+        hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, s, theta, m1, m2,
+                           (const float *)grad, lr, 0.9f, 0.999f, 1e-8f, step, bf16);
+}
+
+void launch_to_bf16(const float *theta, uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, s, theta, out, MLP_NPARAMS);
+}
+
+int mlp_partial_blocks(int n_batch) { return (n_batch + SB - 1) / SB; }
+
+}  // namespace gbp

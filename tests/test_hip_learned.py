@@ -1,0 +1,422 @@
+"""Learned damping on the GPU, through the C ABI: the BF16 MFMA network
+against the FP64 oracle network (forward with the same BF16 storage
+rounding, gradients, Adam), the exported messages against the oracle's
+messages, the features against their definitions, and the in-loop damping
+model against plain GBP runs that must match it bit for bit."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gbp():
+    import paper_2003_03134_amd as g
+    g.load_library()
+    return g
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _theta(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    th = omlp.init_params(seed) * scale
+    # non-zero biases so that every bias path is exercised
+    p = omlp.unpack(th)
+    for b in ("b1", "b2", "b3"):
+        p[b][:] = rng.normal(0, 0.3, p[b].shape)
+    return omlp.pack(p)
+
+
+# --------------------------------------------------------------------------
+# network
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 31, 128, 1000, 4133])
+def test_mlp_infer_matches_bf16_oracle(gbp, n):
+    """Tolerance: both sides round inputs, weights and hidden activations to
+    BF16; the kernel sums in FP32 in MFMA order, so a hidden activation can
+    land one BF16 step (2^-8 relative) away from the FP64 rounding. Through
+    the 64-wide head that moves d = 0.9 sigmoid(o0) by well under 2e-3 and
+    delta = 2.5 tanh(o1) by under 5e-3; most rows agree to FP32 rounding."""
+    import torch
+    rng = np.random.default_rng(n)
+    theta = _theta(11)
+    x = rng.normal(0, 1.5, (n, 16)).astype(np.float32)
+    w = _dev(omlp.to_bf16_bits(theta).view(np.int16))
+    d, delta = gbp.mlp_infer(w, _dev(x))
+    torch.cuda.synchronize()
+    ref = omlp.forward_bf16(theta, x.astype(np.float64))
+    ed = np.abs(d.cpu().numpy() - ref[:, 0])
+    ee = np.abs(delta.cpu().numpy() - ref[:, 1])
+    print(f"n={n}: max |d err| {ed.max():.2e}, max |delta err| {ee.max():.2e}, median {np.median(ed):.1e}")
+    assert ed.max() < 2e-3 and ee.max() < 5e-3
+    assert np.median(ed) < 1e-5 and np.median(ee) < 1e-4
+    # the heads stay in range
+    assert np.all((d.cpu().numpy() >= 0) & (d.cpu().numpy() <= 0.9))
+
+
+def test_mlp_infer_empty_and_bad_arguments(gbp):
+    import torch
+    w = torch.zeros(gbp.MLP_PARAMS, dtype=torch.int16, device="cuda")
+    d, delta = gbp.mlp_infer(w, torch.zeros((0, 16), dtype=torch.float32, device="cuda"))
+    assert d.numel() == 0 and delta.numel() == 0
+    lib = gbp.load_library()
+    assert lib.gbp_mlp_infer(None, None, 5, None, None, None) == -1
+    assert b"gbp_mlp_infer" in lib.gbp_last_error(None)
+
+
+def _bf16(a):
+    return omlp.bf16_round(np.asarray(a, dtype=np.float32))
+
+
+def _per_tensor(g_gpu, g_ref):
+    out = {}
+    o = 0
+    for name, shp in omlp.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g_gpu[o:o + k], g_ref[o:o + k]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+        out[name] = (rel, cos)
+        o += k
+    return out
+
+
+@pytest.mark.parametrize("n_batch", [1, 77, 512])
+def test_mlp_gradient_matches_oracle(gbp, n_batch):
+    """GPU gradient (BF16-rounded forward, FP32 back-propagation) against the
+    FP64 analytic gradient at the BF16-rounded weights and inputs: within
+    2e-2 relative per tensor and cosine above 0.999."""
+    rng = np.random.default_rng(100 + n_batch)
+    n_rows = 600
+    theta = _theta(12).astype(np.float32)
+    x = rng.normal(0, 1.0, (n_rows, 16)).astype(np.float32)
+    y = np.stack([rng.uniform(0, 0.9, n_rows), rng.normal(0, 0.8, n_rows)], 1).astype(np.float32)
+    m = rng.uniform(0.0, 1.0, (n_rows, 2)).astype(np.float32)
+    idx = rng.integers(0, n_rows, n_batch).astype(np.int32)
+    tr = gbp.MLPTrainer(theta, max_batch=512)
+    tr.set_data(x, y, m)
+    g, loss = tr.gradient(idx)
+    g = g.cpu().numpy().astype(np.float64)
+    th_r = _bf16(theta)
+    xr = _bf16(x[idx])
+    ref = omlp.grad(th_r, xr, y[idx], m[idx])
+    ref_loss = omlp.loss(th_r, xr, y[idx], m[idx])
+    assert abs(loss - ref_loss) <= 2e-2 * ref_loss + 1e-7
+    for name, (rel, cos) in _per_tensor(g, ref).items():
+        assert rel < 2e-2 and cos > 0.999, (name, rel, cos)
+    # master weights untouched by a gradient-only call
+    assert np.array_equal(tr.theta_host(), theta)
+
+
+def test_mlp_out_of_range_batch_rows_count_as_zero_weight(gbp):
+    rng = np.random.default_rng(5)
+    n_rows = 100
+    theta = _theta(13).astype(np.float32)
+    x = rng.normal(size=(n_rows, 16)).astype(np.float32)
+    y = rng.uniform(0, 0.9, (n_rows, 2)).astype(np.float32)
+    m = np.ones((n_rows, 2), np.float32)
+    tr = gbp.MLPTrainer(theta, max_batch=64)
+    tr.set_data(x, y, m)
+    idx = np.array([3, -1, 7, 100, 50, 2 ** 30], dtype=np.int32)
+    g, loss = tr.gradient(idx)
+    # same as the valid rows with the invalid ones given weight 0
+    keep = np.array([3, 0, 7, 0, 50, 0])
+    mm = m[keep].copy()
+    mm[[1, 3, 5]] = 0.0
+    ref = omlp.grad(_bf16(theta), _bf16(x[keep]), y[keep], mm)
+    for name, (rel, cos) in _per_tensor(g.cpu().numpy().astype(np.float64), ref).items():
+        assert rel < 2e-2 and cos > 0.999, name
+
+
+def test_adam_steps_match_oracle_update(gbp):
+    """Two Adam steps: the update applied on the GPU equals the textbook
+    update (oracle) applied to the GPU's own gradient, and the BF16 copy is
+    the rounding of the master weights."""
+    rng = np.random.default_rng(9)
+    n_rows = 256
+    theta = _theta(14).astype(np.float32)
+    x = rng.normal(size=(n_rows, 16)).astype(np.float32)
+    y = rng.uniform(0, 0.9, (n_rows, 2)).astype(np.float32)
+    m = np.ones((n_rows, 2), np.float32)
+    tr = gbp.MLPTrainer(theta, max_batch=256)
+    tr.set_data(x, y, m)
+    th = theta.astype(np.float64)
+    mo, vo = np.zeros_like(th), np.zeros_like(th)
+    for step in (1, 2):
+        idx = rng.integers(0, n_rows, 200).astype(np.int32)
+        g, _ = tr.gradient(idx)
+        g = g.cpu().numpy().astype(np.float64)
+        tr.step(idx, lr=1e-3)
+        th, mo, vo = omlp.adam_step(th, mo, vo, g, step, 1e-3)
+        got = tr.theta_host().astype(np.float64)
+        assert np.abs(got - th).max() < 1e-6 * max(1.0, np.abs(th).max()), step
+        assert np.array_equal(tr.weights_bf16(), omlp.to_bf16_bits(tr.theta_host()))
+
+
+def test_training_fits_a_teacher_network_and_is_deterministic(gbp):
+    import torch
+    rng = np.random.default_rng(21)
+    n = 20000
+    x = rng.normal(size=(n, 16)).astype(np.float32)
+    teacher = _theta(30)
+    y = omlp.forward_bf16(teacher, x.astype(np.float64)).astype(np.float32)
+    m = np.ones((n, 2), np.float32)
+    runs = []
+    for _ in range(2):
+        tr = gbp.MLPTrainer(seed=3, max_batch=1024)
+        tr.set_data(x, y, m)
+        order = np.random.default_rng(4).integers(0, n, (400, 1024)).astype(np.int32)
+        _, l0 = tr.gradient(order[0])
+        for k in range(400):
+            tr.step(order[k], lr=3e-3)
+        torch.cuda.synchronize()
+        _, l1 = tr.gradient(order[0])
+        runs.append((l0, l1, tr.theta_host()))
+    l0, l1, th = runs[0]
+    print(f"teacher fit: loss {l0:.4f} -> {l1:.5f}")
+    assert l1 < 0.1 * l0
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
+# --------------------------------------------------------------------------
+# exported state
+# --------------------------------------------------------------------------
+
+def _num_jacobian(prob, x0, l0, h=1e-6):
+    import oracle
+    def proj(v):
+        return oracle.project(v[:6], v[6:], prob.cam)
+    v0 = np.concatenate([x0, l0])
+    J = np.zeros((2, 9))
+    for i in range(9):
+        e = np.zeros(9)
+        e[i] = h
+        J[:, i] = (proj(v0 + e) - proj(v0 - e)) / (2 * h)
+    return J
+
+
+def test_factor_messages_match_oracle_messages(gbp):
+    """FP64 run under a forced schedule: the exported measurement-space
+    messages, mapped to variable space (J^T S J, J^T (g + S J a)), equal the
+    oracle's messages; the counters equal the oracle's."""
+    import oracle
+    prob = synth.make_config0(seed=0)
+    s = gbp.GBPSolver(prob, precision=gbp.GBP_FP64, anneal=False)
+    o = oracle.Oracle(prob, anneal=False)
+    s.iterate(13, 0.4, 2.0)
+    o.iterate(13, 0.4, 2.0)
+    rows = s.factor_messages(np.arange(prob.n_factors, dtype=np.int32)).cpu().numpy().astype(np.float64)
+    om = o.messages()
+    cnt, _ = o.counters()
+    assert np.array_equal(rows[:, 10], np.minimum(cnt, 255))
+    for f in range(prob.n_factors):
+        _, _, lin, _ = o.factor(f)
+        J = _num_jacobian(prob, lin[:6], lin[6:])
+        k, mm = prob.factor_kf[f], prob.factor_lm[f]
+        for side, (s0, g0, j0, Jv, a, lam, eta) in {
+            "k": (0, 3, 12, J[:, :6], prob.kf_init[k], om["k_lam"][f], om["k_eta"][f]),
+            "m": (5, 8, 14, J[:, 6:], prob.lm_init[mm], om["l_lam"][f], om["l_eta"][f]),
+        }.items():
+            S = np.array([[rows[f, s0], rows[f, s0 + 1]], [rows[f, s0 + 1], rows[f, s0 + 2]]])
+            g = rows[f, g0:g0 + 2]
+            ja = rows[f, j0:j0 + 2]
+            assert np.allclose(ja, Jv @ a, rtol=1e-5, atol=1e-4 * np.abs(Jv @ a).max()), (f, side)
+            L = Jv.T @ S @ Jv
+            e = Jv.T @ (g + S @ ja)
+            assert np.abs(L - lam).max() <= 1e-5 * np.abs(lam).max() + 1e-9, (f, side)
+            assert np.abs(e - eta).max() <= 1e-5 * np.abs(eta).max() + 1e-9, (f, side)
+    # an index outside the graph gives a NaN row, never a fault
+    bad = s.factor_messages(np.array([0, -3, prob.n_factors], dtype=np.int32)).cpu().numpy()
+    assert np.all(np.isfinite(bad[0])) and np.all(np.isnan(bad[1:]))
+    s.close()
+
+
+def test_features_follow_their_definitions(gbp):
+    """Features of every factor against their definitions, evaluated from
+    the oracle's state (FP64 run, forced schedule) and the exported
+    messages of two consecutive evaluations."""
+    import oracle
+    prob = synth.make_config0(seed=1)
+    nf = prob.n_factors
+    s = gbp.GBPSolver(prob, precision=gbp.GBP_FP64, anneal=False)
+    o = oracle.Oracle(prob, anneal=False)
+    idx = np.arange(nf, dtype=np.int32)
+    s.iterate(12, 0.4, 2.0)
+    o.iterate(12, 0.4, 2.0)
+    x1 = s.factor_features(idx).cpu().numpy()
+    r1 = s.factor_messages(idx).cpu().numpy().astype(np.float64)
+    s.iterate(3, 0.4, 2.0)
+    o.iterate(3, 0.4, 2.0)
+    x2 = s.factor_features(idx).cpu().numpy().astype(np.float64)
+    r2 = s.factor_messages(idx).cpu().numpy().astype(np.float64)
+    b = o.beliefs()
+    bi = s.beliefs(info=True)
+    assert np.all(x1[:, [5, 6, 7, 8, 13]] == 0)        # no history at the first evaluation
+    sigma, hk = prob.cam.sigma, 2.0
+    kdeg = np.bincount(prob.factor_kf, minlength=prob.n_keyframes)
+    ldeg = np.bincount(prob.factor_lm, minlength=prob.n_landmarks)
+    for f in range(nf):
+        _, _, lin, w = o.factor(f)
+        k, m = prob.factor_kf[f], prob.factor_lm[f]
+        r0 = prob.z[f] - oracle.project(lin[:6], lin[6:], prob.cam)
+        M0 = np.linalg.norm(r0) / sigma
+        ex = {0: min(M0 / (hk / sigma), 10.0), 1: w, 2: np.log1p(M0),
+              3: min(r2[f, 10], 30) / 10.0,
+              4: np.log1p(np.linalg.norm(np.concatenate([b["kf_mu"][k], b["lm_mu"][m]]) - lin) / 0.01),
+              9: np.log(_depth(lin) / 5.0),
+              10: np.log(ldeg[m]), 11: np.log(kdeg[k]),
+              12: np.clip(np.log(np.trace(np.linalg.inv(bi["lm_lam"][m]))), -30.0, 10.0) / 10.0,
+              14: 15 / 300.0,
+              15: np.log1p(np.linalg.norm(_num_jacobian(prob, lin[:6], lin[6:])[:, 6:]
+                                          @ (b["lm_mu"][m] - lin[6:])))}
+        for c, v in ex.items():
+            assert abs(x2[f, c] - v) <= 1e-4 * max(1.0, abs(v)), (f, c, x2[f, c], v)
+        # message-change features from the two exported snapshots
+        dk = r2[f, 3:5] - r1[f, 3:5]
+        dm = r2[f, 8:10] - r1[f, 8:10]
+        nk, nkp = np.linalg.norm(r2[f, 3:5]), np.linalg.norm(r1[f, 3:5])
+        nm, nmp = np.linalg.norm(r2[f, 8:10]), np.linalg.norm(r1[f, 8:10])
+        trS, trSp = r2[f, 5] + r2[f, 7], r1[f, 5] + r1[f, 7]
+        assert abs(x2[f, 5] - np.linalg.norm(dk) / (nk + nkp + 1e-6)) < 1e-4
+        assert abs(x2[f, 6] - np.linalg.norm(dm) / (nm + nmp + 1e-6)) < 1e-4
+        assert abs(x2[f, 7] - abs(trS - trSp) / (abs(trS) + abs(trSp) + 1e-12)) < 1e-4
+    assert np.all(np.isfinite(x2))
+    assert np.all(np.abs(x2[:, [8, 13]]) <= 1.0 + 1e-5)
+    s.close()
+
+
+def _depth(lin):
+    import oracle
+    R = oracle.so3_exp(lin[:3])
+    return float((R @ lin[6:] + lin[3:6])[2])
+
+
+# --------------------------------------------------------------------------
+# damping model inside the iteration
+# --------------------------------------------------------------------------
+
+def _constant_model(gbp, b3_0):
+    """A network whose damping head is the constant 0.9 sigmoid(b3_0) (with
+    b3_0 = 0 the exponential is exact on both sides: d = 0.9f / 2)."""
+    theta = np.zeros(gbp.MLP_PARAMS, np.float32)
+    theta[-2] = b3_0
+    return omlp.to_bf16_bits(theta)
+
+
+def _plain_damping(b3_0):
+    return float(np.float32(0.9) / (np.float32(1.0) + np.exp(np.float32(-b3_0), dtype=np.float32)))
+
+
+@pytest.mark.parametrize("every_k", [1, 5])
+def test_constant_model_equals_plain_run_bitwise(gbp, every_k):
+    prob = synth.make_config1()
+    w = _constant_model(gbp, 0.0)
+    dd = _plain_damping(0.0)
+    a = gbp.GBPSolver(prob)
+    b = gbp.GBPSolver(prob)
+    a.set_damping_model(w, every_k=every_k, fallback_rise=-2.0)
+    for n in (7, 20, 13):
+        a.iterate(n, 0.4, 2.0)
+        b.iterate(n, dd, 2.0)
+    ga, gb = a.beliefs(), b.beliefs()
+    assert np.array_equal(ga["kf_mu"], gb["kf_mu"]) and np.array_equal(ga["lm_mu"], gb["lm_mu"])
+    assert a.fallback_flags().tolist() == [0]
+    # switching the model off restores the constant damping
+    a.set_damping_model(None)
+    a.iterate(10, 0.4, 2.0)
+    b.iterate(10, 0.4, 2.0)
+    assert np.array_equal(a.beliefs()["lm_mu"], b.beliefs()["lm_mu"])
+    a.close()
+    b.close()
+
+
+def test_fallback_switches_to_plain_damping_bitwise(gbp):
+    """fallback_rise = -0.99 makes the monitor switch every problem at its
+    second evaluation (unless the error fell 100-fold in between): the run
+    must then equal model damping for the first every_k iterations and the
+    constant damping afterwards."""
+    probs = [synth.make_config3_problem(p) for p in range(3)]
+    w = _constant_model(gbp, 0.0)
+    dd = _plain_damping(0.0)
+    a = gbp.GBPSolver(probs)
+    b = gbp.GBPSolver(probs)
+    a.set_damping_model(w, every_k=4, fallback_rise=-0.99)
+    a.iterate(4, 0.4, 2.0)
+    b.iterate(4, dd, 2.0)
+    assert a.fallback_flags().tolist() == [0, 0, 0]
+    a.iterate(20, 0.4, 2.0)
+    b.iterate(20, 0.4, 2.0)
+    assert a.fallback_flags().tolist() == [1, 1, 1]
+    ga, gb = a.beliefs(), b.beliefs()
+    assert np.array_equal(ga["kf_mu"], gb["kf_mu"]) and np.array_equal(ga["lm_mu"], gb["lm_mu"])
+    a.close()
+    b.close()
+
+
+def test_learned_growth_keeps_per_factor_state(gbp):
+    """Incremental growth with the model on (constant head) equals plain
+    growth with the same damping: the per-factor damping and history are
+    permuted with the factors."""
+    st = synth.make_incremental_stream(seed=20002, n_kf=9, n0=5, new_lm_per_kf=15)
+    full, base = st.full, st.base
+    cap = (full.n_keyframes, full.n_landmarks, full.n_factors)
+    w = _constant_model(gbp, 0.0)
+    dd = _plain_damping(0.0)
+    a = gbp.GBPSolver(base, capacity=cap)
+    b = gbp.GBPSolver(base, capacity=cap)
+    a.set_damping_model(w, every_k=3, fallback_rise=-2.0)
+    nb = base.n_landmarks
+    step_lms = [s_["lm"] for s_ in st.steps]
+    base_ids = sorted(set(range(full.n_landmarks)) - set(np.concatenate(step_lms)))
+    user_of = {int(j): i for i, j in enumerate(base_ids)}
+    n_lm = nb
+    for step in st.steps:
+        a.iterate(20, 0.4, 2.0)
+        b.iterate(20, dd, 2.0)
+        pose = a.beliefs()["kf_mu"][step["kf"] - 1].copy()
+        for j in step["lm"]:
+            user_of[int(j)] = n_lm
+            n_lm += 1
+        fs = step["factors"]
+        flm = np.array([user_of[int(j)] for j in full.factor_lm[fs]], dtype=np.int32)
+        for s_ in (a, b):
+            s_.add_keyframe(pose, full.lm_init[step["lm"]], full.factor_kf[fs], flm, full.z[fs])
+    a.iterate(15, 0.4, 2.0)
+    b.iterate(15, dd, 2.0)
+    ga, gb = a.beliefs(), b.beliefs()
+    assert np.array_equal(ga["kf_mu"], gb["kf_mu"]) and np.array_equal(ga["lm_mu"], gb["lm_mu"])
+    # features are available for every factor after growth
+    x = a.factor_features(np.arange(full.n_factors, dtype=np.int32)).cpu().numpy()
+    assert np.all(np.isfinite(x))
+    a.close()
+    b.close()
+
+
+def test_data_generation_and_training_pipeline(gbp):
+    """The training pipeline end to end on a small run: labels in range,
+    a useful share of samples labelled, validation loss decreasing."""
+    from paper_2003_03134_amd import learned
+    probs = [synth.make_config1(10000), synth.make_config1(10001)]
+    X, Y, M = learned.generate(probs, iters=60, every=5, frac=0.05, seed=0, log=lambda *_: None)
+    nf = sum(p.n_factors for p in probs)
+    assert X.shape[1] == 16 and Y.shape == M.shape == (X.shape[0], 2)
+    assert X.shape[0] > 0.9 * 12 * int(0.05 * nf)
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(Y))
+    lab = M[:, 0] > 0
+    assert 0.05 < lab.mean() <= 1.0
+    assert np.all((Y[lab, 0] >= 0) & (Y[lab, 0] <= 0.9))
+    assert np.all(np.abs(Y[:, 1]) <= 2.5)
+    theta, rep = learned.train(X, Y, M, epochs=2, batch=1024, lr=2e-3, log=lambda *_: None)
+    assert rep["val_loss"][-1] < rep["val_loss"][0]
+    assert theta.shape == (gbp.MLP_PARAMS,) and np.all(np.isfinite(theta))

@@ -1,0 +1,93 @@
+"""Pins of the FP64 oracle MLP: analytic gradient vs central finite
+differences on every parameter, head ranges, BF16 rounding vs the format's
+definition."""
+import numpy as np
+
+from oracle import mlp
+
+
+def _data(seed, n=40):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, mlp.N_IN))
+    y = np.stack([rng.uniform(0, 0.9, n), rng.normal(0, 1, n)], axis=1)
+    m = rng.uniform(0.2, 1.0, (n, 2))
+    return x, y, m
+
+
+def test_gradient_matches_central_differences_on_every_parameter():
+    theta = mlp.init_params(1) + np.random.default_rng(2).normal(0, 0.05, mlp.N_PARAMS)
+    x, y, m = _data(3)
+    g = mlp.grad(theta, x, y, m)
+    eps = 1e-6
+    fd = np.zeros_like(theta)
+    for i in range(mlp.N_PARAMS):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd[i] = (mlp.loss(tp, x, y, m) - mlp.loss(tm, x, y, m)) / (2 * eps)
+    scale = np.abs(fd).max()
+    assert np.abs(g - fd).max() < 1e-6 * scale
+    # every tensor has a non-trivial gradient (no dead block in the test)
+    o = 0
+    for name, shp in mlp.SHAPES:
+        n = int(np.prod(shp))
+        assert np.abs(g[o:o + n]).max() > 0, name
+        o += n
+
+
+def test_heads_are_in_range_and_zero_weight_samples_do_not_count():
+    theta = mlp.init_params(4)
+    x, y, m = _data(5)
+    heads, _ = mlp.forward(theta * 50, x)
+    assert np.all(heads[:, 0] >= 0) and np.all(heads[:, 0] <= mlp.D_MAX)
+    assert np.all(np.abs(heads[:, 1]) <= mlp.C_DELTA)
+    m2 = m.copy()
+    m2[:10] = 0.0
+    y2 = y.copy()
+    y2[:10] += 100.0
+    assert abs(mlp.loss(theta, x, y, m2) - mlp.loss(theta, x, y2, m2)) < 1e-12
+
+
+def test_bf16_rounding_definition():
+    # values exactly representable stay; halfway cases round to even
+    assert mlp.bf16_round(1.0) == 1.0
+    one_plus_half_ulp = np.float32(1.0 + 2.0 ** -8)          # halfway between 1 and 1+2^-7
+    assert mlp.bf16_round(one_plus_half_ulp) == 1.0          # ties to even (mantissa 0)
+    v = np.float32(1.0 + 3 * 2.0 ** -8)                      # halfway, odd neighbour below
+    assert mlp.bf16_round(v) == 1.0 + 2 * 2.0 ** -7
+    bits = mlp.to_bf16_bits([1.0, -2.0, 0.15625])
+    assert list(bits) == [0x3F80, 0xC000, 0x3E20]
+    assert np.allclose(mlp.from_bf16_bits(bits), [1.0, -2.0, 0.15625])
+
+
+def test_bf16_forward_reduces_to_fp64_forward_on_representable_values():
+    # parameters in {-1/4, 0, 1/4} and integer inputs keep every activation a
+    # multiple of 1/16 below 16, which bfloat16 holds exactly (8 significant
+    # bits): the emulated forward must then equal the plain one bit for bit
+    rng = np.random.default_rng(7)
+    theta = rng.integers(-1, 2, mlp.N_PARAMS) / 4.0
+    x = rng.integers(-2, 3, (30, mlp.N_IN)).astype(float)
+    _, a = mlp.forward(theta, x)
+    for h in (a["h1"], a["h2"]):
+        assert np.abs(h).max() < 16 and np.all((h * 16) % 1 == 0)
+    assert np.array_equal(mlp.forward_bf16(theta, x), mlp.forward(theta, x)[0])
+    # generic values: the emulation differs from FP64 only by rounding
+    theta = mlp.init_params(3)
+    x = rng.normal(size=(50, mlp.N_IN))
+    diff = np.abs(mlp.forward_bf16(theta, x) - mlp.forward(theta, x)[0])
+    assert 0 < diff.max() < 0.05
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # at step 1 the bias-corrected moments are g and g^2: the update is
+    # -lr * g / (|g| + eps), i.e. -lr * sign(g) for |g| >> eps
+    g = np.array([3.0, -0.5, 1e-3, 0.0])
+    th, m, v = mlp.adam_step(np.zeros(4), np.zeros(4), np.zeros(4), g, 1, 0.01)
+    assert np.allclose(th[:3], -0.01 * np.sign(g[:3]), rtol=1e-4)
+    assert th[3] == 0.0
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    # a constant gradient keeps the step at lr (bias correction exact)
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for k in range(1, 6):
+        th, m, v = mlp.adam_step(th, m, v, np.full(4, 2.0), k, 0.1)
+    assert np.allclose(th, -0.5, rtol=1e-6)
