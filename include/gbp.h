@@ -222,6 +222,14 @@ gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6],
 gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
                                  int32_t every_k, double fallback_rise);
 
+/* Restart: back to the state right after creation (every factor linearised
+ * at the initial estimate, zero messages, beliefs = priors at clock 0, and
+ * the damping model's history and fallback state cleared). Recorded
+ * iteration graphs, the reference, the damping model and the tuning stay,
+ * so a restarted run replays without re-recording. GBP_ESTATE after
+ * gbp_add_keyframe. Synchronises. */
+gbp_status gbp_reset(gbp_problem *p);
+
 /* Per-problem fallback state of the damping model (flags[n_problems]: 1 =
  * switched back to the constant damping). Synchronises. */
 gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags);

@@ -269,16 +269,23 @@ class GBPSolver:
         self._check(self._lib.gbp_set_damping_model(self.h, _ptr(w, C.c_uint16), int(every_k),
                                                      float(fallback_rise)), self.h)
 
+    def reset(self) -> None:
+        """Back to the state right after creation (keeps recorded graphs)."""
+        self._check(self._lib.gbp_reset(self.h), self.h)
+
     def fallback_flags(self) -> np.ndarray:
         out = np.zeros(self.n_problems, dtype=np.int32)
         self._check(self._lib.gbp_fallback_flags(self.h, _ptr(out, C.c_int32)), self.h)
         return out
 
     def _device_rows(self, fn, idx, width):
+        # buffers belong to torch's current stream; the library works on its
+        # own stream and synchronises it before returning, so the current
+        # stream is drained first and the two never overlap on them
         torch = self._torch
-        with torch.cuda.stream(self.stream):
-            di = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32)).to(self.device)
-            out = torch.empty((di.numel(), width), dtype=torch.float32, device=self.device)
+        di = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32)).to(self.device)
+        out = torch.empty((di.numel(), width), dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
         self._check(fn(self.h, C.c_void_p(di.data_ptr()), int(di.numel()), C.c_void_p(out.data_ptr())),
                     self.h)
         return out

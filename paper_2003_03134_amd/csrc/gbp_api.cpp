@@ -92,6 +92,7 @@ struct gbp_problem {
     int *d_fallback = nullptr;     // [np]
     double *d_best = nullptr;      // [np] best mean reprojection error seen
     bool learned = false;
+    bool grown = false;            // gbp_add_keyframe was called
     int every_k = 5;
     double fb_rise = 0.1;
     std::string err;
@@ -772,6 +773,7 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
         p->h_z[2 * (size_t)r] = zz[2 * (size_t)f]; p->h_z[2 * (size_t)r + 1] = zz[2 * (size_t)f + 1];
     }
     p->nk = nk1; p->nl = nl1; p->nf = nf1;
+    p->grown = true;
     p->kf_off = {0, nk1}; p->lm_off = {0, nl1}; p->f_off = {0, nf1};
     for (int j = 0; j < n_new_lm; ++j) p->lm_int2user.push_back(nl0 + j);
     build_csr(p);
@@ -876,6 +878,38 @@ gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double
     p->fb_rise = rise > -1.0 ? rise : HUGE_VAL;
     p->df.fdamp = p->fdamp_buf; p->dd.fdamp = p->fdamp_buf;
     p->df.fallback = p->d_fallback; p->dd.fallback = p->d_fallback;
+    return GBP_OK;
+}
+
+// Back to the state right after creation (initial linearisation, zero
+// messages, beliefs = priors at clock 0); buffers, recorded graphs, the
+// reference and the damping model stay.
+template <typename TS>
+gbp_status reset_impl(gbp_problem *p) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    p->huber_k = p->opt.huber_k;
+    p->iopt.huber_k = p->opt.huber_k;
+    HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
+    HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
+    HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)(p->cap_f + 255) / 256 + 1) * 4, s));
+    HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
+    launch_linearise<TS>(d, 0, p->nf, p->huber_k, nullptr, s);
+    launch_prior_base<TS>(d, 0, 0, s);
+    launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+    if (p->learn_mem) {
+        HIP_TRY(p, hipMemsetAsync(p->d_hist, 0, (size_t)p->cap_f * FHIST * 4, s));
+        HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, (size_t)p->np * 4, s));
+        std::vector<double> inf(p->np, HUGE_VAL);
+        HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), (size_t)p->np * 8, hipMemcpyHostToDevice, s));
+        launch_fill_f32(p->fdamp_buf, -1.f, p->cap_f, s);
+    }
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(s));
+    p->t = 0;
     return GBP_OK;
 }
 
@@ -1114,6 +1148,13 @@ gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_
     if (weights && (every_k < 1 || every_k > 1000 || std::isnan(fallback_rise)))
         return fail(p, GBP_EINVAL, "need 1 <= every_k <= 1000 and a fallback_rise that is not NaN");
     return set_model_impl(p, weights, every_k, fallback_rise);
+}
+
+gbp_status gbp_reset(gbp_problem *p) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (p->grown) return fail(p, GBP_ESTATE, "gbp_reset: the problem has grown since creation");
+    return p->precision == GBP_FP32 ? reset_impl<float>(p) : reset_impl<double>(p);
 }
 
 gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags) {

@@ -15,13 +15,16 @@ h_v = g_v + S_v J_v a_v (gbp_factor_messages), which is damped the same way
 while the factor keeps its linearisation. A training run with constant
 damping d0 therefore recovers the undamped update h_new = (h_1 - d0 h_0) /
 (1 - d0) from two consecutive iterations, and the damping that would have
-put the message closest to its converged value h_T is
+put the message closest to where it is heading, h_T, is
 
     d* = clamp(<h_0 - h_new, h_T - h_new> / |h_0 - h_new|^2, 0, 0.9)
 
-over both ends of the factor (4 numbers). The sample counts only when the
-factor was inside its damped regime, kept its linearisation from the sample
-to the end of the run, and its message still moved. The second head is
+over both ends of the factor (4 numbers). Under the relinearisation rule a
+moving factor is relinearised every few iterations (Section 8), which
+changes the space its messages live in; h_T is therefore the factor's last
+message before its next relinearisation (or the end of the run), at least
+two iterations after the sample. The sample counts only when the factor was
+inside its damped regime and its message still moved. The second head is
 trained on log(converged depth / current depth) of the landmark in the
 keyframe's frame.
 
@@ -38,7 +41,8 @@ import time
 
 import numpy as np
 
-from . import (GBP_FP32, GBPSolver, MLP_FEATURES, MLP_PARAMS, MLPTrainer, bf16_bits)
+from . import (GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA, GBP_FP32, GBPSolver, MLP_FEATURES, MLP_PARAMS,
+               MLPTrainer, bf16_bits)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "damping_mlp.npz")
@@ -84,18 +88,18 @@ def info_vectors(rows: np.ndarray) -> np.ndarray:
     return np.concatenate([side(0, 3, 12), side(5, 8, 14)], axis=1)
 
 
-def damping_labels(m0, m1, mT, d0, t, T, undamped=8):
-    """Best damping d* per sample and its weight (0 = no label)."""
+def damping_labels(m0, m1, mT, d0, horizon, undamped=1, min_horizon=2):
+    """Best damping d* per sample and its weight (0 = no label); mT is the
+    message `horizon` iterations after m0 under the same linearisation."""
     h0, h1, hT = info_vectors(m0), info_vectors(m1), info_vectors(mT)
     hnew = (h1 - d0 * h0) / (1.0 - d0)
     dv = h0 - hnew
     den = np.sum(dv * dv, axis=1)
     num = np.sum(dv * (hT - hnew), axis=1)
-    c0, c1, cT = m0[:, 10], m1[:, 10], mT[:, 10]
-    steps_left = T - (t + 1)
-    valid = (c0 >= undamped) & (c0 < 254) & (c1 == c0 + 1)
-    valid &= (cT == np.minimum(255, c1 + steps_left))
-    valid &= den > (1e-8 * np.sum(h0 * h0, axis=1) + 1e-30)
+    c0, c1 = m0[:, 10], m1[:, 10]
+    valid = (c0 >= undamped) & (c1 == c0 + 1) & (horizon >= min_horizon)
+    # the change must stand clear of FP32 rounding of the exported rows
+    valid &= den > (1e-11 * np.sum(h0 * h0, axis=1) + 1e-30)
     valid &= np.isfinite(num) & np.isfinite(den)
     d = np.where(valid, np.clip(num / np.where(den > 0, den, 1.0), 0.0, D_MAX), 0.0)
     return d.astype(np.float32), valid.astype(np.float32)
@@ -121,12 +125,43 @@ def depths(kf_mean: np.ndarray, lm_mean: np.ndarray, fkf: np.ndarray, flm: np.nd
 # data generation
 # ----------------------------------------------------------------------------
 
+class _Pending:
+    """Factors sampled at one iteration, followed until they relinearise."""
+
+    def __init__(self, t0, idx, x, m0, dep):
+        import torch
+        self.t0, self.idx, self.x, self.dep = t0, idx, x, dep
+        self.m0 = m0
+        self.m1 = None
+        self.last = m0.clone()
+        self.last_t = torch.full((m0.shape[0],), t0, dtype=torch.int32, device=m0.device)
+        self.alive = torch.ones(m0.shape[0], dtype=torch.bool, device=m0.device)
+        self.c0 = m0[:, 10]
+
+    def update(self, t, rows):
+        # same linearisation iff the update counter advanced every iteration
+        # (counters saturate at 255: stop following before that)
+        same = self.alive & (rows[:, 10] == self.c0 + float(t - self.t0)) & (self.c0 + float(t - self.t0) < 255)
+        self.last[same] = rows[same]
+        self.last_t[same] = t
+        self.alive = same
+        if t == self.t0 + 1:
+            self.m1 = rows.clone()
+
+
 def generate(problems, *, iters=300, every=5, frac=0.05, damping=0.4, huber_k=2.0, seed=0,
-             log=print):
+             follow=30, undamped=1, damp_mode=GBP_DAMP_ETA_LAMBDA, log=print):
     """Run plain GBP (FP32, constant damping) on a batch of problems and
     return features X (n, 16), labels Y (n, 2) and weights M (n, 2) of a
-    random `frac` of the factors at every `every`-th iteration."""
-    solver = GBPSolver(problems, precision=GBP_FP32)
+    random `frac` of the factors at every `every`-th iteration; each sample
+    is followed for up to `follow` iterations for its damping label. The
+    generating run damps every update but the relinearising one
+    (undamped=1), so that almost every sampled update reveals its undamped
+    value, and damps information and vector together (both stay
+    interpolations, which keeps the run stable on large graphs; the
+    information vector, and with it h, is damped linearly either way)."""
+    solver = GBPSolver(problems, precision=GBP_FP32, undamped=undamped, damp_mode=damp_mode)
+    done = []
     try:
         nf = int(sum(solver.f_counts))
         kf_off = np.concatenate([[0], np.cumsum(solver.kf_counts)[:-1]])
@@ -134,39 +169,47 @@ def generate(problems, *, iters=300, every=5, frac=0.05, damping=0.4, huber_k=2.
         fkf = np.concatenate([np.asarray(p.factor_kf) + o for p, o in zip(problems, kf_off)])
         flm = np.concatenate([np.asarray(p.factor_lm) + o for p, o in zip(problems, lm_off)])
         rng = np.random.default_rng(seed)
-        recs = []
-        for t in range(0, iters - every + 1, every):
+        pending = []
+        for t in range(iters + 1):
             assert solver.t == t
-            idx = np.sort(rng.choice(nf, size=max(1, int(frac * nf)), replace=False)).astype(np.int32)
-            x = solver.factor_features(idx).cpu().numpy()
-            m0 = solver.factor_messages(idx).cpu().numpy()
-            b = solver.beliefs()
-            dep = depths(b["kf_mu"], b["lm_mu"], fkf[idx], flm[idx])
-            solver.iterate(1, damping, huber_k)
-            m1 = solver.factor_messages(idx).cpu().numpy()
-            solver.iterate(every - 1, damping, huber_k)
-            recs.append((t, idx, x, m0, m1, dep))
-        if solver.t < iters:
-            solver.iterate(iters - solver.t, damping, huber_k)
-        T = solver.t
-        mT = solver.factor_messages(np.arange(nf, dtype=np.int32)).cpu().numpy()
+            keep = []
+            for P in pending:
+                P.update(t, solver.factor_messages(P.idx))
+                if t - P.t0 >= follow or t == iters:
+                    done.append(P)
+                else:
+                    keep.append(P)
+            pending = keep
+            if t % every == 0 and t + 1 < iters:
+                idx = np.sort(rng.choice(nf, size=max(1, int(frac * nf)), replace=False)).astype(np.int32)
+                x = solver.factor_features(idx).cpu().numpy()
+                m0 = solver.factor_messages(idx)
+                b = solver.beliefs()
+                pending.append(_Pending(t, idx, x, m0, depths(b["kf_mu"], b["lm_mu"], fkf[idx], flm[idx])))
+            if t < iters:
+                solver.iterate(1, damping, huber_k)
         b = solver.beliefs()
         depT_all = depths(b["kf_mu"], b["lm_mu"], fkf, flm)
     finally:
         solver.close()
     X, Y, M = [], [], []
-    for t, idx, x, m0, m1, dep in recs:
-        d, wd = damping_labels(m0, m1, mT[idx], damping, t, T)
-        dT = depT_all[idx]
+    for P in done:
+        m0, m1, mT = P.m0.cpu().numpy(), P.m1.cpu().numpy(), P.last.cpu().numpy()
+        horizon = P.last_t.cpu().numpy() - P.t0
+        d, wd = damping_labels(m0, m1, mT, damping, horizon, undamped=undamped)
+        dep, dT = P.dep, depT_all[P.idx]
         ok = (dep > 0.05) & (dT > 0.05) & np.isfinite(dep) & np.isfinite(dT)
         delta = np.where(ok, np.clip(np.log(np.where(ok, dT, 1.0) / np.where(ok, dep, 1.0)), -C_DELTA, C_DELTA), 0.0)
-        good = np.all(np.isfinite(x), axis=1)
-        X.append(x[good])
+        good = np.all(np.isfinite(P.x), axis=1)
+        X.append(P.x[good])
         Y.append(np.stack([d, delta], axis=1)[good].astype(np.float32))
         M.append(np.stack([wd, ok.astype(np.float32)], axis=1)[good])
     X, Y, M = np.concatenate(X), np.concatenate(Y), np.concatenate(M)
+    lab = M[:, 0] > 0
     log(f"[learned] {len(problems)} problems, {nf} factors, {X.shape[0]} samples, "
-        f"damping labels {int(M[:, 0].sum())} (mean d* {Y[M[:, 0] > 0, 0].mean():.3f})")
+        f"damping labels {int(lab.sum())} (mean d* {Y[lab, 0].mean() if lab.any() else float('nan'):.3f}, "
+        f"share at 0: {np.mean(Y[lab, 0] == 0.0) if lab.any() else float('nan'):.3f}, "
+        f"at 0.9: {np.mean(Y[lab, 0] == D_MAX) if lab.any() else float('nan'):.3f})")
     return X, Y, M
 
 
@@ -235,6 +278,59 @@ def train(X, Y, M, *, epochs=6, batch=4096, lr=2e-3, seed=0, val_frac=0.1, log=p
 
 
 # ----------------------------------------------------------------------------
+# evaluation: time to target, plain against learned damping
+# ----------------------------------------------------------------------------
+
+def time_to_target(problem, *, weights=None, every_k=5, damping=0.4, huber_k=2.0, target=1.0,
+                   max_iters=300, fallback_rise=0.5, damp_mode=GBP_DAMP_ETA):
+    """Plain (weights None) or learned GBP on one problem (FP32): the first
+    iteration at which the mean error of inliers against their noise-free
+    projections is <= target px, and the GPU wall time to get there. The
+    run is made twice: the first records the iteration graph, the second
+    (after gbp_reset) is timed as one replay with the error logged on the
+    device every iteration; the time to target is the timed run's per
+    iteration time (model evaluations included) times the iterations."""
+    import torch
+    s = GBPSolver(problem, precision=GBP_FP32, damp_mode=damp_mode)
+    try:
+        s.set_reference(problem.z_true, problem.inlier)
+        if weights is not None:
+            s.set_damping_model(weights, every_k=every_k, fallback_rise=fallback_rise)
+        s.iterate_logged(max_iters, damping, huber_k, log_every=1)
+        s.reset()
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        log = s.iterate_logged(max_iters, damping, huber_k, log_every=1)
+        wall = time.perf_counter() - t0
+        fb = int(s.fallback_flags()[0])
+    finally:
+        s.close()
+    are_ref, are_all = log[:, 0, 2], log[:, 0, 1]
+    hit = np.nonzero(are_ref <= target)[0]
+    it = int(hit[0]) + 1 if hit.size else None
+    marks = [i for i in (1, 2, 5, 10, 20, 50, 100, 200, 300, 400, 600) if i <= max_iters]
+    return dict(iterations=it, ms=(wall * 1e3 * it / max_iters) if it else None,
+                ms_per_iter=wall * 1e3 / max_iters, final_are_ref=float(are_ref[-1]),
+                final_are_all=float(are_all[-1]), fallback=fb, max_iters=max_iters,
+                damping=damping, damp_mode=int(damp_mode), are_ref_at={i: round(float(are_ref[i - 1]), 4) for i in marks})
+
+
+def compare(problem, weights, *, undamped_too=False, **kw) -> dict:
+    plain = time_to_target(problem, weights=None, **kw)
+    learned = time_to_target(problem, weights=weights, **kw)
+    sp = (plain["ms"] / learned["ms"]) if plain["ms"] and learned["ms"] else None
+    out = dict(plain=plain, learned=learned, speedup=sp)
+    if undamped_too:
+        out["plain_undamped"] = time_to_target(problem, weights=None, **dict(kw, damping=0.0))
+        out["plain_damp_both"] = time_to_target(problem, weights=None,
+                                                **dict(kw, damp_mode=GBP_DAMP_ETA_LAMBDA))
+        out["learned_damp_both"] = time_to_target(problem, weights=weights,
+                                                  **dict(kw, damp_mode=GBP_DAMP_ETA_LAMBDA))
+    return out
+
+
+# ----------------------------------------------------------------------------
 # command line
 # ----------------------------------------------------------------------------
 
@@ -244,19 +340,41 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--problems", type=int, default=128)
     ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--large", type=int, default=0, help="1000-keyframe problems added to the data")
+    ap.add_argument("--mixed", type=int, default=0, help="uneven batched problems added to the data")
     ap.add_argument("--seed0", type=int, default=10000)
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--every", type=int, default=5)
     ap.add_argument("--frac", type=float, default=0.05)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--eval", action="store_true", help="compare plain and learned damping instead")
+    ap.add_argument("--eval-seeds", default="1,2,3,4")
+    ap.add_argument("--eval-large", action="store_true", help="also the 1000-keyframe problem")
     a = ap.parse_args(argv)
+    if a.eval:
+        w, _, _ = load_weights(a.out)
+        out = {}
+        for sd in [int(v) for v in a.eval_seeds.split(",")]:
+            out[f"random_walk_125kf_seed{sd}"] = compare(synth.make_config1(sd), w, undamped_too=True)
+            print(json.dumps({f"seed{sd}": out[f"random_walk_125kf_seed{sd}"]}), flush=True)
+        if a.eval_large:
+            out["random_walk_1000kf"] = compare(synth.make_config2(), w, max_iters=400, undamped_too=True)
+            print(json.dumps({"large": out["random_walk_1000kf"]}), flush=True)
+        return
     t0 = time.perf_counter()
     parts = []
     for b0 in range(0, a.problems, a.batch_problems):
         seeds = range(a.seed0 + b0, a.seed0 + min(a.problems, b0 + a.batch_problems))
         probs = [synth.make_config1(s) for s in seeds]
         parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=b0))
+    for i in range(a.large):
+        parts.append(generate([synth.make_config2(a.seed0 + 5000 + i)], iters=a.iters, every=a.every,
+                              frac=a.frac, seed=5000 + i))
+    for b0 in range(0, a.mixed, a.batch_problems):
+        probs = [synth.make_config3_problem(p, base_seed=a.seed0 + 7000)
+                 for p in range(b0, min(a.mixed, b0 + a.batch_problems))]
+        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=7000 + b0))
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
     M = np.concatenate([p[2] for p in parts])
@@ -264,6 +382,7 @@ def main(argv=None):
     theta, rep = train(X, Y, M, epochs=a.epochs, lr=a.lr)
     meta = dict(problems=a.problems, seeds=[a.seed0, a.seed0 + a.problems - 1], iters=a.iters,
                 every=a.every, frac=a.frac, damping=0.4, generator="125 keyframes / 1919 landmarks random walk",
+                large_problems=a.large, mixed_problems=a.mixed,
                 label_mean_damping=float(Y[M[:, 0] > 0, 0].mean()), data_seconds=t_gen, **rep)
     save_weights(a.out, theta, meta)
     print(json.dumps(meta))

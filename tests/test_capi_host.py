@@ -89,3 +89,16 @@ def test_workspace_size_scales_with_factors(capi):
     g2, _, k2 = _graph(capi, np.zeros(10000), np.zeros(10000))
     assert lib.gbp_workspace_bytes(1, C.byref(g2), None, C.byref(n)) == 0
     assert n.value > small + 10000 * 150
+
+
+def test_packaged_damping_weights_load():
+    """The shipped network file: BF16 copy is the rounding of the FP32
+    master weights, every value finite, metadata present."""
+    import numpy as np
+    from paper_2003_03134_amd import learned
+    bf16, theta, meta = learned.load_weights()
+    u = theta.view(np.uint32).astype(np.uint64)
+    expect = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+    assert np.array_equal(bf16, expect)
+    assert np.all(np.isfinite(theta))
+    assert meta["samples"] > 0 and meta["val_loss"][-1] < meta["val_loss"][0]

@@ -340,3 +340,40 @@ def test_growth_beyond_capacity_is_rejected(gbp):
         s.add_keyframe(prob.kf_init[1], np.zeros((1, 3)), [5], [prob.n_landmarks], [[300.0, 200.0]])
     assert "capacity" in str(e.value)
     s.close()
+
+
+def test_reset_replays_the_same_run(gbp):
+    """gbp_reset returns to the state after creation: a restarted run (which
+    replays the recorded graphs) equals a fresh solver's run bit for bit;
+    grown problems refuse it."""
+    prob = synth.make_config1()
+    a = gbp.GBPSolver(prob)
+    b = gbp.GBPSolver(prob)
+    a.iterate(25, 0.4, 2.0)
+    a.relinearise(-1)
+    a.iterate(25, 0.3, 1.0)
+    a.reset()
+    assert a.t == 0
+    for s in (a, b):
+        s.iterate(25, 0.4, 2.0)
+        s.iterate(17, 0.4, 2.0)
+    ga, gb = a.beliefs(info=True), b.beliefs(info=True)
+    for key in ga:
+        assert np.array_equal(ga[key], gb[key]), key
+    assert a.reproj()["are_all"] == b.reproj()["are_all"]
+    a.close()
+    b.close()
+    st = synth.make_incremental_stream(seed=20003, n_kf=7, n0=5, new_lm_per_kf=15)
+    cap = (st.full.n_keyframes, st.full.n_landmarks, st.full.n_factors)
+    c = gbp.GBPSolver(st.base, capacity=cap)
+    step = st.steps[0]
+    nb = st.base.n_landmarks
+    flm_map = {int(j): nb + i for i, j in enumerate(step["lm"])}
+    base_ids = sorted(set(range(st.full.n_landmarks)) - set(np.concatenate([s_["lm"] for s_ in st.steps])))
+    flm_map.update({int(j): i for i, j in enumerate(base_ids)})
+    fs = step["factors"]
+    c.add_keyframe(st.full.kf_init[step["kf"]], st.full.lm_init[step["lm"]], st.full.factor_kf[fs],
+                   np.array([flm_map[int(j)] for j in st.full.factor_lm[fs]], dtype=np.int32), st.full.z[fs])
+    with pytest.raises(gbp.GBPError):
+        c.reset()
+    c.close()
