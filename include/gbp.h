@@ -302,8 +302,10 @@ gbp_status gbp_mlp_train_step(const float *x, const float *y, const float *mask,
  * bracketed by HIP events on the problem's stream, then writes the average
  * milliseconds per launch of {relinearisation check, relinearisation of the
  * due factors, factor messages + keyframe beliefs, landmark beliefs,
- * reprojection statistics} to ms_out[5]. The iterations are real: the state
- * advances by n. Synchronises. */
+ * reprojection statistics} to ms_out[0..4], and to ms_out[5] the average
+ * duration of the keyframe factor kernel alone (events recorded by the
+ * driver at the kernel's start and end). The iterations are real: the
+ * state advances by n. Synchronises. */
 gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping,
                            double huber_k, double *ms_out);
 

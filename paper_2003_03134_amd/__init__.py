@@ -192,10 +192,11 @@ class GBPSolver:
         """Average ms per launch of each phase over n real iterations."""
         if huber_k is not None:
             self.huber_k = huber_k
-        ms = np.zeros(5)
+        ms = np.zeros(6)
         self._check(self._lib.gbp_phase_times(self.h, int(n), float(damping), float(self.huber_k),
                                               _ptr(ms, C.c_double)), self.h)
-        return dict(check=ms[0], relin=ms[1], factor_kf=ms[2], belief_lm=ms[3], reproj=ms[4])
+        return dict(check=ms[0], relin=ms[1], factor_kf=ms[2], belief_lm=ms[3], reproj=ms[4],
+                    k_factor_kf=ms[5])
 
     def autotune(self, n_iters: int = 5, cache_path: str | None = None) -> tuple:
         """Pick workgroup sizes by timing (state restored); returns (kf, lm)."""

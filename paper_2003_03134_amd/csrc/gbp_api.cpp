@@ -552,15 +552,16 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
     // all events are recorded back to back on the stream and read after one
     // synchronisation, so queue-empty launch latency is not counted
     constexpr int NPH = 5;
-    std::vector<hipEvent_t> ev(NPH * (size_t)n + 1);
+    std::vector<hipEvent_t> ev(NPH * (size_t)n + 1), kev(2 * (size_t)n);
     for (auto &e : ev) HIP_TRY(p, hipEventCreate(&e));
+    for (auto &e : kev) HIP_TRY(p, hipEventCreate(&e));
     HIP_TRY(p, hipEventRecord(ev[0], s));
     for (int i = 0; i < n; ++i) {
         launch_check<TS>(d, p->iopt, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 1], s));
         launch_relin<TS>(d, p->iopt, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 2], s));
-        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, kev[2 * i], kev[2 * i + 1]);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 3], s));
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 4], s));
@@ -570,15 +571,20 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
     }
     HIP_TRY(p, hipGetLastError());
     HIP_TRY(p, hipEventSynchronize(ev.back()));
-    double acc[NPH] = {0, 0, 0, 0, 0};
-    for (int i = 0; i < n; ++i)
+    double acc[NPH + 1] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
         for (int q = 0; q < NPH; ++q) {
             float t = 0.f;
             HIP_TRY(p, hipEventElapsedTime(&t, ev[NPH * i + q], ev[NPH * i + q + 1]));
             acc[q] += t;
         }
+        float t = 0.f;
+        HIP_TRY(p, hipEventElapsedTime(&t, kev[2 * i], kev[2 * i + 1]));
+        acc[NPH] += t;
+    }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    for (int q = 0; q < NPH; ++q) ms[q] = acc[q] / n;
+    for (auto &e : kev) (void)hipEventDestroy(e);
+    for (int q = 0; q <= NPH; ++q) ms[q] = acc[q] / n;
     p->t += n;
     return GBP_OK;
 }

@@ -93,7 +93,8 @@ template <typename TS> void launch_prior_base(const Dev<TS> &d, int k0, int m0, 
 template <typename TS> void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
 template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s);
-template <typename TS> void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s);
+template <typename TS> void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s,
+                                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s);

@@ -40,6 +40,8 @@
 
 #include "gbp_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 namespace gbp {
@@ -1226,13 +1228,22 @@ void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
     if (d.nl > m0) hipLaunchKernelGGL(k_prior_lm<TS>, dim3(blocks(d.nl - m0, 256)), dim3(256), 0, s, d, m0);
 }
 
+// With events, the keyframe kernel is launched through the driver's
+// extension that records ev0 / ev1 at the kernel's own start and end.
 template <typename TS, int MODE>
-static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s) {
+static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const dim3 g(d.nk);
+    auto go = [&](auto kern, int bs) {
+        if (ev0)
+            hipExtLaunchKernelGGL(kern, g, dim3(bs), 0, s, ev0, ev1, 0, d, o);
+        else
+            hipLaunchKernelGGL(kern, g, dim3(bs), 0, s, d, o);
+    };
     switch (block) {
-        case 64: hipLaunchKernelGGL((k_factor_kf<TS, 64, MODE>), g, dim3(64), 0, s, d, o); break;
-        case 256: hipLaunchKernelGGL((k_factor_kf<TS, 256, MODE>), g, dim3(256), 0, s, d, o); break;
-        default: hipLaunchKernelGGL((k_factor_kf<TS, 128, MODE>), g, dim3(128), 0, s, d, o); break;
+        case 64: go(k_factor_kf<TS, 64, MODE>, 64); break;
+        case 256: go(k_factor_kf<TS, 256, MODE>, 256); break;
+        default: go(k_factor_kf<TS, 128, MODE>, 128); break;
     }
     hipLaunchKernelGGL(k_kf_solve<TS>, dim3(blocks(d.nk, 64)), dim3(64), 0, s, d, o, readout);
 }
@@ -1252,8 +1263,9 @@ void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipS
 }
 
 template <typename TS>
-void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s) {
-    launch_kf<TS, 0>(d, o, block, 0, s);
+void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
+    launch_kf<TS, 0>(d, o, block, 0, s, ev0, ev1);
 }
 
 template <typename TS>
@@ -1339,7 +1351,8 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
     template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
     template void launch_check<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
     template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
-    template void launch_factor_kf<TS>(const Dev<TS> &, const IterOpts &, int, hipStream_t);                       \
+    template void launch_factor_kf<TS>(const Dev<TS> &, const IterOpts &, int, hipStream_t, hipEvent_t,            \
+                                       hipEvent_t);                                                              \
     template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_belief_kf<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
