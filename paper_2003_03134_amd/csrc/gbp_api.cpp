@@ -142,6 +142,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.f_kf, F * 4);
     L.add((void **)&d.f_lm, F * 4);
     L.add((void **)&d.kf_row, (K + 1) * 4);
+    L.add((void **)&d.kf_order, 8 * K * 4 + 4);  // at most 8 slots per keyframe (runs of unequal length)
     L.add((void **)&d.lm_edge, F * 4);
     L.add((void **)&d.lm_row, (M + 1) * 4);
     L.add((void **)&d.f_row_prob, (P + 1) * 4);
@@ -314,6 +315,42 @@ void build_csr(gbp_problem *p) {
     }
 }
 
+// Workgroup order of the keyframe kernel. Workgroups are dispatched
+// round-robin over the eight XCDs, so slot b runs on XCD b % 8. The
+// keyframes, in index order (problems concatenated), are cut into eight
+// contiguous runs of about equal work (factor chunks of the workgroup size),
+// one per XCD, which keeps keyframes that share landmarks in one L2; within
+// a run the largest keyframes go first, so the long workgroups start early.
+// Slots past the end of a shorter run hold -1 (the workgroup exits).
+std::vector<int> kf_order(const gbp_problem *p) {
+    constexpr int NX = 8;
+    const int nk = p->nk;
+    std::vector<double> w(nk);
+    double total = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        const int n = p->h_kf_row[k + 1] - p->h_kf_row[k];
+        w[k] = (double)((n + 63) / 64) + 0.25;  // chunks plus a per-workgroup cost
+        total += w[k];
+    }
+    std::vector<std::vector<int>> run(NX);
+    double acc = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        int x = (int)(acc * NX / (total > 0.0 ? total : 1.0));
+        if (x >= NX) x = NX - 1;
+        run[x].push_back(k);
+        acc += w[k];
+    }
+    size_t len = 0;
+    for (auto &r : run) {
+        std::stable_sort(r.begin(), r.end(), [&](int a, int b) { return w[a] > w[b]; });
+        len = std::max(len, r.size());
+    }
+    std::vector<int> order(len * NX, -1);
+    for (int x = 0; x < NX; ++x)
+        for (size_t i = 0; i < run[x].size(); ++i) order[i * NX + x] = run[x][i];
+    return order;
+}
+
 void destroy_graphs(gbp_problem *p) {
     for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
     p->graphs.clear();
@@ -385,6 +422,9 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     UP(d.f_kf, p->h_fkf.data(), (size_t)nf * 4);
     UP(d.f_lm, p->h_flm.data(), (size_t)nf * 4);
     UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk + 1) * 4);
+    const std::vector<int> order = kf_order(p);
+    d.n_kf_slots = (int)order.size();
+    if (!order.empty()) UP(d.kf_order, order.data(), order.size() * 4);
     UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf * 4);
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl + 1) * 4);
     std::vector<int> frp(p->f_off.begin(), p->f_off.end());
@@ -810,6 +850,9 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     UP(d.f_lm, p->h_flm.data(), (size_t)nf1 * 4);
     UP(d.z, p->h_z.data(), (size_t)nf1 * 2 * 8);
     UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk1 + 1) * 4);
+    const std::vector<int> korder = kf_order(p);
+    d.n_kf_slots = (int)korder.size();
+    UP(d.kf_order, korder.data(), korder.size() * 4);
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl1 + 1) * 4);
     UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf1 * 4);
     std::vector<int> frp = {0, nf1};

@@ -13,7 +13,7 @@ constexpr int AREC = 16;  // factor-private record
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
-constexpr int RBLK = 1024;  // factors per residual-phase block
+constexpr int RBLK = 256;   // factors per residual-phase block (one per lane)
 constexpr int NFEAT = 16;   // learned-model features per factor
 constexpr int FHIST = 12;   // floats of per-factor feature history
 constexpr int MSG_W = 16;   // floats per exported factor-message row
@@ -51,6 +51,8 @@ struct Dev {
     // graph
     const int *f_kf, *f_lm;
     const int *kf_row;                    // factors of keyframe k: [kf_row[k], kf_row[k+1])
+    const int *kf_order;                  // keyframe of each keyframe-kernel workgroup (-1: none)
+    int n_kf_slots;                       // workgroups of the keyframe kernel
     const int *lm_row, *lm_edge;          // factors of each landmark (CSR, increasing)
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state

@@ -148,6 +148,14 @@ __device__ __forceinline__ void chol_inverse_solve(const double (&L)[D * (D + 1)
     }
 }
 
+// a wave-uniform double moved into scalar registers
+__device__ __forceinline__ double uniform_f64(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // --------------------------------------------------------------------------
 // XCD-aware work mapping: workgroups are dispatched round-robin over the
 // eight XCDs (each with its own L2); this bijection on [0, n) gives XCD x a
@@ -642,15 +650,17 @@ __global__ __launch_bounds__(256) void k_check(Dev<TS> d, IterOpts o) {
     if (threadIdx.x == 0) d.relin_qcount[blk] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
 }
 
-// queue segment of check-workgroup b: relinearise and send (marks done)
+// queue segment of check-workgroup b: relinearise and send (marks done);
+// one wave per segment, since a segment holds few due factors in steady state
 template <typename TS>
-__global__ __launch_bounds__(256) void k_relin(Dev<TS> d, IterOpts o) {
+__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int n = d.relin_qcount[blk];
-    if ((int)threadIdx.x >= n) return;
-    const int f = d.relin_queue[(size_t)blk * 256 + threadIdx.x];
-    const int k = d.f_kf[f];
-    factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
+    for (int i = threadIdx.x; i < n; i += 64) {
+        const int f = d.relin_queue[(size_t)blk * 256 + i];
+        const int k = d.f_kf[f];
+        factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
+    }
 }
 
 // factors relinearised in the last iteration: sum of the queue segments
@@ -725,7 +735,7 @@ __device__ void kf_solve(const Dev<TS> &d, const IterOpts &o, const int k, const
 // Contribution of one factor's keyframe-side message to the keyframe belief
 // (eqs. (beliefeta), (belieflambda)): J^T S J (21 packed) and J^T g (6).
 template <typename TS>
-__device__ __forceinline__ void kf_contrib(const TS *row, double *c) {
+__device__ __forceinline__ void kf_contrib(const TS *row, TS *c) {
     double J0[6], J1[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) { J0[i] = (double)row[i]; J1[i] = (double)row[6 + i]; }
@@ -736,8 +746,8 @@ __device__ __forceinline__ void kf_contrib(const TS *row, double *c) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
 #pragma unroll
-        for (int j = i; j < 6; ++j) c[pidx<6>(i, j)] = J0[i] * SJ0[j] + J1[i] * SJ1[j];
-        c[21 + i] = J0[i] * g0 + J1[i] * g1;
+        for (int j = i; j < 6; ++j) c[pidx<6>(i, j)] = (TS)(J0[i] * SJ0[j] + J1[i] * SJ1[j]);
+        c[21 + i] = (TS)(J0[i] * g0 + J1[i] * g1);
     }
 }
 
@@ -745,19 +755,29 @@ __device__ __forceinline__ void kf_contrib(const TS *row, double *c) {
 // relinearised this iteration sends its messages, then the keyframe's
 // message sums (information and information vector) are formed; MODE 1:
 // sums only (creation, read-out). k_kf_solve turns the sums into beliefs.
-// Each lane forms its factor's 27 contributions and writes them to a padded
-// LDS row; 27 x G lanes then add interleaved rows column by column and the G
-// partials are added in group order (fixed order, no cross-lane shuffles).
+// Each lane forms its factor's 27 contributions and writes them, rounded to
+// the factor-state precision, to a padded LDS row; 27 x G lanes then add
+// interleaved rows column by column in FP64 and the G partials are added in
+// group order (fixed order, no cross-lane shuffles).
 template <typename TS, int BS, int MODE>
 __global__ __launch_bounds__(BS) void k_factor_kf(Dev<TS> d, IterOpts o) {
     constexpr int G = BS / 32;     // row groups in the column sums
     constexpr int RS = 29;         // padded row stride (doubles) against bank conflicts
-    __shared__ double red[BS * RS];
+    __shared__ TS red[BS * RS];
     __shared__ double part[G][28];
-    const int k = xcd_remap(blockIdx.x, gridDim.x);
+    // slot -> keyframe (per-XCD runs, largest first; -1: no keyframe)
+    const int k = d.kf_order[blockIdx.x];
+    if (k < 0) return;
     const int tid = threadIdx.x;
     const int e0 = d.kf_row[k], e1 = d.kf_row[k + 1];
-    const double *bk = d.kf_bel + (size_t)k * KBEL;
+    // the keyframe's belief is the same for every lane: broadcast it into
+    // scalar registers (loaded per lane, the compiler would keep 54 vector
+    // registers for it, since it cannot rule out that the record stores
+    // alias the belief array)
+    double kb[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) kb[i] = uniform_f64(d.kf_bel[(size_t)k * KBEL + i]);
+    const double *bk = kb;
     const int col = tid % 27, grp = tid / 27;
     double acc = 0.0;
     for (int base = e0; base < e1; base += BS) {
@@ -782,7 +802,7 @@ __global__ __launch_bounds__(BS) void k_factor_kf(Dev<TS> d, IterOpts o) {
         __syncthreads();
         if (grp < G) {
             double s = 0.0;
-            for (int q = grp; q < BS; q += G) s += red[q * RS + col];
+            for (int q = grp; q < BS; q += G) s += (double)red[q * RS + col];
             part[grp][col] = s;
         }
         __syncthreads();
@@ -1112,17 +1132,19 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
 // --------------------------------------------------------------------------
 
 // Per-block partial statistics over the factor range of one block (blocks
-// never straddle problems): {sum_all, sum_quad, sum_ref, n_valid, n_quad,
-// n_lin, n_inv, n_ref}, tree-reduced in a fixed order.
+// never straddle problems; one factor per lane): {sum_all, sum_quad,
+// sum_ref, n_valid, n_quad, n_lin, n_inv, n_ref}, reduced in a fixed order
+// (a butterfly inside each wave, then the four waves in order).
 template <typename TS>
-__global__ __launch_bounds__(256) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
-                                                      const uint8_t *mask) {
+__global__ __launch_bounds__(RBLK) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
+                                                       const uint8_t *mask) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int f0 = d.rblk_start[b], f1 = d.rblk_start[b + 1];
     const ProbParams pp = d.prob[d.rblk_prob[b]];
     const double N = huber_k / pp.sigma;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
+    const int f = f0 + (int)threadIdx.x;
+    if (f < f1) {
         const int k = d.f_kf[f], m = d.f_lm[f];
         const double *ps = d.kf_pose + 12 * (size_t)k;
         double l[3];
@@ -1131,40 +1153,57 @@ __global__ __launch_bounds__(256) void k_reproj_block(Dev<TS> d, double huber_k,
         double p[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) p[i] = ps[3 * i] * l[0] + ps[3 * i + 1] * l[1] + ps[3 * i + 2] * l[2] + ps[9 + i];
-        if (!(p[2] > pp.zmin)) { acc[6] += 1.0; continue; }
-        const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
-        const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
-        acc[0] += e;
-        acc[3] += 1.0;
-        if (N > 0.0 && e / pp.sigma > N) acc[5] += 1.0;
-        else { acc[1] += e; acc[4] += 1.0; }
-        if (zref && mask[f]) {
-            acc[2] += hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
-            acc[7] += 1.0;
+        if (!(p[2] > pp.zmin)) {
+            acc[6] = 1.0;
+        } else {
+            const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
+            const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
+            acc[0] = e;
+            acc[3] = 1.0;
+            if (N > 0.0 && e / pp.sigma > N) acc[5] = 1.0;
+            else { acc[1] = e; acc[4] = 1.0; }
+            if (zref && mask[f]) {
+                acc[2] = hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
+                acc[7] = 1.0;
+            }
         }
     }
-    __shared__ double sh[8][256];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) sh[i][threadIdx.x] = acc[i];
-    __syncthreads();
-    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w)
+    for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + w];
-        __syncthreads();
+        for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    __shared__ double sh[RBLK / 64][8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < 8) {
+        double v = acc[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) v = (lane == i) ? acc[i] : v;
+        sh[wave][lane] = v;
     }
-    if (threadIdx.x < 8) d.rblk_part[8 * (size_t)b + threadIdx.x] = sh[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < RBLK / 64; ++w) s += sh[w][threadIdx.x];
+        d.rblk_part[8 * (size_t)b + threadIdx.x] = s;
+    }
 }
 
-// one thread per problem: sums its blocks' partials in block order
-__global__ __launch_bounds__(256) void k_reproj_reduce(const double *part, const int *prob_blk, int np,
-                                                       double *out, double *log_row, const int *t_dev) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per problem: lane l sums blocks l, l + 64, ... of the problem in
+// order, then a butterfly adds the lanes (a fixed order: deterministic)
+__global__ __launch_bounds__(64) void k_reproj_reduce(const double *part, const int *prob_blk, int np,
+                                                      double *out, double *log_row, const int *t_dev) {
+    const int p = blockIdx.x;
     if (p >= np) return;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = prob_blk[p]; b < prob_blk[p + 1]; ++b)
+    for (int b = prob_blk[p] + (int)threadIdx.x; b < prob_blk[p + 1]; b += 64)
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] += part[8 * (size_t)b + i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (threadIdx.x != 0) return;
     if (out)
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[8 * (size_t)p + i] = acc[i];
@@ -1233,7 +1272,7 @@ void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
 template <typename TS, int MODE>
 static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    const dim3 g(d.nk);
+    const dim3 g(d.n_kf_slots);
     auto go = [&](auto kern, int bs) {
         if (ev0)
             hipExtLaunchKernelGGL(kern, g, dim3(bs), 0, s, ev0, ev1, 0, d, o);
@@ -1255,7 +1294,7 @@ void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
 
 template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
-    hipLaunchKernelGGL(k_relin<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(256), 0, s, d, o);
+    hipLaunchKernelGGL(k_relin<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(64), 0, s, d, o);
 }
 
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
@@ -1287,8 +1326,8 @@ template <typename TS>
 void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref, const uint8_t *mask, double *log_row,
                    hipStream_t s) {
     if (d.n_rblk > 0)
-        hipLaunchKernelGGL(k_reproj_block<TS>, dim3(d.n_rblk), dim3(256), 0, s, d, huber_k, zref, mask);
-    hipLaunchKernelGGL(k_reproj_reduce, dim3(blocks(d.np, 256)), dim3(256), 0, s, (const double *)d.rblk_part,
+        hipLaunchKernelGGL(k_reproj_block<TS>, dim3(d.n_rblk), dim3(RBLK), 0, s, d, huber_k, zref, mask);
+    hipLaunchKernelGGL(k_reproj_reduce, dim3(d.np), dim3(64), 0, s, (const double *)d.rblk_part,
                        d.prob_rblk, d.np, log_row ? (double *)nullptr : d.are_out, log_row, (const int *)d.t_dev);
 }
 
