@@ -185,7 +185,9 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
  * variable sets (new keyframe = old count, new landmarks follow the old
  * ones). New factors are linearised at the current means; new variables get
  * automatic priors from the new factors and their own annealing clock.
- * GBP_ENOMEM when the capacity set at creation is exceeded. */
+ * A reference set with gbp_set_reference is dropped (set it again for the
+ * grown factor set). GBP_ENOMEM when the capacity set at creation is
+ * exceeded. */
 gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6],
                             int32_t n_new_lm, const double *lm_init,
                             int32_t n_new_f, const int32_t *f_kf,
@@ -229,6 +231,21 @@ gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
  * so a restarted run replays without re-recording. GBP_ESTATE after
  * gbp_add_keyframe. Synchronises. */
 gbp_status gbp_reset(gbp_problem *p);
+
+/* Learned initial depth (the second head of the damping model): for each
+ * listed landmark (caller indices, host array; duplicates ignored) the
+ * network is evaluated on every factor, and the landmark is moved along the
+ * ray from the camera centre of its newest observing keyframe to
+ * c + exp(mean log-depth head over its factors) (l - c); its prior mean moves
+ * with it, and every one of its factors is relinearised at the new position
+ * with zero messages (a fresh start for that landmark; GBP is insensitive to
+ * the prior mean, Section 8). Meant for landmarks initialised at a guessed
+ * depth a few iterations after they join (Section 9.2). Also advances the
+ * feature history and rewrites the per-factor damping. GBP_ESTATE without a
+ * model (gbp_set_damping_model), GBP_EINVAL for an index outside
+ * [0, n_landmarks). Synchronises. */
+gbp_status gbp_apply_depth_model(gbp_problem *p, const int32_t *landmarks,
+                                 int32_t n);
 
 /* Per-problem fallback state of the damping model (flags[n_problems]: 1 =
  * switched back to the constant damping). Synchronises. */

@@ -274,6 +274,13 @@ class GBPSolver:
         """Back to the state right after creation (keeps recorded graphs)."""
         self._check(self._lib.gbp_reset(self.h), self.h)
 
+    def apply_depth_model(self, landmarks) -> None:
+        """Move the listed landmarks (caller indices) by the network's
+        log-depth head along their newest keyframe's ray and restart their
+        factors there."""
+        lm = _i32(landmarks).ravel()
+        self._check(self._lib.gbp_apply_depth_model(self.h, _ptr(lm, C.c_int32), int(lm.size)), self.h)
+
     def fallback_flags(self) -> np.ndarray:
         out = np.zeros(self.n_problems, dtype=np.int32)
         self._check(self._lib.gbp_fallback_flags(self.h, _ptr(out, C.c_int32)), self.h)

@@ -57,6 +57,7 @@ struct gbp_problem {
     // host mirrors needed to rebuild the layout on growth
     std::vector<int> h_fkf, h_flm, h_kf_row, h_lm_row, h_lm_edge;
     std::vector<double> h_z, h_kf_anchor, h_lm_anchor;
+    std::vector<double> h_lm_anchor0;  // landmark anchors at creation (the learned depth moves anchors)
     std::vector<int> h_first_obs;  // first observing keyframe of each internal landmark
     // device
     void *ws = nullptr;
@@ -89,6 +90,7 @@ struct gbp_problem {
     float *d_delta = nullptr;      // [cap_f] log-depth head
     uint16_t *d_w = nullptr;       // network weights (BF16 bits)
     int *d_u2i = nullptr;          // caller factor index -> internal slot
+    int *d_lms = nullptr;          // [cap_l] landmark list (learned depth)
     int *d_fallback = nullptr;     // [np]
     double *d_best = nullptr;      // [np] best mean reprojection error seen
     bool learned = false;
@@ -410,6 +412,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     }
     p->h_kf_anchor = kf_anchor;
     p->h_lm_anchor = lm_anchor;
+    p->h_lm_anchor0 = lm_anchor;
 #define UP(dst, src, bytes) HIP_TRY(p, hipMemcpyAsync((void *)(dst), (const void *)(src), (bytes), hipMemcpyHostToDevice, s))
     UP(d.kf_anchor, kf_anchor.data(), kf_anchor.size() * 8);
     UP(d.lm_anchor, lm_anchor.data(), lm_anchor.size() * 8);
@@ -742,6 +745,7 @@ gbp_status ensure_learn_mem(gbp_problem *p) {
     L.add((void **)&p->d_delta, F * 4);
     L.add((void **)&p->d_w, MLP_NPARAMS * 2);
     L.add((void **)&p->d_u2i, F * 4);
+    L.add((void **)&p->d_lms, (size_t)p->cap_l * 4);
     L.add((void **)&p->d_fallback, P * 4);
     L.add((void **)&p->d_best, P * 8);
     void *mem = nullptr;
@@ -820,6 +824,7 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     }
     p->nk = nk1; p->nl = nl1; p->nf = nf1;
     p->grown = true;
+    p->has_ref = false;  // the reference covered the old factor set
     p->kf_off = {0, nk1}; p->lm_off = {0, nl1}; p->f_off = {0, nf1};
     for (int j = 0; j < n_new_lm; ++j) p->lm_int2user.push_back(nl0 + j);
     build_csr(p);
@@ -904,6 +909,35 @@ gbp_status messages_impl(gbp_problem *p, const int32_t *idx, int n, float *out) 
     return GBP_OK;
 }
 
+// Learned depth for the listed (internal) landmarks: a fresh evaluation of
+// the network, the move along the ray, then every factor of a moved
+// landmark relinearised at the new position with zero messages, and the
+// beliefs re-formed.
+template <typename TS>
+gbp_status depth_impl(gbp_problem *p, const std::vector<int> &lms) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    std::vector<int> fl;
+    for (int m : lms)
+        for (int e = p->h_lm_row[m]; e < p->h_lm_row[m + 1]; ++e) fl.push_back(p->h_lm_edge[e]);
+    std::sort(fl.begin(), fl.end());
+    if (!lms.empty())
+        HIP_TRY(p, hipMemcpyAsync(p->d_lms, lms.data(), lms.size() * 4, hipMemcpyHostToDevice, s));
+    if (!fl.empty())
+        HIP_TRY(p, hipMemcpyAsync(p->d_perm, fl.data(), fl.size() * 4, hipMemcpyHostToDevice, s));
+    launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
+    launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
+    launch_depth_move<TS>(d, p->d_lms, (int)lms.size(), p->d_delta, s);
+    launch_linearise<TS>(d, 0, (int)fl.size(), p->huber_k, p->d_perm, s);
+    launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+    HIP_TRY(p, hipGetLastError());
+    // the host mirror of the anchors (absolute means = anchor + offset)
+    HIP_TRY(p, hipMemcpyAsync(p->h_lm_anchor.data(), d.lm_anchor, (size_t)p->nl * 3 * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
 gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double rise) {
     destroy_graphs(p);
     if (!w) {
@@ -939,6 +973,8 @@ gbp_status reset_impl(gbp_problem *p) {
     hipStream_t s = p->stream;
     p->huber_k = p->opt.huber_k;
     p->iopt.huber_k = p->opt.huber_k;
+    p->h_lm_anchor = p->h_lm_anchor0;
+    HIP_TRY(p, hipMemcpyAsync(d.lm_anchor, p->h_lm_anchor.data(), p->h_lm_anchor.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
@@ -1204,6 +1240,23 @@ gbp_status gbp_reset(gbp_problem *p) {
     if (st != GBP_OK) return st;
     if (p->grown) return fail(p, GBP_ESTATE, "gbp_reset: the problem has grown since creation");
     return p->precision == GBP_FP32 ? reset_impl<float>(p) : reset_impl<double>(p);
+}
+
+gbp_status gbp_apply_depth_model(gbp_problem *p, const int32_t *landmarks, int32_t n) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!p->learned) return fail(p, GBP_ESTATE, "gbp_apply_depth_model: set a damping/depth model first");
+    if (n < 0 || (n > 0 && !landmarks)) return fail(p, GBP_EINVAL, "gbp_apply_depth_model: need n >= 0 and landmarks");
+    std::vector<int> u2i(p->nl);
+    for (int i = 0; i < p->nl; ++i) u2i[p->lm_int2user[i]] = i;
+    std::vector<char> seen(p->nl, 0);
+    std::vector<int> lms;
+    for (int i = 0; i < n; ++i) {
+        const int u = landmarks[i];
+        if (u < 0 || u >= p->nl) return fail(p, GBP_EINVAL, "gbp_apply_depth_model: landmark index out of range");
+        if (!seen[u]) { seen[u] = 1; lms.push_back(u2i[u]); }
+    }
+    return p->precision == GBP_FP32 ? depth_impl<float>(p, lms) : depth_impl<double>(p, lms);
 }
 
 gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags) {

@@ -41,7 +41,8 @@ template <typename TS>
 struct Dev {
     int nk, nl, nf, np;
     // variables
-    const double *kf_anchor, *lm_anchor;  // absolute initial estimate (prior mean)
+    const double *kf_anchor;              // absolute initial estimate (prior mean)
+    double *lm_anchor;                    // (moved only by the learned depth)
     double *kf_pbase, *lm_pbase;          // automatic prior information (diag)
     const double *kf_pinfo;               // anchor prior information (0: automatic)
     const int *kf_t0, *lm_t0;             // iteration at which the variable was born
@@ -113,6 +114,8 @@ void launch_gather_rows(const float *src, float *dst, const int *idx, const int 
                         hipStream_t s);
 void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
                     hipStream_t s);
+template <typename TS> void launch_depth_move(const Dev<TS> &d, const int *lms, int n, const float *delta,
+                                              hipStream_t s);
 void launch_tick(int *t_dev, hipStream_t s);
 
 }  // namespace gbp

@@ -1217,6 +1217,34 @@ __global__ __launch_bounds__(64) void k_reproj_reduce(const double *part, const 
 
 __global__ void k_tick(int *t_dev) { t_dev[0] = t_dev[0] + 1; }
 
+// Learned depth: landmark lms[i] moves along the ray from the camera centre
+// of its newest observing keyframe (the keyframe of its last factor, factors
+// being keyframe-major) to c + exp(mean depth head over its factors) (l - c);
+// its prior mean (the anchor) moves with it and its mean offset is cleared.
+template <typename TS>
+__global__ void k_depth_move(Dev<TS> d, const int *__restrict__ lms, int n, const float *__restrict__ delta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = lms[i];
+    const int e0 = d.lm_row[m], e1 = d.lm_row[m + 1];
+    if (e1 <= e0) return;
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) acc += (double)delta[d.lm_edge[e]];
+    const double scale = exp(acc / (double)(e1 - e0));
+    const int k = d.f_kf[d.lm_edge[e1 - 1]];
+    const double *ps = d.kf_pose + 12 * (size_t)k;
+    double c[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c[j] = -(ps[j] * ps[9] + ps[3 + j] * ps[10] + ps[6 + j] * ps[11]);
+    double *bm = d.lm_bel + (size_t)m * LBEL;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double l = d.lm_anchor[3 * (size_t)m + j] + bm[j];
+        d.lm_anchor[3 * (size_t)m + j] = c[j] + scale * (l - c[j]);
+        bm[j] = 0.0;
+    }
+}
+
 // Fallback monitor of the learned damping, one thread per problem: the
 // problem switches to the plain constant damping for good once its mean
 // reprojection error exceeds (1 + rise) times the best seen so far, or is not
@@ -1368,6 +1396,11 @@ void launch_export_messages(const Dev<TS> &d, const int *idx, const int *u2i, in
     if (n > 0) hipLaunchKernelGGL(k_export_messages<TS>, dim3(blocks(n, 256)), dim3(256), 0, s, d, idx, u2i, n, out);
 }
 
+template <typename TS>
+void launch_depth_move(const Dev<TS> &d, const int *lms, int n, const float *delta, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_depth_move<TS>, dim3(blocks(n, 64)), dim3(64), 0, s, d, lms, n, delta);
+}
+
 void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
                     hipStream_t s) {
     if (np > 0)
@@ -1399,6 +1432,7 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
                                     hipStream_t);                                                                 \
     template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, float *, float *,         \
                                              hipStream_t);              \
+    template void launch_depth_move<TS>(const Dev<TS> &, const int *, int, const float *, hipStream_t);            \
     template void launch_features<TS>(const Dev<TS> &, const IterOpts &, float *, float *, double, hipStream_t);  \
     template void launch_export_messages<TS>(const Dev<TS> &, const int *, const int *, int, float *, hipStream_t);
 

@@ -41,8 +41,9 @@ import time
 
 import numpy as np
 
-from . import (GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA, GBP_FP32, GBPSolver, MLP_FEATURES, MLP_PARAMS,
-               MLPTrainer, bf16_bits)
+from . import (GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA, GBP_FP32, GBPError, GBPSolver, MLP_FEATURES,
+               MLP_PARAMS, MLPTrainer, bf16_bits)
+from ._capi import GBP_ENUMERIC
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "damping_mlp.npz")
@@ -316,6 +317,89 @@ def time_to_target(problem, *, weights=None, every_k=5, damping=0.4, huber_k=2.0
                 damping=damping, damp_mode=int(damp_mode), are_ref_at={i: round(float(are_ref[i - 1]), 4) for i in marks})
 
 
+def incremental_run(stream, *, weights=None, use_depth=False, every_k=5, damping=0.4, huber_k=2.0,
+                    iters_per_kf=20, depth_delay=5, target=1.0, fallback_rise=0.5, damp_mode=GBP_DAMP_ETA,
+                    trace=False):
+    """The SLAM protocol of Section 9.2 on an incremental stream: start from
+    the base problem, and for every later keyframe add it (initialised at
+    the previous keyframe's current estimate) with its new landmarks and
+    factors, then run `iters_per_kf` iterations. With `use_depth` the
+    learned depth head moves the new landmarks (and, in the first window,
+    the base problem's) `depth_delay` iterations after they join. Returns per-addition iterations to the inlier target,
+    final errors and the GPU wall time of the whole run (host work for the
+    additions included)."""
+    import torch
+    full, base = stream.full, stream.base
+    cap = (full.n_keyframes, full.n_landmarks, full.n_factors)
+    s = GBPSolver(base, precision=GBP_FP32, capacity=cap, damp_mode=damp_mode)
+    try:
+        if weights is not None:
+            s.set_damping_model(weights, every_k=every_k, fallback_rise=fallback_rise)
+        nb = base.n_landmarks
+        step_lms = [st["lm"] for st in stream.steps]
+        base_ids = sorted(set(range(full.n_landmarks)) - set(np.concatenate(step_lms).tolist()))
+        user_of = {int(j): i for i, j in enumerate(base_ids)}
+        # caller order of the grown factor set: the base factors, then each
+        # step's factors in arrival order
+        base_f = np.flatnonzero(np.isin(full.factor_lm, np.array(base_ids)))
+        forder = [base_f]
+        s.set_reference(full.z_true[base_f], full.inlier[base_f])
+        n_lm = nb
+        to_target, final_ref = [], []
+        diverged_at = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if use_depth and weights is not None:
+            s.iterate(depth_delay, damping, huber_k)
+            s.apply_depth_model(np.arange(nb, dtype=np.int32))
+            s.iterate(iters_per_kf - depth_delay, damping, huber_k)
+        else:
+            s.iterate(iters_per_kf, damping, huber_k)
+        for st in stream.steps:
+            try:
+                pose = s.beliefs()["kf_mu"][st["kf"] - 1].copy()
+            except GBPError as e:
+                if e.status != GBP_ENUMERIC:
+                    raise
+                diverged_at = int(st["kf"])  # a belief lost positive definiteness
+                break
+            new_users = []
+            for j in st["lm"]:
+                user_of[int(j)] = n_lm
+                new_users.append(n_lm)
+                n_lm += 1
+            fs = st["factors"]
+            flm = np.array([user_of[int(j)] for j in full.factor_lm[fs]], dtype=np.int32)
+            s.add_keyframe(pose, full.lm_init[st["lm"]], full.factor_kf[fs], flm, full.z[fs])
+            forder.append(fs)
+            allf = np.concatenate(forder)
+            s.set_reference(full.z_true[allf], full.inlier[allf])
+            if use_depth and weights is not None and new_users:
+                a = s.iterate_logged(depth_delay, damping, huber_k, log_every=1)
+                s.apply_depth_model(np.array(new_users, dtype=np.int32))
+                b = s.iterate_logged(iters_per_kf - depth_delay, damping, huber_k, log_every=1)
+                log = np.concatenate([a, b])
+            else:
+                log = s.iterate_logged(iters_per_kf, damping, huber_k, log_every=1)
+            ref = log[:, 0, 2]
+            hit = np.nonzero(ref <= target)[0]
+            to_target.append(int(hit[0]) + 1 if hit.size else None)
+            final_ref.append(float(ref[-1]))
+        s.synchronize()
+        wall = time.perf_counter() - t0
+        fb = int(s.fallback_flags()[0])
+        last = s.reproj() if diverged_at is None else dict(are_ref=float("nan"), are_all=float("nan"))
+    finally:
+        s.close()
+    reached = [v for v in to_target if v is not None]
+    extra = dict(final_are_ref_per_addition=[round(v, 3) for v in final_ref]) if trace else {}
+    return dict(additions=len(to_target), reached=len(reached), diverged_at_keyframe=diverged_at, **extra,
+                mean_iters_to_target=float(np.mean(reached)) if reached else None,
+                mean_final_are_ref=float(np.mean(final_ref)), last_are_ref=float(last["are_ref"]),
+                last_are_all=float(last["are_all"]), wall_s=wall, fallback=fb,
+                iterations=iters_per_kf * (len(to_target) + 1))
+
+
 def compare(problem, weights, *, undamped_too=False, **kw) -> dict:
     plain = time_to_target(problem, weights=None, **kw)
     learned = time_to_target(problem, weights=weights, **kw)
@@ -342,6 +426,10 @@ def main(argv=None):
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--large", type=int, default=0, help="1000-keyframe problems added to the data")
     ap.add_argument("--mixed", type=int, default=0, help="uneven batched problems added to the data")
+    ap.add_argument("--depth-init", type=int, default=0,
+                    help="125-keyframe problems with landmarks started at 1 m depth added to the data")
+    ap.add_argument("--eval-incremental", type=int, default=0,
+                    help="also the incremental run up to this many keyframes")
     ap.add_argument("--seed0", type=int, default=10000)
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--every", type=int, default=5)
@@ -358,6 +446,15 @@ def main(argv=None):
         for sd in [int(v) for v in a.eval_seeds.split(",")]:
             out[f"random_walk_125kf_seed{sd}"] = compare(synth.make_config1(sd), w, undamped_too=True)
             print(json.dumps({f"seed{sd}": out[f"random_walk_125kf_seed{sd}"]}), flush=True)
+        if a.eval_incremental:
+            for tag, init in (("landmarks_at_1m", 1.0), ("landmarks_noisy", None)):
+                st = synth.make_incremental_stream(seed=20000, n_kf=a.eval_incremental, init_depth=init)
+                res = {"plain": incremental_run(st),
+                       "plain_damp_both": incremental_run(st, damp_mode=GBP_DAMP_ETA_LAMBDA),
+                       "learned_damping": incremental_run(st, weights=w),
+                       "learned_damping_and_depth": incremental_run(st, weights=w, use_depth=True)}
+                out[f"incremental_{tag}"] = res
+                print(json.dumps({f"incremental_{tag}": res}), flush=True)
         if a.eval_large:
             out["random_walk_1000kf"] = compare(synth.make_config2(), w, max_iters=400, undamped_too=True)
             print(json.dumps({"large": out["random_walk_1000kf"]}), flush=True)
@@ -371,6 +468,10 @@ def main(argv=None):
     for i in range(a.large):
         parts.append(generate([synth.make_config2(a.seed0 + 5000 + i)], iters=a.iters, every=a.every,
                               frac=a.frac, seed=5000 + i))
+    for b0 in range(0, a.depth_init, a.batch_problems):
+        probs = [synth.reinit_at_depth(synth.make_config1(a.seed0 + 9000 + i))
+                 for i in range(b0, min(a.depth_init, b0 + a.batch_problems))]
+        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=9000 + b0))
     for b0 in range(0, a.mixed, a.batch_problems):
         probs = [synth.make_config3_problem(p, base_seed=a.seed0 + 7000)
                  for p in range(b0, min(a.mixed, b0 + a.batch_problems))]
@@ -382,7 +483,7 @@ def main(argv=None):
     theta, rep = train(X, Y, M, epochs=a.epochs, lr=a.lr)
     meta = dict(problems=a.problems, seeds=[a.seed0, a.seed0 + a.problems - 1], iters=a.iters,
                 every=a.every, frac=a.frac, damping=0.4, generator="125 keyframes / 1919 landmarks random walk",
-                large_problems=a.large, mixed_problems=a.mixed,
+                large_problems=a.large, mixed_problems=a.mixed, depth_init_problems=a.depth_init,
                 label_mean_damping=float(Y[M[:, 0] > 0, 0].mean()), data_seconds=t_gen, **rep)
     save_weights(a.out, theta, meta)
     print(json.dumps(meta))

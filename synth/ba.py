@@ -441,3 +441,22 @@ def make_incremental_stream(seed: int = 20000, n_kf: int = 300, n0: int = 5,
 def _first_factor(p: BAProblem, j: int, k: int) -> int:
     idx = np.flatnonzero((p.factor_lm == j) & (p.factor_kf == k))
     return int(idx[0])
+
+
+def reinit_at_depth(p: BAProblem, depth: float = 1.0) -> BAProblem:
+    """A copy of `p` whose landmarks start `depth` metres along the measured
+    ray of their newest observing keyframe, placed with that keyframe's
+    initial pose (the monocular SLAM initialisation of Section 9.2)."""
+    q = BAProblem(p.name + f"_depth{depth:g}", p.cam, p.kf_true, p.lm_true, p.kf_init.copy(),
+                  p.lm_init.copy(), p.factor_kf, p.factor_lm, p.z, p.z_true, p.inlier, p.kf_anchor_info)
+    cam = p.cam
+    rots = _rotmat(p.kf_init[:, :3])
+    for j in range(p.n_landmarks):
+        fs = np.flatnonzero(p.factor_lm == j)
+        if fs.size == 0:
+            continue
+        f = fs[np.argmax(p.factor_kf[fs])]
+        k = int(p.factor_kf[f])
+        ray = np.array([(p.z[f, 0] - cam.cx) / cam.fx, (p.z[f, 1] - cam.cy) / cam.fy, 1.0])
+        q.lm_init[j] = rots[k].T @ (depth * ray - p.kf_init[k, 3:])
+    return q

@@ -437,3 +437,50 @@ def test_packaged_model_keeps_the_fixed_point_and_reaches_target_sooner(gbp):
     l_eta = learned.time_to_target(prob, weights=w)
     print("iterations to 1 px:", p_eta["iterations"], l_eta["iterations"])
     assert l_eta["iterations"] is not None and l_eta["iterations"] <= p_eta["iterations"]
+
+
+def _depth_model(gbp, b3_1):
+    """Damping head 0.45 (b3[0] = 0) and a constant log-depth head
+    2.5 tanh(b3_1)."""
+    theta = np.zeros(gbp.MLP_PARAMS, np.float32)
+    theta[-1] = b3_1
+    return omlp.to_bf16_bits(theta)
+
+
+@pytest.mark.parametrize("b3_1", [0.0, 0.5, -0.25])
+def test_depth_model_moves_landmarks_along_the_newest_ray(gbp, b3_1):
+    """With a constant head delta, every listed landmark lands at
+    c + exp(delta) (l - c), c the camera centre of its newest observer; its
+    factors restart (zero messages, counters 0) and nothing else moves."""
+    import oracle
+    prob = synth.make_config1(3)
+    s = gbp.GBPSolver(prob)
+    s.set_damping_model(_depth_model(gbp, b3_1), every_k=5, fallback_rise=-2.0)
+    s.iterate(12, 0.4, 2.0)
+    before = s.beliefs()
+    pick = np.array([0, 5, 17, 400, 1918, 17], dtype=np.int32)
+    s.apply_depth_model(pick)
+    after = s.beliefs()
+    delta = float(np.float32(2.5) * np.tanh(np.float32(omlp.bf16_round(b3_1))))
+    moved = np.unique(pick)
+    for j in moved:
+        fs = np.flatnonzero(prob.factor_lm == j)
+        k = int(prob.factor_kf[fs].max())
+        x = before["kf_mu"][k]
+        R = oracle.so3_exp(x[:3])
+        c = -R.T @ x[3:]
+        want = c + np.exp(delta) * (before["lm_mu"][j] - c)
+        assert np.allclose(after["lm_mu"][j], want, rtol=0, atol=1e-5 * max(1.0, np.abs(want).max())), j
+        rows = s.factor_messages(fs.astype(np.int32)).cpu().numpy()
+        assert np.all(rows[:, 10] == 0) and np.all(rows[:, :10] == 0), j
+    rest = np.setdiff1d(np.arange(prob.n_landmarks), moved)
+    assert np.array_equal(after["lm_mu"][rest], before["lm_mu"][rest])
+    s.iterate(10, 0.4, 2.0)
+    assert np.all(np.isfinite(s.beliefs()["lm_mu"]))
+    with pytest.raises(gbp.GBPError):
+        s.apply_depth_model(np.array([prob.n_landmarks], dtype=np.int32))
+    s.close()
+    t = gbp.GBPSolver(prob)
+    with pytest.raises(gbp.GBPError):
+        t.apply_depth_model(np.array([0], dtype=np.int32))   # no model set
+    t.close()
