@@ -377,3 +377,59 @@ def test_reset_replays_the_same_run(gbp):
     with pytest.raises(gbp.GBPError):
         c.reset()
     c.close()
+
+
+def test_full_batch_sampled_problems_match_oracle(gbp):
+    """The benchmark's workload at full size (256 uneven problems, 2.15 M
+    factors) in the benchmark's launch configuration (autotuned workgroup
+    sizes, logged graph replays): sampled problems agree with the oracle run
+    on them alone, under the same forced relinearisation schedule, and the
+    logged per-problem errors agree with the oracle's."""
+    import oracle
+    probs = synth.make_config3(256)
+    s = gbp.GBPSolver(probs, precision=gbp.GBP_FP32)
+    s.autotune(3, None)
+    log = None
+    for _ in range(3):
+        log = s.iterate_logged(10, 0.4, 2.0, log_every=1)
+        s.relinearise(-1)
+    g = s.beliefs()
+    kf_off = np.concatenate([[0], np.cumsum([p.n_keyframes for p in probs])])
+    lm_off = np.concatenate([[0], np.cumsum([p.n_landmarks for p in probs])])
+    worst = 0.0
+    for i in (0, 97, 183, 255):
+        o = oracle.Oracle(probs[i], anneal=True)
+        for _ in range(3):
+            o.iterate(10, 0.4, 2.0)
+            o.relinearise(-1)
+        r = o.beliefs()
+        e = max(rel_mean_err(g["kf_mu"][kf_off[i]:kf_off[i + 1]], r["kf_mu"]),
+                rel_mean_err(g["lm_mu"][lm_off[i]:lm_off[i + 1]], r["lm_mu"]))
+        worst = max(worst, e)
+        assert e < 1e-4, (i, e)
+        # the last logged error (before the final relinearisation request,
+        # which changes no mean) against the oracle's
+        assert abs(log[-1, i, 1] - o.reproj()["are_all"]) < 1e-3, i
+    print(f"full batch: worst relative mean error over sampled problems {worst:.2e}")
+    s.close()
+
+
+def test_large_problem_full_size_matches_oracle(gbp):
+    """The 1000-keyframe, 40000-landmark problem (about 310 k factors) at full
+    size, FP32 factor state, information and vector damped, forced
+    relinearisation every 10 iterations: every mean within 1e-4 relative of
+    the FP64 oracle and the error within 1e-3 px."""
+    prob = synth.make_config2()
+    s, o = pair(gbp, prob, gbp.GBP_FP32, damp_lambda=True)
+    worst = 0.0
+    for it in range(3):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        e = mean_errs(s.beliefs(), o.beliefs())
+        worst = max(worst, e)
+        assert e < 1e-4, (it, e)
+        assert abs(s.reproj()["are_all"] - o.reproj()["are_all"]) < 1e-3
+        s.relinearise(-1)
+        o.relinearise(-1)
+    print(f"large problem: worst relative mean error {worst:.2e}")
+    s.close()
