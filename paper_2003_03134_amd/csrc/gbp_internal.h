@@ -9,7 +9,8 @@ namespace gbp {
 
 constexpr int KREC = 16;  // keyframe-side record per factor (see layout below)
 constexpr int LREC = 12;  // landmark-side record per factor
-constexpr int AREC = 16;  // factor-private record
+constexpr int AREC = 10;  // factor-private record read by the message update
+constexpr int DREC = 12;  // factor's linearisation point (check, features)
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
@@ -29,8 +30,9 @@ constexpr int MSG_W = 16;   // floats per exported factor-message row
 // landmark-side record:
 //   [0..5]  d h / d l (2x3)   [6..8] S to landmark   [9..10] g to landmark
 // factor-private record:
-//   [0..1]  r0 = z - h(x0)   [2..7] x0_k - anchor_k   [8..10] x0_m - anchor_m
-//   [11..12] J_k anchor_k    [13..14] J_m anchor_m
+//   [0..1]  r0 = z - h(x0)   [2..3] J_k (x0_k - anchor_k)   [4..5] J_m (x0_m - anchor_m)
+//   [6..7]  J_k anchor_k     [8..9] J_m anchor_m
+// linearisation-point record: [0..5] x0_k - anchor_k, [6..8] x0_m - anchor_m, pad
 
 struct ProbParams {
     double fx, fy, cx, cy, sigma, inv_s2, zmin, pad;
@@ -58,7 +60,7 @@ struct Dev {
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state
     const double *z;
-    TS *krec, *lrec, *arec;
+    TS *krec, *lrec, *arec, *drec;
     uint8_t *cnt, *flags;
     float *fdamp;                         // per-factor damping (learned model) or null
     const int *fallback;                  // per problem: 1 = learned damping switched off

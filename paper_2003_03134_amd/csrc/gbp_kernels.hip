@@ -89,6 +89,17 @@ __device__ __forceinline__ void load12(const double *__restrict__ p, double (&v)
     for (int i = 0; i < 6; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
 }
 
+__device__ __forceinline__ void load10(const float *__restrict__ p, float (&v)[10]) {
+    const float2 *q = reinterpret_cast<const float2 *>(p);  // 40-byte records: 8-byte aligned
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { float2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
+}
+__device__ __forceinline__ void load10(const double *__restrict__ p, double (&v)[10]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
+}
+
 // Cholesky of a packed symmetric D x D matrix; returns false when a pivot is
 // not positive. L is stored packed by rows of the lower triangle in `L`.
 template <int D>
@@ -367,7 +378,7 @@ __device__ __forceinline__ void cavity(const double (&Jo)[2][D], const double (&
 // covariance, so each covariance entry is used once as it arrives.
 template <int D>
 __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const double *__restrict__ cov,
-                                              const double (&dmu)[D], const double (&d0)[D], double Sa,
+                                              const double (&dmu)[D], double jdd0, double jdd1, double Sa,
                                               double Sb, double Sc, double g0, double g1, double &Pa,
                                               double &Pb, double &Pc, double &m0, double &m1) {
     double poa = 0, pob = 0, poc = 0;
@@ -387,14 +398,14 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
             }
         }
     }
-    double jd0 = 0, jd1 = 0, jn0 = 0, jn1 = 0;
+    double jd0 = 0, jd1 = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         jd0 += J[0][i] * dmu[i];
         jd1 += J[1][i] * dmu[i];
-        jn0 += J[0][i] * (dmu[i] - d0[i]);
-        jn1 += J[1][i] * (dmu[i] - d0[i]);
     }
+    // J (dmu - d0), with J d0 stored at linearisation
+    const double jn0 = jd0 - jdd0, jn1 = jd1 - jdd1;
     // M = (I - S Po)^-1 ; G = M S ; h = M (S J dmu - g)
     double e00 = 1.0 - (Sa * poa + Sb * pob), e01 = -(Sa * pob + Sb * poc);
     double e10 = -(Sb * poa + Sc * pob), e11 = 1.0 - (Sb * pob + Sc * poc);
@@ -436,7 +447,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
                                             const double *__restrict__ bk, TS *__restrict__ stage) {
     const int m = d.f_lm[f];
     TS ar[AREC], kr[KREC], lr[LREC];
-    load16(d.arec + (size_t)f * AREC, ar);
+    load10(d.arec + (size_t)f * AREC, ar);
     load16(d.krec + (size_t)f * KREC, kr);
     load12(d.lrec + (size_t)f * LREC, lr);
     int c = d.cnt[f];
@@ -449,11 +460,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 #pragma unroll
     for (int i = 0; i < 3; ++i) dmm[i] = bm[i];
 
-    double d0k[6], d0m[3];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) d0k[i] = (double)ar[2 + i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) d0m[i] = (double)ar[8 + i];
+    // J d0 of both blocks (d0: linearisation point relative to the anchors)
+    double jdk0 = (double)ar[2], jdk1 = (double)ar[3], jdm0 = (double)ar[4], jdm1 = (double)ar[5];
     constexpr bool relin = RELIN;
 
     // current (old) Jacobian blocks
@@ -467,7 +475,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
     double r0[2] = {(double)ar[0], (double)ar[1]};
     double s = (double)kr[15];
-    double jak0 = (double)ar[11], jak1 = (double)ar[12], jam0 = (double)ar[13], jam1 = (double)ar[14];
+    double jak0 = (double)ar[6], jak1 = (double)ar[7], jam0 = (double)ar[8], jam1 = (double)ar[9];
     const double Ska = kr[10], Skb = kr[11], Skc = kr[12], gk0 = kr[13], gk1 = kr[14];
     const double Sma = lr[6], Smb = lr[7], Smc = lr[8], gm0 = lr[9], gm1 = lr[10];
 
@@ -493,10 +501,12 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         r0[0] = L.r0[0]; r0[1] = L.r0[1];
         s = L.s;
         nfl = L.valid ? (uint8_t)(nfl & ~FLAG_INVALID) : (uint8_t)(nfl | FLAG_INVALID);
+        // the new linearisation point is the current mean: d0 = dmu
+        jdk0 = jdk1 = jdm0 = jdm1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) d0k[i] = dmk[i];
+        for (int i = 0; i < 6; ++i) { jdk0 += Jkn[0][i] * dmk[i]; jdk1 += Jkn[1][i] * dmk[i]; }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) d0m[i] = dmm[i];
+        for (int i = 0; i < 3; ++i) { jdm0 += Jmn[0][i] * dmm[i]; jdm1 += Jmn[1][i] * dmm[i]; }
         jak0 = jak1 = jam0 = jam1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -524,11 +534,11 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     // cavities of both variables in the factor's measurement space
     double Pka, Pkb, Pkc, mk0, mk1, Pma, Pmb, Pmc, mm0, mm1;
     if constexpr (RELIN) {
-        cavity<6>(Jko, Jkn, relin, bk + 6, dmk, d0k, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
-        cavity<3>(Jmo, Jmn, relin, bm + 3, dmm, d0m, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+        cavity<6>(Jko, Jkn, relin, bk + 6, dmk, dmk, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+        cavity<3>(Jmo, Jmn, relin, bm + 3, dmm, dmm, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
     } else {
-        cavity_same_j<3>(Jmo, bm + 3, dmm, d0m, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
-        cavity_same_j<6>(Jko, bk + 6, dmk, d0k, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+        cavity_same_j<3>(Jmo, bm + 3, dmm, jdm0, jdm1, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+        cavity_same_j<6>(Jko, bk + 6, dmk, jdk0, jdk1, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
     }
 
     // new messages: to the landmark through the keyframe cavity and back
@@ -537,9 +547,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         double qa = 1.0 + s * Pka, qb = s * Pkb, qc = 1.0 + s * Pkc;
         double f0 = s / (qa * qc - qb * qb);
         nSm_a = f0 * qc; nSm_b = -f0 * qb; nSm_c = f0 * qa;
-        double u0 = r0[0] - mk0, u1 = r0[1] - mk1;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { u0 += Jmn[0][i] * d0m[i]; u1 += Jmn[1][i] * d0m[i]; }
+        const double u0 = r0[0] - mk0 + jdm0, u1 = r0[1] - mk1 + jdm1;
         ngm0 = nSm_a * u0 + nSm_b * u1;
         ngm1 = nSm_b * u0 + nSm_c * u1;
     }
@@ -547,9 +555,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         double qa = 1.0 + s * Pma, qb = s * Pmb, qc = 1.0 + s * Pmc;
         double f0 = s / (qa * qc - qb * qb);
         nSk_a = f0 * qc; nSk_b = -f0 * qb; nSk_c = f0 * qa;
-        double u0 = r0[0] - mm0, u1 = r0[1] - mm1;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) { u0 += Jkn[0][i] * d0k[i]; u1 += Jkn[1][i] * d0k[i]; }
+        const double u0 = r0[0] - mm0 + jdk0, u1 = r0[1] - mm1 + jdk1;
         ngk0 = nSk_a * u0 + nSk_b * u1;
         ngk1 = nSk_b * u0 + nSk_c * u1;
     }
@@ -592,12 +598,14 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
             for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)Jkn[r][i]; lw[3 * r + i] = (TS)Jmn[r][i]; }
         kw[6] = (TS)Jkn[0][3]; kw[7] = (TS)Jkn[1][4]; kw[8] = (TS)Jkn[0][5]; kw[9] = (TS)Jkn[1][5];
         kw[15] = (TS)s;
+        TS *dw = d.drec + (size_t)f * DREC;
         aw[0] = (TS)r0[0]; aw[1] = (TS)r0[1];
+        aw[2] = (TS)jdk0; aw[3] = (TS)jdk1; aw[4] = (TS)jdm0; aw[5] = (TS)jdm1;
+        aw[6] = (TS)jak0; aw[7] = (TS)jak1; aw[8] = (TS)jam0; aw[9] = (TS)jam1;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) aw[2 + i] = (TS)d0k[i];
+        for (int i = 0; i < 6; ++i) dw[i] = (TS)dmk[i];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) aw[8 + i] = (TS)d0m[i];
-        aw[11] = (TS)jak0; aw[12] = (TS)jak1; aw[13] = (TS)jam0; aw[14] = (TS)jam1;
+        for (int i = 0; i < 3; ++i) dw[6 + i] = (TS)dmm[i];
     }
     d.cnt[f] = (uint8_t)(c + 1 > 255 ? 255 : c + 1);
     if constexpr (RELIN) d.flags[f] = nfl;
@@ -628,14 +636,14 @@ __global__ __launch_bounds__(256) void k_check(Dev<TS> d, IterOpts o) {
             need = true;
         } else if (d.cnt[f] >= o.interval) {
             const int k = d.f_kf[f], m = d.f_lm[f];
-            const TS *ar = d.arec + (size_t)f * AREC;
+            const TS *dr = d.drec + (size_t)f * DREC;
             const double *bk = d.kf_bel + (size_t)k * KBEL;
             const double *bm = d.lm_bel + (size_t)m * LBEL;
             double dist2 = 0.0;
 #pragma unroll
-            for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)ar[2 + i]; dist2 += e * e; }
+            for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)ar[8 + i]; dist2 += e * e; }
+            for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)dr[6 + i]; dist2 += e * e; }
             need = dist2 > o.beta2;
         }
     }
@@ -759,8 +767,15 @@ __device__ __forceinline__ void kf_contrib(const TS *row, TS *c) {
 // the factor-state precision, to a padded LDS row; 27 x G lanes then add
 // interleaved rows column by column in FP64 and the G partials are added in
 // group order (fixed order, no cross-lane shuffles).
+// FP32 factor state, 64-lane workgroups: four waves per SIMD. At 137
+// registers the kernel ran three; the compiler fits it in 128 with a 12-byte
+// spill, which measured 4% faster. (No target for the other variants.)
+template <typename TS, int BS>
+constexpr int kf_waves_per_eu() { return (sizeof(TS) == 4 && BS == 64) ? 4 : 1; }
+
 template <typename TS, int BS, int MODE>
-__global__ __launch_bounds__(BS) void k_factor_kf(Dev<TS> d, IterOpts o) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per_eu<TS, BS>()))) void k_factor_kf(
+    Dev<TS> d, IterOpts o) {
     constexpr int G = BS / 32;     // row groups in the column sums
     constexpr int RS = 29;         // padded row stride (doubles) against bank conflicts
     __shared__ TS red[BS * RS];
@@ -848,20 +863,21 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.nf) return;
     const int k = d.f_kf[f], m = d.f_lm[f];
-    TS kr[KREC], lr[LREC], ar[AREC];
+    TS kr[KREC], lr[LREC], ar[AREC], dr[DREC];
     load16(d.krec + (size_t)f * KREC, kr);
     load12(d.lrec + (size_t)f * LREC, lr);
-    load16(d.arec + (size_t)f * AREC, ar);
+    load10(d.arec + (size_t)f * AREC, ar);
+    load12(d.drec + (size_t)f * DREC, dr);
     const ProbParams pp = d.prob[d.kf_prob[k]];
     const double *bk = d.kf_bel + (size_t)k * KBEL, *bm = d.lm_bel + (size_t)m * LBEL;
     const double M0 = sqrt((double)ar[0] * ar[0] + (double)ar[1] * ar[1]) / pp.sigma;
     const double N = huber_k / pp.sigma;
     double dist2 = 0.0;
-    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)ar[2 + i]; dist2 += e * e; }
-    for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)ar[8 + i]; dist2 += e * e; }
+    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
+    for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)dr[6 + i]; dist2 += e * e; }
     double ju0 = 0, ju1 = 0;
     for (int i = 0; i < 3; ++i) {
-        const double e = bm[i] - (double)ar[8 + i];
+        const double e = bm[i] - (double)dr[6 + i];
         ju0 += (double)lr[i] * e;
         ju1 += (double)lr[3 + i] * e;
     }
@@ -937,7 +953,7 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
     const TS *ar = d.arec + (size_t)f * AREC;
-    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[11 + c];
+    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[6 + c];
 }
 
 // --------------------------------------------------------------------------
@@ -959,6 +975,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     Lin L;
     linearise(x, l, zz, pp, huber_k, L);
     TS *kw = d.krec + (size_t)f * KREC, *lw = d.lrec + (size_t)f * LREC, *aw = d.arec + (size_t)f * AREC;
+    TS *dw = d.drec + (size_t)f * DREC;
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -970,10 +987,14 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
 #pragma unroll
     for (int i = 6; i < 12; ++i) lw[i] = (TS)0;
     aw[0] = (TS)L.r0[0]; aw[1] = (TS)L.r0[1];
+    double jdk0 = 0, jdk1 = 0, jdm0 = 0, jdm1 = 0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) aw[2 + i] = (TS)dmk[i];
+    for (int i = 0; i < 6; ++i) { jdk0 += L.J[0][i] * dmk[i]; jdk1 += L.J[1][i] * dmk[i]; dw[i] = (TS)dmk[i]; }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) aw[8 + i] = (TS)dmm[i];
+    for (int i = 0; i < 3; ++i) { jdm0 += L.J[0][6 + i] * dmm[i]; jdm1 += L.J[1][6 + i] * dmm[i]; dw[6 + i] = (TS)dmm[i]; }
+#pragma unroll
+    for (int i = 9; i < DREC; ++i) dw[i] = (TS)0;
+    aw[2] = (TS)jdk0; aw[3] = (TS)jdk1; aw[4] = (TS)jdm0; aw[5] = (TS)jdm1;
     double jak0 = 0, jak1 = 0, jam0 = 0, jam1 = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -987,7 +1008,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
         jam0 += L.J[0][6 + i] * a;
         jam1 += L.J[1][6 + i] * a;
     }
-    aw[11] = (TS)jak0; aw[12] = (TS)jak1; aw[13] = (TS)jam0; aw[14] = (TS)jam1; aw[15] = (TS)0;
+    aw[6] = (TS)jak0; aw[7] = (TS)jak1; aw[8] = (TS)jam0; aw[9] = (TS)jam1;
     d.cnt[f] = 0;
     d.flags[f] = L.valid ? 0 : FLAG_INVALID;
 }
@@ -1113,12 +1134,12 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
     // point, so its distance is zero: only beta < 0 selects it again
     if (!sel && !(d.flags[f] & FLAG_PENDING)) {
         const int k = d.f_kf[f], m = d.f_lm[f];
-        const TS *ar = d.arec + (size_t)f * AREC;
+        const TS *dr = d.drec + (size_t)f * DREC;
         double dist2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) { double e = d.kf_bel[(size_t)k * KBEL + i] - (double)ar[2 + i]; dist2 += e * e; }
+        for (int i = 0; i < 6; ++i) { double e = d.kf_bel[(size_t)k * KBEL + i] - (double)dr[i]; dist2 += e * e; }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { double e = d.lm_bel[(size_t)m * LBEL + i] - (double)ar[8 + i]; dist2 += e * e; }
+        for (int i = 0; i < 3; ++i) { double e = d.lm_bel[(size_t)m * LBEL + i] - (double)dr[6 + i]; dist2 += e * e; }
         sel = sqrt(dist2) > beta;
     }
     if (sel) {
@@ -1370,6 +1391,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         T *tmp = (T *)scratch;
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 10: hipLaunchKernelGGL((k_gather<T, 10>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             default: return;
@@ -1379,6 +1401,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
     run(d.krec, TS(0), KREC);
     run(d.lrec, TS(0), LREC);
     run(d.arec, TS(0), AREC);
+    run(d.drec, TS(0), DREC);
     run(d.cnt, uint8_t(0), 1);
     run(d.flags, uint8_t(0), 1);
     if (fdamp) run(fdamp, -1.f, 1);  // fresh factors: constant damping until the next evaluation
