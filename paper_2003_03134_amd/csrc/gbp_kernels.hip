@@ -1077,29 +1077,43 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
 
 template <typename TS>
 __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout) {
-    const int m = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (m >= d.nl) return;
-    const int t = d.t_dev[0];
-    const double sc = prior_scale(o, t - d.lm_t0[m]);
+    // LM_LANES lanes per landmark: lane q of a group sums edges q, q + LM_LANES,
+    // ... (in order), then the group adds its partial sums with a fixed
+    // butterfly; every lane of the group ends with the same sums
+    const int gid = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int m = gid / LM_LANES, q = gid % LM_LANES;
+    const bool live = m < d.nl;
     double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
-    A[pidx<3>(0, 0)] = d.lm_pbase[3 * (size_t)m] * sc;
-    A[pidx<3>(1, 1)] = d.lm_pbase[3 * (size_t)m + 1] * sc;
-    A[pidx<3>(2, 2)] = d.lm_pbase[3 * (size_t)m + 2] * sc;
-    for (int ei = d.lm_row[m]; ei < d.lm_row[m + 1]; ++ei) {
-        TS r[LREC];
-        load12(d.lrec + (size_t)d.lm_edge[ei] * LREC, r);
-        double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
-        double Sa = r[6], Sb = r[7], Sc = r[8], g0 = r[9], g1 = r[10];
-        double SJ0[3], SJ1[3];
+    if (live) {
+        for (int ei = d.lm_row[m] + q; ei < d.lm_row[m + 1]; ei += LM_LANES) {
+            TS r[LREC];
+            load12(d.lrec + (size_t)d.lm_edge[ei] * LREC, r);
+            double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
+            double Sa = r[6], Sb = r[7], Sc = r[8], g0 = r[9], g1 = r[10];
+            double SJ0[3], SJ1[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+            for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
+            for (int i = 0; i < 3; ++i) {
 #pragma unroll
-            for (int j = i; j < 3; ++j) A[pidx<3>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
-            e[i] += J0[i] * g0 + J1[i] * g1;
+                for (int j = i; j < 3; ++j) A[pidx<3>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
+                e[i] += J0[i] * g0 + J1[i] * g1;
+            }
         }
     }
+#pragma unroll
+    for (int off = 1; off < LM_LANES; off <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[i] += __shfl_xor(A[i], off, 64);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e[i] += __shfl_xor(e[i], off, 64);
+    }
+    if (!live || q != 0) return;
+    const int t = d.t_dev[0];
+    const double sc = prior_scale(o, t - d.lm_t0[m]);
+    A[pidx<3>(0, 0)] += d.lm_pbase[3 * (size_t)m] * sc;
+    A[pidx<3>(1, 1)] += d.lm_pbase[3 * (size_t)m + 1] * sc;
+    A[pidx<3>(2, 2)] += d.lm_pbase[3 * (size_t)m + 2] * sc;
     if (readout) {
         double *out = d.lm_info + 9 * (size_t)m;
 #pragma unroll
@@ -1358,7 +1372,8 @@ void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_
 
 template <typename TS>
 void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
-    if (d.nl > 0) hipLaunchKernelGGL(k_belief_lm<TS>, dim3(blocks(d.nl, block)), dim3(block), 0, s, d, o, readout);
+    if (d.nl > 0)
+        hipLaunchKernelGGL(k_belief_lm<TS>, dim3(blocks(d.nl * LM_LANES, block)), dim3(block), 0, s, d, o, readout);
 }
 
 template <typename TS>
