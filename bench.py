@@ -184,7 +184,8 @@ def main():
     solver.set_reference(zt, inl)
     tuned = solver.autotune(5, None if args.no_tune_cache else
                             os.path.join(ROOT, "paper_2003_03134_amd", "tuning", "autotune_cache.txt"))
-    log(f"autotuned workgroup sizes: keyframe kernel {tuned[0]}, landmark kernel {tuned[1]}")
+    log(f"autotuned: keyframe kernel {tuned[0]} lanes/workgroup, landmark kernel {tuned[1]} "
+        f"lanes/workgroup, {tuned[2]} lanes per landmark")
 
     K, W = args.steps, args.warmup
     c = max(1, min(args.chunk, K))
@@ -275,7 +276,8 @@ def main():
                    "factor_state": "f32", "beliefs": "f64",
                    "step": "relinearisation check + factor messages + beliefs + per-problem reprojection error",
                    "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU",
-                   "autotuned_blocks": {"keyframe_kernel": tuned[0], "landmark_kernel": tuned[1]}},
+                   "autotuned": {"keyframe_kernel_block": tuned[0], "landmark_kernel_block": tuned[1],
+                                 "lanes_per_landmark": tuned[2]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -444,6 +444,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
 #undef UP
     p->fdamp_buf = d.fdamp;
+    d.lm_lanes = LM_LANES;
     d.fdamp = nullptr;
     d.fallback = nullptr;
     // initial linearisation at the initial estimate, automatic priors,
@@ -671,57 +672,74 @@ std::string tune_key(gbp_problem *p) {
     return os.str();
 }
 
-// tiny cache: one line per key, "key kf_block lm_block ms"
-bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb) {
+// tiny cache: one line per key, "key kf_block lm_block lm_lanes ms"
+bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll) {
     if (!path) return false;
     std::ifstream in(path);
-    std::string k2;
-    int a = 0, b = 0;
-    double ms = 0;
-    while (in >> k2 >> a >> b >> ms)
-        if (k2 == key) { kb = a; lb = b; return true; }
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream is(line);
+        std::string k2;
+        int a = 0, b = 0, c = 0;
+        double ms = 0;
+        if ((is >> k2 >> a >> b >> c >> ms) && k2 == key) { kb = a; lb = b; ll = c; return true; }
+    }
     return false;
 }
 
-void cache_store(const char *path, const std::string &key, int kb, int lb, double ms) {
+void cache_store(const char *path, const std::string &key, int kb, int lb, int ll, double ms) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << kb << " " << lb << " " << ms << "\n";
+    out << key << " " << kb << " " << lb << " " << ll << " " << ms << "\n";
 }
 
+// Autotuner: the workgroup sizes of the keyframe kernel and of the landmark
+// belief kernel (3 x 3, with 4 lanes per landmark), then the lanes per
+// landmark (2 / 4 / 8) with the chosen sizes; each candidate runs n
+// iterations from a snapshot of the workspace, which is restored after it.
 template <typename TS>
 gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t *chosen) {
+    Dev<TS> &d = dev<TS>(p);
     const std::string key = tune_key(p);
-    int kb = 0, lb = 0;
-    if (cache_lookup(cache_path, key, kb, lb)) {
+    int kb = 0, lb = 0, ll = 0;
+    if (cache_lookup(cache_path, key, kb, lb, ll) && (ll == 2 || ll == 4 || ll == 8)) {
         p->blk_kf = kb;
         p->blk_lm = lb;
+        d.lm_lanes = ll;
     } else {
-        // snapshot the whole workspace, time every candidate, restore
         void *snap = nullptr;
         HIP_TRY(p, hipMalloc(&snap, p->ws_bytes));
         HIP_TRY(p, hipMemcpyAsync(snap, p->ws, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
-        const int kbs[3] = {64, 128, 256}, lbs[3] = {64, 128, 256};
         double best = 1e30;
-        int bk = p->blk_kf, bl = p->blk_lm;
-        for (int x : kbs)
-            for (int y : lbs) {
-                p->blk_kf = x;
-                p->blk_lm = y;
-                double ms = 0;
-                gbp_status st = time_config<TS>(p, n, &ms);
-                if (st != GBP_OK) { (void)hipFree(snap); return st; }
-                HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
-                if (ms < best) { best = ms; bk = x; bl = y; }
-            }
+        int bk = p->blk_kf, bl = p->blk_lm, bll = 4;
+        auto trial = [&](int x, int y, int z) -> gbp_status {
+            p->blk_kf = x;
+            p->blk_lm = y;
+            d.lm_lanes = z;
+            double ms = 0;
+            gbp_status st = time_config<TS>(p, n, &ms);
+            if (st != GBP_OK) return st;
+            HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+            if (ms < best) { best = ms; bk = x; bl = y; bll = z; }
+            return GBP_OK;
+        };
+        gbp_status st = GBP_OK;
+        for (int x : {64, 128, 256})
+            for (int y : {64, 128, 256})
+                if (st == GBP_OK) st = trial(x, y, 4);
+        const int bk0 = bk, bl0 = bl;
+        for (int z : {2, 8})
+            if (st == GBP_OK) st = trial(bk0, bl0, z);
         HIP_TRY(p, hipStreamSynchronize(p->stream));
         (void)hipFree(snap);
+        if (st != GBP_OK) return st;
         p->blk_kf = bk;
         p->blk_lm = bl;
-        cache_store(cache_path, key, bk, bl, best);
+        d.lm_lanes = bll;
+        cache_store(cache_path, key, bk, bl, bll, best);
     }
     destroy_graphs(p);
-    if (chosen) { chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; }
+    if (chosen) { chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; chosen[2] = d.lm_lanes; }
     return GBP_OK;
 }
 

@@ -15,7 +15,7 @@ constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed)
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
 constexpr int RBLK = 256;   // factors per residual-phase block (one per lane)
-constexpr int LM_LANES = 4;  // lanes per landmark in the landmark belief kernel
+constexpr int LM_LANES = 4;  // default lanes per landmark in the landmark belief kernel
 constexpr int NFEAT = 16;   // learned-model features per factor
 constexpr int FHIST = 12;   // floats of per-factor feature history
 constexpr int MSG_W = 16;   // floats per exported factor-message row
@@ -57,6 +57,7 @@ struct Dev {
     const int *kf_row;                    // factors of keyframe k: [kf_row[k], kf_row[k+1])
     const int *kf_order;                  // keyframe of each keyframe-kernel workgroup (-1: none)
     int n_kf_slots;                       // workgroups of the keyframe kernel
+    int lm_lanes;                         // lanes per landmark in the landmark belief kernel (2, 4, 8)
     const int *lm_row, *lm_edge;          // factors of each landmark (CSR, increasing)
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state

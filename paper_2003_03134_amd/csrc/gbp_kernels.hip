@@ -767,11 +767,11 @@ __device__ __forceinline__ void kf_contrib(const TS *row, TS *c) {
 // the factor-state precision, to a padded LDS row; 27 x G lanes then add
 // interleaved rows column by column in FP64 and the G partials are added in
 // group order (fixed order, no cross-lane shuffles).
-// FP32 factor state, 64-lane workgroups: four waves per SIMD. At 137
-// registers the kernel ran three; the compiler fits it in 128 with a 12-byte
-// spill, which measured 4% faster. (No target for the other variants.)
+// FP32 factor state: four waves per SIMD. At 137 registers the kernel ran
+// three; the compiler fits it in 128 with a 12-byte spill, which measured 4%
+// faster. (No target for FP64 factor state, which cannot reach it.)
 template <typename TS, int BS>
-constexpr int kf_waves_per_eu() { return (sizeof(TS) == 4 && BS == 64) ? 4 : 1; }
+constexpr int kf_waves_per_eu() { return sizeof(TS) == 4 ? 4 : 1; }
 
 template <typename TS, int BS, int MODE>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per_eu<TS, BS>()))) void k_factor_kf(
@@ -1075,17 +1075,17 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
 // --------------------------------------------------------------------------
 
 
-template <typename TS>
+template <typename TS, int LANES>
 __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout) {
-    // LM_LANES lanes per landmark: lane q of a group sums edges q, q + LM_LANES,
+    // LANES lanes per landmark: lane q of a group sums edges q, q + LANES,
     // ... (in order), then the group adds its partial sums with a fixed
     // butterfly; every lane of the group ends with the same sums
     const int gid = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int m = gid / LM_LANES, q = gid % LM_LANES;
+    const int m = gid / LANES, q = gid % LANES;
     const bool live = m < d.nl;
     double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
     if (live) {
-        for (int ei = d.lm_row[m] + q; ei < d.lm_row[m + 1]; ei += LM_LANES) {
+        for (int ei = d.lm_row[m] + q; ei < d.lm_row[m + 1]; ei += LANES) {
             TS r[LREC];
             load12(d.lrec + (size_t)d.lm_edge[ei] * LREC, r);
             double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
@@ -1102,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
         }
     }
 #pragma unroll
-    for (int off = 1; off < LM_LANES; off <<= 1) {
+    for (int off = 1; off < LANES; off <<= 1) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) A[i] += __shfl_xor(A[i], off, 64);
 #pragma unroll
@@ -1372,8 +1372,12 @@ void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_
 
 template <typename TS>
 void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
-    if (d.nl > 0)
-        hipLaunchKernelGGL(k_belief_lm<TS>, dim3(blocks(d.nl * LM_LANES, block)), dim3(block), 0, s, d, o, readout);
+    if (d.nl <= 0) return;
+    switch (d.lm_lanes) {
+        case 2: hipLaunchKernelGGL((k_belief_lm<TS, 2>), dim3(blocks(d.nl * 2, block)), dim3(block), 0, s, d, o, readout); break;
+        case 8: hipLaunchKernelGGL((k_belief_lm<TS, 8>), dim3(blocks(d.nl * 8, block)), dim3(block), 0, s, d, o, readout); break;
+        default: hipLaunchKernelGGL((k_belief_lm<TS, 4>), dim3(blocks(d.nl * 4, block)), dim3(block), 0, s, d, o, readout); break;
+    }
 }
 
 template <typename TS>

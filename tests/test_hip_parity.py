@@ -267,14 +267,14 @@ def test_autotune_leaves_state_unchanged(gbp, tmp_path):
     s.iterate(15, 0.4, 2.0)
     before = s.beliefs()          # stored beliefs (no recomputation)
     cache = str(tmp_path / "tune.txt")
-    kb, lb = s.autotune(3, cache)
-    assert kb in (64, 128, 256) and lb in (64, 128, 256)
+    kb, lb, ll = s.autotune(3, cache)
+    assert kb in (64, 128, 256) and lb in (64, 128, 256) and ll in (2, 4, 8)
     after = s.beliefs()
     for key in before:            # the device state was restored exactly
         assert np.array_equal(before[key], after[key]), key
     # a second problem of the same size bucket takes the cached choice
     s2 = gbp.GBPSolver(prob)
-    assert s2.autotune(3, cache) == (kb, lb)
+    assert s2.autotune(3, cache) == (kb, lb, ll)
     assert open(cache).read().count("\n") == 1
     o = oracle.Oracle(prob, anneal=True)
     o.iterate(15, 0.4, 2.0)
@@ -283,6 +283,33 @@ def test_autotune_leaves_state_unchanged(gbp, tmp_path):
     assert mean_errs(s.beliefs(), o.beliefs()) < 1e-4
     s.close()
     s2.close()
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8])
+def test_every_landmark_lane_count_matches_oracle(gbp, lanes, tmp_path):
+    """The landmark belief kernel with 2, 4 and 8 lanes per landmark (forced
+    through a tuning-cache entry) agrees with the FP64 oracle in FP64."""
+    import oracle
+    prob = synth.make_config0(seed=0)
+    s = gbp.GBPSolver(prob, precision=gbp.GBP_FP64, anneal=False)
+    nf = prob.n_factors
+    key_bucket = lambda v: max(0, int(np.floor(np.log2(v)))) if v > 1 else 0  # noqa: E731
+    cache = tmp_path / "tune.txt"
+    arch = "gfx950"
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = (f"{arch}/p{gbp.GBP_FP64}/f{key_bucket(nf)}/k{key_bucket(prob.n_keyframes)}"
+           f"/l{key_bucket(prob.n_landmarks)}")
+    cache.write_text(f"{key} 64 64 {lanes} 0.0\n")
+    assert s.autotune(2, str(cache)) == (64, 64, lanes)
+    o = oracle.Oracle(prob, anneal=False)
+    for _ in range(4):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
+        s.relinearise(-1)
+        o.relinearise(-1)
+    s.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
