@@ -29,12 +29,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # keyframe: every factor's two messages, then the keyframe's message sums),
 # with FP32 factor state (layout in paper_2003_03134_amd/csrc/gbp_internal.h):
 #   per factor: read the keyframe-side record 16 x 4 B, the landmark-side
-#     Jacobian + message 11 x 4 B, the factor-private record 15 x 4 B (r0,
-#     linearisation offset, J*anchor), the landmark index 4 B, counter and
-#     flags 2 x 1 B; write both new messages 2 x 5 x 4 B and the counter 1 B;
+#     Jacobian + message 11 x 4 B, the factor-private record 10 x 4 B (r0,
+#     J times linearisation offset, J times anchor), the landmark index 4 B,
+#     counter and flags 2 x 1 B; write both new messages 2 x 5 x 4 B and the
+#     counter 1 B;
 #   per keyframe: read its belief (27 doubles), write its 27 message sums;
 #   per landmark: read its belief once (9 doubles; gathered by its factors).
-FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 15 * 4 + 4 + 2 + 2 * 5 * 4 + 1  # 215
+FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 10 * 4 + 4 + 2 + 2 * 5 * 4 + 1  # 195
 KF_BELIEF_BYTES = 27 * 8 + 27 * 8
 LM_BELIEF_BYTES = 9 * 8
 
