@@ -7,7 +7,8 @@
 
 namespace gbp {
 
-constexpr int KREC = 16;  // keyframe-side record per factor (see layout below)
+constexpr int KREC = 12;  // keyframe-side Jacobian record per factor (see layout below)
+constexpr int KMSG = 5;   // message to the keyframe (dense, rewritten every iteration)
 constexpr int LREC = 12;  // landmark-side record per factor
 constexpr int AREC = 10;  // factor-private record read by the message update
 constexpr int DREC = 12;  // factor's linearisation point (check, features)
@@ -24,10 +25,11 @@ constexpr int MSG_W = 16;   // floats per exported factor-message row
 //   [0..5]  d h / d omega (2x3, row-major)
 //   [6]     fx / pz   [7] fy / pz   [8] -fx px / pz^2   [9] -fy py / pz^2
 //           (d h / d t = [[6], 0, [8]; 0, [7], [9]])
-//   [10..12] message to the keyframe, S (a, b, c) = [[a b][b c]]
-//   [13..14] message to the keyframe, g (anchor-relative information vector
-//            in the factor's 2-D measurement space)
-//   [15]    s = w / sigma^2
+//   [10]    s = w / sigma^2   [11] pad
+// message to the keyframe (its own dense array, so that the rewrite every
+// iteration covers whole cache lines):
+//   [0..2] S (a, b, c) = [[a b][b c]]   [3..4] g (anchor-relative information
+//          vector in the factor's 2-D measurement space)
 // landmark-side record:
 //   [0..5]  d h / d l (2x3)   [6..8] S to landmark   [9..10] g to landmark
 // factor-private record:
@@ -62,7 +64,7 @@ struct Dev {
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state
     const double *z;
-    TS *krec, *lrec, *arec, *drec;
+    TS *krec, *kmsg, *lrec, *arec, *drec;
     uint8_t *cnt, *flags;
     float *fdamp;                         // per-factor damping (learned model) or null
     const int *fallback;                  // per problem: 1 = learned damping switched off

@@ -89,6 +89,12 @@ __device__ __forceinline__ void load12(const double *__restrict__ p, double (&v)
     for (int i = 0; i < 6; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
 }
 
+template <typename TS>
+__device__ __forceinline__ void load5(const TS *__restrict__ p, TS (&v)[5]) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] = p[i];  // 20-byte records: dword loads, coalesced across lanes
+}
+
 __device__ __forceinline__ void load10(const float *__restrict__ p, float (&v)[10]) {
     const float2 *q = reinterpret_cast<const float2 *>(p);  // 40-byte records: 8-byte aligned
 #pragma unroll
@@ -446,9 +452,10 @@ template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
                                             const double *__restrict__ bk, TS *__restrict__ stage) {
     const int m = d.f_lm[f];
-    TS ar[AREC], kr[KREC], lr[LREC];
+    TS ar[AREC], kr[KREC], lr[LREC], km[KMSG];
     load10(d.arec + (size_t)f * AREC, ar);
-    load16(d.krec + (size_t)f * KREC, kr);
+    load12(d.krec + (size_t)f * KREC, kr);
+    load5(d.kmsg + (size_t)f * KMSG, km);
     load12(d.lrec + (size_t)f * LREC, lr);
     int c = d.cnt[f];
     const uint8_t fl = d.flags[f];
@@ -474,9 +481,9 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     Jko[0][3] = (double)kr[6]; Jko[0][4] = 0.0; Jko[0][5] = (double)kr[8];
     Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
     double r0[2] = {(double)ar[0], (double)ar[1]};
-    double s = (double)kr[15];
+    double s = (double)kr[10];
     double jak0 = (double)ar[6], jak1 = (double)ar[7], jam0 = (double)ar[8], jam1 = (double)ar[9];
-    const double Ska = kr[10], Skb = kr[11], Skc = kr[12], gk0 = kr[13], gk1 = kr[14];
+    const double Ska = km[0], Skb = km[1], Skc = km[2], gk0 = km[3], gk1 = km[4];
     const double Sma = lr[6], Smb = lr[7], Smc = lr[8], gm0 = lr[9], gm1 = lr[10];
 
     double Jkn[2][6], Jmn[2][3];
@@ -588,7 +595,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 
     TS *kw = d.krec + (size_t)f * KREC;
     TS *lw = d.lrec + (size_t)f * LREC;
-    kw[10] = (TS)oSk_a; kw[11] = (TS)oSk_b; kw[12] = (TS)oSk_c; kw[13] = (TS)ogk0; kw[14] = (TS)ogk1;
+    TS *mw = d.kmsg + (size_t)f * KMSG;  // dense: full-line writes
+    mw[0] = (TS)oSk_a; mw[1] = (TS)oSk_b; mw[2] = (TS)oSk_c; mw[3] = (TS)ogk0; mw[4] = (TS)ogk1;
     lw[6] = (TS)oSm_a; lw[7] = (TS)oSm_b; lw[8] = (TS)oSm_c; lw[9] = (TS)ogm0; lw[10] = (TS)ogm1;
     if constexpr (RELIN) {
         TS *aw = d.arec + (size_t)f * AREC;
@@ -597,7 +605,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 #pragma unroll
             for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)Jkn[r][i]; lw[3 * r + i] = (TS)Jmn[r][i]; }
         kw[6] = (TS)Jkn[0][3]; kw[7] = (TS)Jkn[1][4]; kw[8] = (TS)Jkn[0][5]; kw[9] = (TS)Jkn[1][5];
-        kw[15] = (TS)s;
+        kw[10] = (TS)s;
         TS *dw = d.drec + (size_t)f * DREC;
         aw[0] = (TS)r0[0]; aw[1] = (TS)r0[1];
         aw[2] = (TS)jdk0; aw[3] = (TS)jdk1; aw[4] = (TS)jdm0; aw[5] = (TS)jdm1;
@@ -805,11 +813,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
             if (MODE == 0 && !(fl & FLAG_DONE)) {
                 factor_body<TS, false>(d, o, f, k, bk, row);
             } else {
-                TS kr[KREC];
-                load16(d.krec + (size_t)f * KREC, kr);
+                TS kr[KREC], km[KMSG];
+                load12(d.krec + (size_t)f * KREC, kr);
+                load5(d.kmsg + (size_t)f * KMSG, km);
                 row[0] = kr[0]; row[1] = kr[1]; row[2] = kr[2]; row[3] = kr[6]; row[5] = kr[8];
                 row[6] = kr[3]; row[7] = kr[4]; row[8] = kr[5]; row[10] = kr[7]; row[11] = kr[9];
-                row[12] = kr[10]; row[13] = kr[11]; row[14] = kr[12]; row[15] = kr[13]; row[16] = kr[14];
+                row[12] = km[0]; row[13] = km[1]; row[14] = km[2]; row[15] = km[3]; row[16] = km[4];
                 if (MODE == 0) d.flags[f] = (uint8_t)(fl & ~FLAG_DONE);
             }
         }
@@ -863,8 +872,9 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.nf) return;
     const int k = d.f_kf[f], m = d.f_lm[f];
-    TS kr[KREC], lr[LREC], ar[AREC], dr[DREC];
-    load16(d.krec + (size_t)f * KREC, kr);
+    TS kr[KREC], lr[LREC], ar[AREC], dr[DREC], km[KMSG];
+    load12(d.krec + (size_t)f * KREC, kr);
+    load5(d.kmsg + (size_t)f * KMSG, km);
     load12(d.lrec + (size_t)f * LREC, lr);
     load10(d.arec + (size_t)f * AREC, ar);
     load12(d.drec + (size_t)f * DREC, dr);
@@ -881,7 +891,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
         ju0 += (double)lr[i] * e;
         ju1 += (double)lr[3 + i] * e;
     }
-    const float gk0 = kr[13], gk1 = kr[14], gm0 = lr[9], gm1 = lr[10], trS = (float)lr[6] + (float)lr[8];
+    const float gk0 = km[3], gk1 = km[4], gm0 = lr[9], gm1 = lr[10], trS = (float)lr[6] + (float)lr[8];
     float *h = hist + FHIST * (size_t)f;
     const bool have = h[7] > 0.5f;
     const float dk0 = gk0 - h[0], dk1 = gk1 - h[1], dm0 = gm0 - h[2], dm1 = gm1 - h[3];
@@ -891,7 +901,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     const float ndk = sqrtf(dk0 * dk0 + dk1 * dk1), ndkp = sqrtf(h[8] * h[8] + h[9] * h[9]);
     float *x = feat + 16 * (size_t)f;
     x[0] = N > 0.0 ? (float)fmin(M0 / N, 10.0) : 0.f;
-    x[1] = (float)((double)kr[15] / pp.inv_s2);
+    x[1] = (float)((double)kr[10] / pp.inv_s2);
     x[2] = (float)log1p(M0);
     x[3] = fminf((float)d.cnt[f], 30.f) / 10.f;
     x[4] = (float)log1p(sqrt(dist2) / sqrt(o.beta2 > 0.0 ? o.beta2 : 1e-4));
@@ -948,7 +958,8 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     }
     const int f = u2i[u];
     const TS *kr = d.krec + (size_t)f * KREC, *lr = d.lrec + (size_t)f * LREC;
-    for (int c = 0; c < 5; ++c) o[c] = (float)kr[10 + c];
+    const TS *km = d.kmsg + (size_t)f * KMSG;
+    for (int c = 0; c < 5; ++c) o[c] = (float)km[c];
     for (int c = 0; c < 5; ++c) o[5 + c] = (float)lr[6 + c];
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
@@ -981,9 +992,11 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
 #pragma unroll
         for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)L.J[r][i]; lw[3 * r + i] = (TS)L.J[r][6 + i]; }
     kw[6] = (TS)L.J[0][3]; kw[7] = (TS)L.J[1][4]; kw[8] = (TS)L.J[0][5]; kw[9] = (TS)L.J[1][5];
+    kw[10] = (TS)L.s;
+    kw[11] = (TS)0;
+    TS *mw = d.kmsg + (size_t)f * KMSG;
 #pragma unroll
-    for (int i = 10; i < 15; ++i) kw[i] = (TS)0;
-    kw[15] = (TS)L.s;
+    for (int i = 0; i < KMSG; ++i) mw[i] = (TS)0;
 #pragma unroll
     for (int i = 6; i < 12; ++i) lw[i] = (TS)0;
     aw[0] = (TS)L.r0[0]; aw[1] = (TS)L.r0[1];
@@ -1410,6 +1423,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         T *tmp = (T *)scratch;
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 5: hipLaunchKernelGGL((k_gather<T, 5>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 10: hipLaunchKernelGGL((k_gather<T, 10>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
@@ -1418,6 +1432,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         (void)hipMemcpyAsync(arr, tmp, sizeof(T) * (size_t)w * nf, hipMemcpyDeviceToDevice, s);
     };
     run(d.krec, TS(0), KREC);
+    run(d.kmsg, TS(0), KMSG);
     run(d.lrec, TS(0), LREC);
     run(d.arec, TS(0), AREC);
     run(d.drec, TS(0), DREC);
