@@ -152,6 +152,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.krec, F * KREC * sizeof(TS));
     L.add((void **)&d.kmsg, F * KMSG * sizeof(TS));
     L.add((void **)&d.lrec, F * LREC * sizeof(TS));
+    L.add((void **)&d.mmsg, F * MMSG * sizeof(TS));
     L.add((void **)&d.arec, F * AREC * sizeof(TS));
     L.add((void **)&d.drec, F * DREC * sizeof(TS));
     L.add((void **)&d.cnt, F);

@@ -9,7 +9,8 @@ namespace gbp {
 
 constexpr int KREC = 12;  // keyframe-side Jacobian record per factor (see layout below)
 constexpr int KMSG = 5;   // message to the keyframe (dense, rewritten every iteration)
-constexpr int LREC = 12;  // landmark-side record per factor
+constexpr int LREC = 8;   // landmark-side Jacobian record per factor
+constexpr int MMSG = 5;   // message to the landmark (dense, rewritten every iteration)
 constexpr int AREC = 10;  // factor-private record read by the message update
 constexpr int DREC = 12;  // factor's linearisation point (check, features)
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
@@ -30,8 +31,8 @@ constexpr int MSG_W = 16;   // floats per exported factor-message row
 // iteration covers whole cache lines):
 //   [0..2] S (a, b, c) = [[a b][b c]]   [3..4] g (anchor-relative information
 //          vector in the factor's 2-D measurement space)
-// landmark-side record:
-//   [0..5]  d h / d l (2x3)   [6..8] S to landmark   [9..10] g to landmark
+// landmark-side record: [0..5] J_m (2x3), [6..7] pad; message to the
+// landmark (dense array): [0..2] S, [3..4] g
 // factor-private record:
 //   [0..1]  r0 = z - h(x0)   [2..3] J_k (x0_k - anchor_k)   [4..5] J_m (x0_m - anchor_m)
 //   [6..7]  J_k anchor_k     [8..9] J_m anchor_m
@@ -64,7 +65,7 @@ struct Dev {
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state
     const double *z;
-    TS *krec, *kmsg, *lrec, *arec, *drec;
+    TS *krec, *kmsg, *lrec, *mmsg, *arec, *drec;
     uint8_t *cnt, *flags;
     float *fdamp;                         // per-factor damping (learned model) or null
     const int *fallback;                  // per problem: 1 = learned damping switched off

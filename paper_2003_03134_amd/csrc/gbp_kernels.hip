@@ -95,6 +95,20 @@ __device__ __forceinline__ void load5(const TS *__restrict__ p, TS (&v)[5]) {
     for (int i = 0; i < 5; ++i) v[i] = p[i];  // 20-byte records: dword loads, coalesced across lanes
 }
 
+__device__ __forceinline__ void load8(const float *__restrict__ p, float (&v)[8]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        float4 a = q[i];
+        v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
+    }
+}
+__device__ __forceinline__ void load8(const double *__restrict__ p, double (&v)[8]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
+}
+
 __device__ __forceinline__ void load10(const float *__restrict__ p, float (&v)[10]) {
     const float2 *q = reinterpret_cast<const float2 *>(p);  // 40-byte records: 8-byte aligned
 #pragma unroll
@@ -452,11 +466,12 @@ template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
                                             const double *__restrict__ bk, TS *__restrict__ stage) {
     const int m = d.f_lm[f];
-    TS ar[AREC], kr[KREC], lr[LREC], km[KMSG];
+    TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
     load10(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
     load5(d.kmsg + (size_t)f * KMSG, km);
-    load12(d.lrec + (size_t)f * LREC, lr);
+    load8(d.lrec + (size_t)f * LREC, lr);
+    load5(d.mmsg + (size_t)f * MMSG, mm);
     int c = d.cnt[f];
     const uint8_t fl = d.flags[f];
 
@@ -484,7 +499,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     double s = (double)kr[10];
     double jak0 = (double)ar[6], jak1 = (double)ar[7], jam0 = (double)ar[8], jam1 = (double)ar[9];
     const double Ska = km[0], Skb = km[1], Skc = km[2], gk0 = km[3], gk1 = km[4];
-    const double Sma = lr[6], Smb = lr[7], Smc = lr[8], gm0 = lr[9], gm1 = lr[10];
+    const double Sma = mm[0], Smb = mm[1], Smc = mm[2], gm0 = mm[3], gm1 = mm[4];
 
     double Jkn[2][6], Jmn[2][3];
     uint8_t nfl = (uint8_t)((fl & ~FLAG_PENDING) | (RELIN ? FLAG_DONE : 0));
@@ -597,7 +612,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     TS *lw = d.lrec + (size_t)f * LREC;
     TS *mw = d.kmsg + (size_t)f * KMSG;  // dense: full-line writes
     mw[0] = (TS)oSk_a; mw[1] = (TS)oSk_b; mw[2] = (TS)oSk_c; mw[3] = (TS)ogk0; mw[4] = (TS)ogk1;
-    lw[6] = (TS)oSm_a; lw[7] = (TS)oSm_b; lw[8] = (TS)oSm_c; lw[9] = (TS)ogm0; lw[10] = (TS)ogm1;
+    TS *nw = d.mmsg + (size_t)f * MMSG;  // dense: full-line writes
+    nw[0] = (TS)oSm_a; nw[1] = (TS)oSm_b; nw[2] = (TS)oSm_c; nw[3] = (TS)ogm0; nw[4] = (TS)ogm1;
     if constexpr (RELIN) {
         TS *aw = d.arec + (size_t)f * AREC;
 #pragma unroll
@@ -872,10 +888,11 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.nf) return;
     const int k = d.f_kf[f], m = d.f_lm[f];
-    TS kr[KREC], lr[LREC], ar[AREC], dr[DREC], km[KMSG];
+    TS kr[KREC], lr[LREC], ar[AREC], dr[DREC], km[KMSG], mm[MMSG];
     load12(d.krec + (size_t)f * KREC, kr);
     load5(d.kmsg + (size_t)f * KMSG, km);
-    load12(d.lrec + (size_t)f * LREC, lr);
+    load8(d.lrec + (size_t)f * LREC, lr);
+    load5(d.mmsg + (size_t)f * MMSG, mm);
     load10(d.arec + (size_t)f * AREC, ar);
     load12(d.drec + (size_t)f * DREC, dr);
     const ProbParams pp = d.prob[d.kf_prob[k]];
@@ -891,7 +908,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
         ju0 += (double)lr[i] * e;
         ju1 += (double)lr[3 + i] * e;
     }
-    const float gk0 = km[3], gk1 = km[4], gm0 = lr[9], gm1 = lr[10], trS = (float)lr[6] + (float)lr[8];
+    const float gk0 = km[3], gk1 = km[4], gm0 = mm[3], gm1 = mm[4], trS = (float)mm[0] + (float)mm[2];
     float *h = hist + FHIST * (size_t)f;
     const bool have = h[7] > 0.5f;
     const float dk0 = gk0 - h[0], dk1 = gk1 - h[1], dm0 = gm0 - h[2], dm1 = gm1 - h[3];
@@ -960,7 +977,8 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     const TS *kr = d.krec + (size_t)f * KREC, *lr = d.lrec + (size_t)f * LREC;
     const TS *km = d.kmsg + (size_t)f * KMSG;
     for (int c = 0; c < 5; ++c) o[c] = (float)km[c];
-    for (int c = 0; c < 5; ++c) o[5 + c] = (float)lr[6 + c];
+    const TS *mm = d.mmsg + (size_t)f * MMSG;
+    for (int c = 0; c < 5; ++c) o[5 + c] = (float)mm[c];
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
     const TS *ar = d.arec + (size_t)f * AREC;
@@ -997,8 +1015,10 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     TS *mw = d.kmsg + (size_t)f * KMSG;
 #pragma unroll
     for (int i = 0; i < KMSG; ++i) mw[i] = (TS)0;
+    lw[6] = (TS)0; lw[7] = (TS)0;
+    TS *nw = d.mmsg + (size_t)f * MMSG;
 #pragma unroll
-    for (int i = 6; i < 12; ++i) lw[i] = (TS)0;
+    for (int i = 0; i < MMSG; ++i) nw[i] = (TS)0;
     aw[0] = (TS)L.r0[0]; aw[1] = (TS)L.r0[1];
     double jdk0 = 0, jdk1 = 0, jdm0 = 0, jdm1 = 0;
 #pragma unroll
@@ -1099,10 +1119,12 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
     double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
     if (live) {
         for (int ei = d.lm_row[m] + q; ei < d.lm_row[m + 1]; ei += LANES) {
-            TS r[LREC];
-            load12(d.lrec + (size_t)d.lm_edge[ei] * LREC, r);
+            const int fe = d.lm_edge[ei];
+            TS r[LREC], mr[MMSG];
+            load8(d.lrec + (size_t)fe * LREC, r);
+            load5(d.mmsg + (size_t)fe * MMSG, mr);
             double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
-            double Sa = r[6], Sb = r[7], Sc = r[8], g0 = r[9], g1 = r[10];
+            double Sa = mr[0], Sb = mr[1], Sc = mr[2], g0 = mr[3], g1 = mr[4];
             double SJ0[3], SJ1[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
@@ -1424,6 +1446,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 5: hipLaunchKernelGGL((k_gather<T, 5>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 8: hipLaunchKernelGGL((k_gather<T, 8>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 10: hipLaunchKernelGGL((k_gather<T, 10>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
@@ -1434,6 +1457,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
     run(d.krec, TS(0), KREC);
     run(d.kmsg, TS(0), KMSG);
     run(d.lrec, TS(0), LREC);
+    run(d.mmsg, TS(0), MMSG);
     run(d.arec, TS(0), AREC);
     run(d.drec, TS(0), DREC);
     run(d.cnt, uint8_t(0), 1);
