@@ -460,3 +460,61 @@ def test_large_problem_full_size_matches_oracle(gbp):
         o.relinearise(-1)
     print(f"large problem: worst relative mean error {worst:.2e}")
     s.close()
+
+
+def _with_isolated_variables(p):
+    """p plus one keyframe and one landmark that nothing observes."""
+    from synth import BAProblem
+    kf_extra = p.kf_init[-1] + np.array([0.0, 0.0, 0.0, 0.3, -0.2, 0.1])
+    lm_extra = np.array([[0.2, -0.1, 0.3]])
+    return BAProblem(p.name + "_isolated", p.cam, np.vstack([p.kf_true, kf_extra]),
+                     np.vstack([p.lm_true, lm_extra]), np.vstack([p.kf_init, kf_extra]),
+                     np.vstack([p.lm_init, lm_extra]), p.factor_kf, p.factor_lm, p.z, p.z_true,
+                     p.inlier, np.concatenate([p.kf_anchor_info, [0.0]]))
+
+
+def _empty_problem(cam):
+    from synth import BAProblem
+    kf = np.array([[0.1, -0.2, 0.05, 0.3, 0.0, 1.0]])
+    e2, e1 = np.zeros((0, 2)), np.zeros(0)
+    return BAProblem("empty", cam, kf, np.zeros((0, 3)), kf.copy(), np.zeros((0, 3)),
+                     np.zeros(0, np.int32), np.zeros(0, np.int32), e2, e2.copy(), e1.astype(bool),
+                     np.array([0.0]))
+
+
+def test_empty_problems_and_isolated_variables(gbp):
+    """Degenerate inputs: a problem with one keyframe and nothing else, and a
+    problem with a keyframe and a landmark that no factor touches, batched
+    with an ordinary one. Each agrees with the oracle run alone (FP64); a
+    variable without factors keeps its initial estimate (its belief is its
+    floored prior); the batch's error statistics of the empty problem are
+    zero."""
+    import oracle
+    base = synth.make_config0(seed=4)
+    iso = _with_isolated_variables(base)
+    empty = _empty_problem(base.cam)
+    probs = [empty, iso, synth.make_config0(seed=5)]
+    s = gbp.GBPSolver(probs, precision=gbp.GBP_FP64, anneal=False)
+    for _ in range(2):
+        s.iterate(10, 0.4, 2.0)
+        s.relinearise(-1)
+    g = s.beliefs()
+    kf_off = np.concatenate([[0], np.cumsum([p.n_keyframes for p in probs])])
+    lm_off = np.concatenate([[0], np.cumsum([p.n_landmarks for p in probs])])
+    for i, p in enumerate(probs):
+        o = oracle.Oracle(p, anneal=False)
+        for _ in range(2):
+            o.iterate(10, 0.4, 2.0)
+            o.relinearise(-1)
+        r = o.beliefs()
+        gk, gl = g["kf_mu"][kf_off[i]:kf_off[i + 1]], g["lm_mu"][lm_off[i]:lm_off[i + 1]]
+        assert rel_mean_err(gk, r["kf_mu"]) < 1e-8, i
+        if p.n_landmarks:
+            assert rel_mean_err(gl, r["lm_mu"]) < 1e-8, i
+    # isolated variables stay where they started
+    assert np.allclose(g["kf_mu"][kf_off[2] - 1], iso.kf_init[-1], atol=1e-12)
+    assert np.allclose(g["lm_mu"][lm_off[2] - 1], iso.lm_init[-1], atol=1e-12)
+    assert np.allclose(g["kf_mu"][0], empty.kf_init[0], atol=1e-12)
+    st = s.reproj(0)
+    assert st["n_valid"] == 0 and st["are_all"] == 0.0
+    s.close()
