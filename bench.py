@@ -140,6 +140,38 @@ def time_to_target(gbp):
     return res
 
 
+def studies_leg(trials):
+    """The robustness and Huber studies (Sections 9.3, 9.4) at one setting
+    each on the GPU, with the FP64 oracle timed on one trial of the same
+    setting beside them (the trials are independent problems, so the
+    oracle's time for the batch is trials x that)."""
+    import oracle
+    from paper_2003_03134_amd import studies
+    out = {}
+    cases = (("basin_fr1desk30_noise0.1m", [studies.basin_problem("fr1desk30", 0.1, t) for t in range(trials)],
+              dict(huber_k=2.0, log_every=5), 300),
+             ("outliers_20kf_3pct", [studies.outlier_problem(0.03, t) for t in range(trials)],
+              dict(huber_k=2.0, reference="measured"), 300),
+             ("no_huber_20kf_3pct", [studies.outlier_problem(0.03, t) for t in range(trials)],
+              dict(huber_k=0.0, reference="measured", log_every=10), 400))
+    for name, probs, kw, iters in cases:
+        studies.run_batch(probs, iters=iters, **kw)          # records the graph once
+        log_, wall, _ = studies.run_batch(probs, iters=iters, **kw)
+        nf = sum(p.n_factors for p in probs)
+        o = oracle.Oracle(probs[0], anneal=True, huber_k=kw["huber_k"])
+        t0 = time.perf_counter()
+        o.iterate(iters, 0.4, kw["huber_k"])
+        to = time.perf_counter() - t0
+        out[name] = dict(trials=trials, iters=iters, factors=nf, gpu_ms=round(wall * 1e3, 3),
+                         gpu_factor_updates_per_s=round(nf * iters / wall, 1),
+                         oracle_ms_one_trial=round(to * 1e3, 1),
+                         oracle_factor_updates_per_s=round(probs[0].n_factors * iters / to, 1),
+                         oracle_threads=oracle.threads())
+        log(f"study {name}: GPU {wall * 1e3:.1f} ms for {trials} trials x {iters} iterations; "
+            f"oracle {to * 1e3:.0f} ms for one trial")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +184,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--studies", type=int, default=0,
+                    help="also time the robustness / Huber studies with this many trials")
     ap.add_argument("--no-tune-cache", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (PMC counter reference)")
@@ -247,6 +281,8 @@ def main():
         extra["time_to_target"] = tt
         log(f"iterations to 1 px: plain {tt['plain']['iterations']}, learned {tt['learned']['iterations']}; "
             f"wall-time speed-up {tt['speedup']}")
+    if args.studies > 0:
+        extra["studies"] = studies_leg(args.studies)
     cpu = None
     if not args.no_cpu_baseline:
         log("FP64 oracle on a bounded sample (host cores)")

@@ -103,7 +103,10 @@ typedef struct {
     int64_t n_quadratic;
     int64_t n_linear;      /* factors in the linear (outlier) regime       */
     int64_t n_invalid;     /* factors with camera depth <= zmin            */
-    int64_t n_ref;
+    int64_t n_ref;         /* valid factors inside the reference mask      */
+    int64_t n_linear_ref;  /* of those, in the linear regime: with the mask
+                              marking true inliers, the outlier classes that
+                              are false positives (Section 9.4, Fig. 7a)  */
 } gbp_reproj;
 
 /* Fill opt with the paper's hyperparameters and FP32 storage. */
@@ -172,9 +175,10 @@ gbp_status gbp_set_reference(gbp_problem *p, const double *z_ref,
                              const uint8_t *mask);
 
 /* As gbp_iterate, and every log_every iterations records
- * {t, are_all, are_ref, n_linear} of every problem into a device log; the
- * log (n/log_every rows x n_problems x 4 doubles) is copied to log_out at
- * the end, with no host synchronisation in between. */
+ * {t, are_all, are_ref, n_linear, n_linear_ref} of every problem into a
+ * device log; the log (n/log_every rows x n_problems x GBP_LOG_COLS doubles)
+ * is copied to log_out at the end, with no host synchronisation in between. */
+#define GBP_LOG_COLS 5
 gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
                               double huber_k, int32_t log_every,
                               double *log_out);

@@ -173,7 +173,7 @@ class Oracle:
                     kf_eta=kf_eta, lm_eta=lm_eta)
 
     def reproj(self, zref=None, mask=None) -> dict:
-        out, po = _out(8)
+        out, po = _out(9)
         if zref is not None:
             zr, pzr = _d(zref)
             mk = np.ascontiguousarray(mask, dtype=np.uint8)
@@ -182,7 +182,8 @@ class Oracle:
             _lib().oracle_reproj(self.h, po, None, None)
         return dict(are_all=out[0], are_quadratic=out[1], n_valid=int(out[2]),
                     n_quadratic=int(out[3]), n_linear=int(out[4]),
-                    n_invalid=int(out[5]), are_ref=out[6], n_ref=int(out[7]))
+                    n_invalid=int(out[5]), are_ref=out[6], n_ref=int(out[7]),
+                    n_linear_ref=int(out[8]))
 
     def factor(self, f: int):
         eta, a = _out(9)

@@ -625,12 +625,15 @@ void oracle_beliefs(void *h, double *kf_mu, double *lm_mu, double *kf_lam,
  * reprojection error over the measurements; Section 9.4: a measurement is
  * classed an outlier when it lies in the linear Huber regime).
  * out = {are_all, are_quadratic, n_valid, n_quadratic, n_linear, n_invalid,
- *        are_ref, n_ref}; zref/mask optional (both or neither). */
+ *        are_ref, n_ref, n_linear_ref}; zref/mask optional (both or
+ * neither). n_linear_ref counts the linear-regime factors inside the mask:
+ * with the mask marking the true inliers, the measurements wrongly classed
+ * outliers (the precision of Fig. 7a). */
 void oracle_reproj(void *h, double *out, const double *zref, const unsigned char *mask) {
     oracle_t *o = h;
     double cam[4] = { o->fx, o->fy, o->cx, o->cy };
     double s_all = 0, s_q = 0, s_ref = 0;
-    long n_valid = 0, n_q = 0, n_lin = 0, n_inv = 0, n_ref = 0;
+    long n_valid = 0, n_q = 0, n_lin = 0, n_inv = 0, n_ref = 0, n_lin_ref = 0;
     double N = o->huber_k / o->sigma;
     for (int f = 0; f < o->nf; ++f) {
         double hp[2];
@@ -638,13 +641,17 @@ void oracle_reproj(void *h, double *out, const double *zref, const unsigned char
         if (!(pz > o->zmin)) { n_inv++; continue; }
         double e = hypot(o->z[2*f] - hp[0], o->z[2*f+1] - hp[1]);
         s_all += e; n_valid++;
-        if (N > 0.0 && e / o->sigma > N) n_lin++; else { s_q += e; n_q++; }
-        if (zref && mask && mask[f]) { s_ref += hypot(zref[2*f] - hp[0], zref[2*f+1] - hp[1]); n_ref++; }
+        int lin = N > 0.0 && e / o->sigma > N;
+        if (lin) n_lin++; else { s_q += e; n_q++; }
+        if (zref && mask && mask[f]) {
+            s_ref += hypot(zref[2*f] - hp[0], zref[2*f+1] - hp[1]); n_ref++;
+            if (lin) n_lin_ref++;
+        }
     }
     out[0] = n_valid ? s_all / n_valid : 0.0;
     out[1] = n_q ? s_q / n_q : 0.0;
     out[2] = (double)n_valid; out[3] = (double)n_q; out[4] = (double)n_lin; out[5] = (double)n_inv;
-    out[6] = n_ref ? s_ref / n_ref : 0.0; out[7] = (double)n_ref;
+    out[6] = n_ref ? s_ref / n_ref : 0.0; out[7] = (double)n_ref; out[8] = (double)n_lin_ref;
 }
 
 /* linearised factor f: eta (9), Lambda (81), linearisation point (9), weight */

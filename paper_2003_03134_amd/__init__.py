@@ -23,6 +23,7 @@ __all__ = ["GBPSolver", "GBPError", "GBP_FP32", "GBP_FP64", "GBP_DAMP_ETA",
 
 MLP_PARAMS = _capi.MLP_PARAMS
 MLP_FEATURES = _capi.MLP_FEATURES
+LOG_COLS = _capi.LOG_COLS
 
 
 class GBPError(RuntimeError):
@@ -179,11 +180,12 @@ class GBPSolver:
 
     def iterate_logged(self, n: int, damping: float = 0.4, huber_k: float | None = None,
                        log_every: int = 1) -> np.ndarray:
-        """Returns [n // log_every, n_problems, 4] rows of (t, are_all, are_ref, n_linear)."""
+        """Returns [n // log_every, n_problems, 5] rows of (t, are_all, are_ref,
+        n_linear, n_linear_ref)."""
         if huber_k is not None:
             self.huber_k = huber_k
         rows = n // log_every
-        out = np.zeros((max(rows, 1), self.n_problems, 4))
+        out = np.zeros((max(rows, 1), self.n_problems, LOG_COLS))
         self._check(self._lib.gbp_iterate_logged(self.h, int(n), float(damping), float(self.huber_k),
                                                  int(log_every), _ptr(out, C.c_double)), self.h)
         return out[:rows]
@@ -227,7 +229,7 @@ class GBPSolver:
         self._check(self._lib.gbp_reproj_stats(self.h, int(problem_index), C.byref(r)), self.h)
         return dict(are_all=r.are_all, are_quadratic=r.are_quadratic, are_ref=r.are_ref,
                     n_valid=r.n_valid, n_quadratic=r.n_quadratic, n_linear=r.n_linear,
-                    n_invalid=r.n_invalid, n_ref=r.n_ref)
+                    n_invalid=r.n_invalid, n_ref=r.n_ref, n_linear_ref=r.n_linear_ref)
 
     def reproj_error(self):
         a, q, n = C.c_double(), C.c_double(), C.c_int32()

@@ -51,7 +51,8 @@ class gbp_reproj(C.Structure):
     _fields_ = [("are_all", C.c_double), ("are_quadratic", C.c_double),
                 ("are_ref", C.c_double), ("n_valid", C.c_int64),
                 ("n_quadratic", C.c_int64), ("n_linear", C.c_int64),
-                ("n_invalid", C.c_int64), ("n_ref", C.c_int64)]
+                ("n_invalid", C.c_int64), ("n_ref", C.c_int64),
+                ("n_linear_ref", C.c_int64)]
 
 
 EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
@@ -63,6 +64,7 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
 
 MLP_PARAMS = 5378
+LOG_COLS = 5           # GBP_LOG_COLS: columns of a gbp_iterate_logged row
 MLP_FEATURES = 16
 
 _LIB = None

@@ -546,7 +546,7 @@ gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_b
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
         if (log_every > 0 && (i + 1) % log_every == 0)
             launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
-                              log_base + (size_t)((i + 1) / log_every - 1) * p->np * 4, s);
+                              log_base + (size_t)((i + 1) / log_every - 1) * p->np * GBP_LOG_COLS, s);
     }
     return GBP_OK;
 }
@@ -1082,13 +1082,15 @@ gbp_status reproj_impl(gbp_problem *p, std::vector<double> &sums) {
 
 void sums_to_stats(const double *s, gbp_reproj *o) {
     o->are_all = s[3] > 0 ? s[0] / s[3] : 0.0;
-    o->are_quadratic = s[4] > 0 ? s[1] / s[4] : 0.0;
+    const double nq = s[3] - s[5];  // valid factors in the quadratic regime
+    o->are_quadratic = nq > 0 ? s[1] / nq : 0.0;
     o->are_ref = s[7] > 0 ? s[2] / s[7] : 0.0;
     o->n_valid = (int64_t)s[3];
-    o->n_quadratic = (int64_t)s[4];
+    o->n_quadratic = (int64_t)nq;
     o->n_linear = (int64_t)s[5];
     o->n_invalid = (int64_t)s[6];
     o->n_ref = (int64_t)s[7];
+    o->n_linear_ref = (int64_t)s[4];
 }
 
 template <typename TS>
@@ -1167,7 +1169,7 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping, double 
     if (n < 0 || log_every < 1 || !log_out || !(damping >= 0.0 && damping < 1.0))
         return fail(p, GBP_EINVAL, "need n >= 0, log_every >= 1, a log buffer and 0 <= damping < 1");
     const size_t rows = (size_t)(n / log_every);
-    const size_t bytes = std::max<size_t>(rows, 1) * p->np * 4 * 8;
+    const size_t bytes = std::max<size_t>(rows, 1) * p->np * GBP_LOG_COLS * 8;
     if (bytes > p->log_cap) {
         destroy_graphs(p);  // graphs may reference the old log buffer
         if (p->d_log) (void)hipFree(p->d_log);
@@ -1178,7 +1180,7 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping, double 
     st = p->precision == GBP_FP32 ? iterate_impl<float>(p, n, damping, huber_k, log_every, p->d_log)
                                   : iterate_impl<double>(p, n, damping, huber_k, log_every, p->d_log);
     if (st != GBP_OK) return st;
-    if (rows) HIP_TRY(p, hipMemcpyAsync(log_out, p->d_log, rows * p->np * 4 * 8, hipMemcpyDeviceToHost, p->stream));
+    if (rows) HIP_TRY(p, hipMemcpyAsync(log_out, p->d_log, rows * p->np * GBP_LOG_COLS * 8, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     return GBP_OK;
 }

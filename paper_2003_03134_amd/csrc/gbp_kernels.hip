@@ -39,6 +39,7 @@
 // bitwise reproducible run to run. No floating-point atomics are used.
 
 #include "gbp_internal.h"
+#include "../../include/gbp.h"
 
 #include <hip/hip_ext.h>
 
@@ -1203,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
 
 // Per-block partial statistics over the factor range of one block (blocks
 // never straddle problems; one factor per lane): {sum_all, sum_quad,
-// sum_ref, n_valid, n_quad, n_lin, n_inv, n_ref}, reduced in a fixed order
+// sum_ref, n_valid, n_lin_ref, n_lin, n_inv, n_ref}, reduced in a fixed order
 // (a butterfly inside each wave, then the four waves in order).
 template <typename TS>
 __global__ __launch_bounds__(RBLK) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
@@ -1230,11 +1231,13 @@ __global__ __launch_bounds__(RBLK) void k_reproj_block(Dev<TS> d, double huber_k
             const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
             acc[0] = e;
             acc[3] = 1.0;
-            if (N > 0.0 && e / pp.sigma > N) acc[5] = 1.0;
-            else { acc[1] = e; acc[4] = 1.0; }
+            const bool lin = N > 0.0 && e / pp.sigma > N;
+            if (lin) acc[5] = 1.0;
+            else acc[1] = e;
             if (zref && mask[f]) {
                 acc[2] = hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
                 acc[7] = 1.0;
+                if (lin) acc[4] = 1.0;
             }
         }
     }
@@ -1278,10 +1281,12 @@ __global__ __launch_bounds__(64) void k_reproj_reduce(const double *part, const 
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[8 * (size_t)p + i] = acc[i];
     if (log_row) {
-        log_row[4 * (size_t)p + 0] = (double)t_dev[0];
-        log_row[4 * (size_t)p + 1] = acc[3] > 0 ? acc[0] / acc[3] : 0.0;
-        log_row[4 * (size_t)p + 2] = acc[7] > 0 ? acc[2] / acc[7] : 0.0;
-        log_row[4 * (size_t)p + 3] = acc[5];
+        double *r = log_row + GBP_LOG_COLS * (size_t)p;
+        r[0] = (double)t_dev[0];
+        r[1] = acc[3] > 0 ? acc[0] / acc[3] : 0.0;
+        r[2] = acc[7] > 0 ? acc[2] / acc[7] : 0.0;
+        r[3] = acc[5];
+        r[4] = acc[4];
     }
 }
 

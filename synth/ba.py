@@ -216,6 +216,8 @@ def _count_sampler(kind, rng):
         return lambda: int(rng.choice(ns, p=p))
     if kind == "uniform4_12":
         return lambda: int(rng.integers(4, 13))
+    if kind == "sparse":           # clamp(2 + Poisson(2.6), 2, 20): ~4.6 per point
+        return lambda: int(np.clip(2 + rng.poisson(2.6), 2, 20))
     raise ValueError(kind)
 
 

@@ -26,6 +26,14 @@ def test_header_declarations_are_exported(capi):
     assert declared == set(capi.EXPORTS)
 
 
+def test_header_constants_match_the_binding(capi):
+    text = open(os.path.join(ROOT, "include", "gbp.h")).read()
+    assert int(re.search(r"#define GBP_LOG_COLS (\d+)", text).group(1)) == capi.LOG_COLS
+    fields = re.search(r"typedef struct \{([^}]*)\} gbp_reproj;", text).group(1)
+    names = re.findall(r"\b(?:double|int64_t)\s+(\w+);", fields)
+    assert names == [n for n, _ in capi.gbp_reproj._fields_]
+
+
 def test_default_options_are_the_papers(capi):
     lib = capi.load()
     o = capi.gbp_options()

@@ -241,15 +241,16 @@ def test_reproj_stats_and_log(gbp):
     s, o = pair(gbp, prob, gbp.GBP_FP64)
     s.set_reference(prob.z_true, prob.inlier)
     log = s.iterate_logged(20, 0.4, 2.0, log_every=5)
-    assert log.shape == (4, 1, 4)
+    assert log.shape == (4, 1, 5)
     for row in log[:, 0]:
         o.iterate(5, 0.4, 2.0)
         r = o.reproj(prob.z_true, prob.inlier)
         assert int(row[0]) == o.t
         assert abs(row[1] - r["are_all"]) < 1e-8 and abs(row[2] - r["are_ref"]) < 1e-8
-        assert int(row[3]) == r["n_linear"]
+        assert int(row[3]) == r["n_linear"] and int(row[4]) == r["n_linear_ref"]
     rg, ro = s.reproj(), o.reproj(prob.z_true, prob.inlier)
-    for key in ("n_valid", "n_quadratic", "n_linear", "n_invalid", "n_ref"):
+    assert 0 < ro["n_linear_ref"] < ro["n_linear"]
+    for key in ("n_valid", "n_quadratic", "n_linear", "n_invalid", "n_ref", "n_linear_ref"):
         assert rg[key] == ro[key], key
     for key in ("are_all", "are_quadratic", "are_ref"):
         assert abs(rg[key] - ro[key]) < 1e-8, key

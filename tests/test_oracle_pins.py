@@ -371,6 +371,12 @@ def test_reprojection_error_brute_force(oracle_mod):
     assert abs(r["are_quadratic"] - e[valid & ~lin].mean()) < 1e-10
     eref = np.linalg.norm(p.z_true - hz, axis=1)
     assert abs(r["are_ref"] - eref[valid & p.inlier].mean()) < 1e-10
+    # outlier classification (Section 9.4): linear-regime true inliers are
+    # the false positives; with 5% outliers after 15 iterations both kinds
+    # of linear-regime factor occur
+    assert r["n_ref"] == (valid & p.inlier).sum()
+    assert r["n_linear_ref"] == (lin & p.inlier).sum()
+    assert 0 < r["n_linear_ref"] < r["n_linear"]
 
 
 def test_point_behind_camera_carries_no_information(oracle_mod):
