@@ -162,9 +162,9 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.t_dev, 4);
     L.add((void **)&d.status, 4);
     L.add((void **)&d.pending_k, 8);
-    const size_t QB = (F + 255) / 256 + 1;
-    L.add((void **)&d.relin_queue, QB * 256 * 4);
-    L.add((void **)&d.relin_qcount, QB * 4);
+    // relinearisation queue: one segment per residual block (F / RBLK + P + 1)
+    L.add((void **)&d.relin_queue, (F / RBLK + P + 1) * RBLK * 4);
+    L.add((void **)&d.relin_qcount, (F / RBLK + P + 1) * 4);
     L.add((void **)&d.kf_sums, K * 32 * 8);
     L.add((void **)&p->d_total, 8);
     L.add((void **)&d.kf_pose, K * 12 * 8);
@@ -442,7 +442,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
-    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)(p->cap_f + 255) / 256 + 1) * 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
 #undef UP
     p->fdamp_buf = d.fdamp;
@@ -528,7 +528,7 @@ gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const
 template <typename TS>
 void record_model(gbp_problem *p, hipStream_t s) {
     Dev<TS> &d = dev<TS>(p);
-    launch_reproj<TS>(d, p->huber_k, nullptr, nullptr, nullptr, s);
+    launch_reproj<TS>(d, p->iopt, p->huber_k, nullptr, nullptr, nullptr, s);
     launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.status, s);
     launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
     launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
@@ -538,15 +538,33 @@ template <typename TS>
 gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_base) {
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
+    const double *zref = p->has_ref ? p->d_zref : nullptr;
+    const uint8_t *mask = p->has_ref ? p->d_mask : nullptr;
+    auto model_at = [&](int i) { return p->learned && (p->t + i) % p->every_k == 0; };
+    // A logged iteration followed by another (with no model evaluation in
+    // between) runs the next iteration's relinearisation check inside its
+    // residual pass, and the next relinearisation launch reduces the
+    // residual statistics: two launches fewer per logged iteration.
+    bool checked = false;
+    double *pending_row = nullptr;
     for (int i = 0; i < n; ++i) {
-        if (p->learned && (p->t + i) % p->every_k == 0) record_model<TS>(p, s);
-        launch_check<TS>(d, p->iopt, s);
-        launch_relin<TS>(d, p->iopt, s);
-        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
-        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
-        if (log_every > 0 && (i + 1) % log_every == 0)
-            launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
-                              log_base + (size_t)((i + 1) / log_every - 1) * p->np * GBP_LOG_COLS, s);
+        if (model_at(i)) record_model<TS>(p, s);
+        if (!checked) launch_check<TS>(d, p->iopt, s);
+        launch_relin<TS>(d, p->iopt, s, pending_row);
+        checked = false;
+        pending_row = nullptr;
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, false);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, true);
+        if (log_every > 0 && (i + 1) % log_every == 0) {
+            double *row = log_base + (size_t)((i + 1) / log_every - 1) * p->np * GBP_LOG_COLS;
+            if (i + 1 < n && !model_at(i + 1)) {
+                launch_reproj_check<TS>(d, p->iopt, p->huber_k, zref, mask, s);
+                checked = true;
+                pending_row = row;
+            } else {
+                launch_reproj<TS>(d, p->iopt, p->huber_k, zref, mask, row, s);
+            }
+        }
     }
     return GBP_OK;
 }
@@ -612,8 +630,8 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 3], s));
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 4], s));
-        launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr,
-                          nullptr, s);
+        launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? p->d_zref : nullptr,
+                          p->has_ref ? p->d_mask : nullptr, nullptr, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 5], s));
     }
     HIP_TRY(p, hipGetLastError());
@@ -647,8 +665,8 @@ gbp_status time_config(gbp_problem *p, int n, double *ms) {
     for (int i = 0; i < n; ++i) {
         launch_check<TS>(d, p->iopt, s);
         launch_relin<TS>(d, p->iopt, s);
-        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s);
-        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, false);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, true);
     }
     HIP_TRY(p, hipEventRecord(b, s));
     HIP_TRY(p, hipGetLastError());
@@ -1000,7 +1018,7 @@ gbp_status reset_impl(gbp_problem *p) {
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
-    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)(p->cap_f + 255) / 256 + 1) * 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
     launch_linearise<TS>(d, 0, p->nf, p->huber_k, nullptr, s);
     launch_prior_base<TS>(d, 0, 0, s);
@@ -1071,7 +1089,7 @@ gbp_status beliefs_impl(gbp_problem *p, double *kf_mean, double *lm_mean, double
 template <typename TS>
 gbp_status reproj_impl(gbp_problem *p, std::vector<double> &sums) {
     Dev<TS> &d = dev<TS>(p);
-    launch_reproj<TS>(d, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr, nullptr,
+    launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr, nullptr,
                       p->stream);
     HIP_TRY(p, hipGetLastError());
     sums.resize((size_t)p->np * 8);
@@ -1364,7 +1382,8 @@ gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
     const int *qc = p->precision == GBP_FP32 ? p->df.relin_qcount : p->dd.relin_qcount;
-    launch_relin_total(qc, (p->nf + 255) / 256, p->d_total, p->stream);
+    const int nb = p->precision == GBP_FP32 ? p->df.n_rblk : p->dd.n_rblk;
+    launch_relin_total(qc, nb, p->d_total, p->stream);
     HIP_TRY(p, hipGetLastError());
     unsigned long long v = 0;
     HIP_TRY(p, hipMemcpyAsync(&v, p->d_total, 8, hipMemcpyDeviceToHost, p->stream));

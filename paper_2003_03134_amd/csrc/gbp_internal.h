@@ -16,7 +16,9 @@ constexpr int DREC = 12;  // factor's linearisation point (check, features)
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
 constexpr int MAX_ANNEAL = 64;
-constexpr int RBLK = 256;   // factors per residual-phase block (one per lane)
+constexpr int RTHREADS = 256;          // threads of a residual-phase block
+constexpr int RPL = 1;                 // factors per lane in the residual phase (more: slower, latency-bound)
+constexpr int RBLK = RTHREADS * RPL;   // factors per residual-phase block
 constexpr int LM_LANES = 4;  // default lanes per landmark in the landmark belief kernel
 constexpr int NFEAT = 16;   // learned-model features per factor
 constexpr int FHIST = 12;   // floats of per-factor feature history
@@ -74,8 +76,8 @@ struct Dev {
     int *t_dev;                           // iteration clock
     unsigned *status;                     // bit 0: non-PD belief, bit 1: non-finite
     double *pending_k;                    // Huber threshold for requested relinearisations
-    int *relin_queue;                     // factors due for relinearisation, 256 per check block
-    int *relin_qcount;                    // queue entries of each check block
+    int *relin_queue;                     // factors due for relinearisation, RBLK per residual block
+    int *relin_qcount;                    // queue entries of each residual block
     double *kf_sums;                      // per keyframe: 21 information + 6 vector sums (32)
     double *kf_pose;                      // absolute R (9) and t (3) of each keyframe mean
     // residual phase: blocks of at most RBLK factors inside one problem
@@ -101,15 +103,23 @@ template <typename TS> void launch_linearise(const Dev<TS> &d, int f0, int f1, d
                                              hipStream_t s);
 template <typename TS> void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s);
 template <typename TS> void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
-template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s);
+// pending_log_row: also reduce the statistics of a preceding launch_reproj_check
+template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s,
+                                         double *pending_log_row = nullptr);
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s);
+// solve = false leaves the keyframe solve to launch_belief_lm(..., with_kf = true)
 template <typename TS> void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s,
-                                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
+                                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool solve = true);
+template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s,
+                                             bool with_kf = false);
 template <typename TS> void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s);
-template <typename TS> void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref,
+template <typename TS> void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref,
                                           const uint8_t *mask, double *log_row, hipStream_t s);
+// residual partials of every block plus the next iteration's check (the
+// statistics are reduced by the next launch_relin)
+template <typename TS> void launch_reproj_check(const Dev<TS> &d, const IterOpts &o, double huber_k,
+                                                const double *zref, const uint8_t *mask, hipStream_t s);
 template <typename TS> void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf,
                                                    void *scratch, float *fdamp, float *hist, hipStream_t s);
 template <typename TS> void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist,

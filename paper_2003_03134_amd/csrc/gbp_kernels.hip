@@ -451,10 +451,13 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 // --------------------------------------------------------------------------
 //
 // One iteration runs k_check (relinearisation check; due factors go to a
-// queue), k_relin (queued factors relinearise and send their messages),
-// k_factor_kf (one workgroup per keyframe: every other factor of the
-// keyframe sends its messages, then the keyframe's new belief is formed from
-// all of its factors' messages in the same kernel) and k_belief_lm.
+// queue per residual block), k_relin (queued factors relinearise and send
+// their messages), k_factor_kf (one workgroup per keyframe: every other
+// factor of the keyframe sends its messages, then the keyframe's message sums
+// are formed in the same kernel) and k_belief_lm (landmark beliefs, with the
+// keyframe solves of those sums in its first workgroups). When the residual
+// statistics are logged, k_reproj_block also runs the next iteration's check
+// and k_relin reduces the statistics, so a logged iteration is four launches.
 // Factors are stored sorted by keyframe, so a workgroup's keyframe belief is
 // a uniform (scalar) load and its factor records are contiguous.
 
@@ -646,51 +649,101 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 
 // Relinearisation check (Section 5, Section 8): a pending request, or at
 // least `interval` updates since the last linearisation and the stacked means
-// farther than beta from the linearisation point. Each workgroup compacts
-// its due factors into its own queue segment (wave ballots and a prefix over
-// the workgroup's waves), so no atomics are needed. Also advances the clock.
+// farther than beta from the linearisation point. bk, bm: the keyframe and
+// landmark mean offsets.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_check(Dev<TS> d, IterOpts o) {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int f = blk * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
-    bool need = false;
-    if (f < d.nf) {
-        const uint8_t fl = d.flags[f];
-        if (fl & FLAG_PENDING) {
-            need = true;
-        } else if (d.cnt[f] >= o.interval) {
-            const int k = d.f_kf[f], m = d.f_lm[f];
-            const TS *dr = d.drec + (size_t)f * DREC;
-            const double *bk = d.kf_bel + (size_t)k * KBEL;
-            const double *bm = d.lm_bel + (size_t)m * LBEL;
-            double dist2 = 0.0;
+__device__ __forceinline__ bool check_due(const Dev<TS> &d, const IterOpts &o, const int f,
+                                          const double *__restrict__ bk, const double *__restrict__ bm) {
+    const uint8_t fl = d.flags[f];
+    if (fl & FLAG_PENDING) return true;
+    if (d.cnt[f] < o.interval) return false;
+    const TS *dr = d.drec + (size_t)f * DREC;
+    double dist2 = 0.0;
 #pragma unroll
-            for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
+    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)dr[6 + i]; dist2 += e * e; }
-            need = dist2 > o.beta2;
-        }
-    }
-    __shared__ int wcount[4];
+    for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)dr[6 + i]; dist2 += e * e; }
+    return dist2 > o.beta2;
+}
+
+// The due factors of residual block b (RTHREADS threads, all calling) go to
+// the block's own queue segment (wave ballots and a prefix over the block's
+// waves: no atomics).
+template <typename TS>
+__device__ __forceinline__ void queue_due(const Dev<TS> &d, const int b, const int f, const bool need) {
+    __shared__ int wcount[RTHREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(need);
     if (lane == 0) wcount[wave] = __popcll(mask);
     __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wave; ++w) base += wcount[w];
-    if (need) d.relin_queue[(size_t)blk * 256 + base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
-    if (threadIdx.x == 0) d.relin_qcount[blk] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < RTHREADS / 64; ++w) {
+        base += w < wave ? wcount[w] : 0;
+        tot += wcount[w];
+    }
+    if (need) d.relin_queue[(size_t)b * RBLK + base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
+    if (threadIdx.x == 0) d.relin_qcount[b] = tot;
 }
 
-// queue segment of check-workgroup b: relinearise and send (marks done);
-// one wave per segment, since a segment holds few due factors in steady state
+// Standalone check over the residual blocks (one factor per thread); also
+// advances the clock.
 template <typename TS>
-__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o) {
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int n = d.relin_qcount[blk];
+__global__ __launch_bounds__(RTHREADS) void k_check(Dev<TS> d, IterOpts o) {
+    static_assert(RPL == 1, "one factor per thread per residual block");
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = d.rblk_start[b] + (int)threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
+    bool need = false;
+    if (f < d.rblk_start[b + 1])
+        need = check_due(d, o, f, d.kf_bel + (size_t)d.f_kf[f] * KBEL, d.lm_bel + (size_t)d.f_lm[f] * LBEL);
+    queue_due(d, b, f, need);
+}
+
+// One problem's residual statistics from its blocks' partials (64 threads):
+// lane l adds blocks l, l + 64, ... in order, then a butterfly adds the lanes
+// (a fixed order: deterministic). Writes the 8 sums to out (if set) and a log
+// row {t, are_all, are_ref, n_linear, n_linear_ref} (if set), t being the
+// clock plus t_off.
+__device__ __forceinline__ void reduce_problem(const double *part, const int *prob_blk, const int p, double *out,
+                                               double *log_row, const int *t_dev, const int t_off) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = prob_blk[p] + (int)threadIdx.x; b < prob_blk[p + 1]; b += 64)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += part[8 * (size_t)b + i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (threadIdx.x != 0) return;
+    if (out)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[8 * (size_t)p + i] = acc[i];
+    if (log_row) {
+        double *r = log_row + GBP_LOG_COLS * (size_t)p;
+        r[0] = (double)(t_dev[0] + t_off);
+        r[1] = acc[3] > 0 ? acc[0] / acc[3] : 0.0;
+        r[2] = acc[7] > 0 ? acc[2] / acc[7] : 0.0;
+        r[3] = acc[5];
+        r[4] = acc[4];
+    }
+}
+
+// Queue segment of residual block b: relinearise and send (marks done); one
+// wave per segment, since a segment holds few due factors in steady state.
+// Workgroups nseg .. nseg + np - 1, when present, reduce the residual
+// statistics of the previous iteration's fused residual pass (whose check
+// advanced the clock: t_off -1) into log_row.
+template <typename TS>
+__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o, int nseg, double *log_row) {
+    if ((int)blockIdx.x >= nseg) {
+        reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
+        return;
+    }
+    const int b = xcd_remap(blockIdx.x, nseg);
+    const int n = d.relin_qcount[b];
     for (int i = threadIdx.x; i < n; i += 64) {
-        const int f = d.relin_queue[(size_t)blk * 256 + i];
+        const int f = d.relin_queue[(size_t)b * RBLK + i];
         const int k = d.f_kf[f];
         factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
     }
@@ -1109,12 +1162,32 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
 // --------------------------------------------------------------------------
 
 
-template <typename TS, int LANES>
-__global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout) {
+template <typename TS, int LANES, bool WITH_KF>
+__global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout, int nkb) {
+    // WITH_KF: the first nkb workgroups turn the keyframe message sums into
+    // keyframe beliefs (one thread per keyframe, as k_kf_solve), overlapping
+    // that short serial solve with the landmark beliefs, which do not depend
+    // on it.
+    int bid = blockIdx.x, nb = gridDim.x;
+    if constexpr (WITH_KF) {
+        if (bid < nkb) {
+            const int k = bid * blockDim.x + threadIdx.x;
+            if (k < d.nk) {
+                double sm[27];
+                const double *src = d.kf_sums + 32 * (size_t)k;
+#pragma unroll
+                for (int i = 0; i < 27; ++i) sm[i] = src[i];
+                kf_solve<TS>(d, o, k, sm, 0);
+            }
+            return;
+        }
+        bid -= nkb;
+        nb -= nkb;
+    }
     // LANES lanes per landmark: lane q of a group sums edges q, q + LANES,
     // ... (in order), then the group adds its partial sums with a fixed
     // butterfly; every lane of the group ends with the same sums
-    const int gid = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int gid = xcd_remap(bid, nb) * blockDim.x + threadIdx.x;
     const int m = gid / LANES, q = gid % LANES;
     const bool live = m < d.nl;
     double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
@@ -1203,91 +1276,96 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
 // --------------------------------------------------------------------------
 
 // Per-block partial statistics over the factor range of one block (blocks
-// never straddle problems; one factor per lane): {sum_all, sum_quad,
-// sum_ref, n_valid, n_lin_ref, n_lin, n_inv, n_ref}, reduced in a fixed order
-// (a butterfly inside each wave, then the four waves in order).
-template <typename TS>
-__global__ __launch_bounds__(RBLK) void k_reproj_block(Dev<TS> d, double huber_k, const double *zref,
-                                                       const uint8_t *mask) {
+// never straddle problems): {sum_all, sum_quad, sum_ref, n_valid, n_lin_ref,
+// n_lin, n_inv, n_ref}. Each lane takes the block's factors tid, tid + 256,
+// ... in order; the wave adds its three error sums with a butterfly and
+// counts its flags with ballots, then the four waves are added in order (a
+// fixed order: deterministic). CHECK: the same pass also runs the next
+// iteration's relinearisation check on the updated beliefs (sharing the
+// factor's indices and landmark mean) and advances the clock, so the next
+// iteration needs no separate check.
+template <typename TS, bool CHECK>
+__global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o, double huber_k,
+                                                           const double *zref, const uint8_t *mask) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int f0 = d.rblk_start[b], f1 = d.rblk_start[b + 1];
     const ProbParams pp = d.prob[d.rblk_prob[b]];
     const double N = huber_k / pp.sigma;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int f = f0 + (int)threadIdx.x;
-    if (f < f1) {
-        const int k = d.f_kf[f], m = d.f_lm[f];
-        const double *ps = d.kf_pose + 12 * (size_t)k;
-        double l[3];
+    if (CHECK && blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
+    double s_all = 0.0, s_quad = 0.0, s_ref = 0.0;
+    int c_valid = 0, c_lin_ref = 0, c_lin = 0, c_inv = 0, c_ref = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool need = false;
+    int fq = f0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + d.lm_bel[(size_t)m * LBEL + i];
-        double p[3];
+    for (int r = 0; r < RPL; ++r) {
+        const int f = f0 + r * RTHREADS + (int)threadIdx.x;
+        bool valid = false, lin = false, inv = false, ref = false;
+        if (f < f1) {
+            const int k = d.f_kf[f], m = d.f_lm[f];
+            const double *ps = d.kf_pose + 12 * (size_t)k;
+            const double *bm = d.lm_bel + (size_t)m * LBEL;
+            double l[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) p[i] = ps[3 * i] * l[0] + ps[3 * i + 1] * l[1] + ps[3 * i + 2] * l[2] + ps[9 + i];
-        if (!(p[2] > pp.zmin)) {
-            acc[6] = 1.0;
-        } else {
-            const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
-            const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
-            acc[0] = e;
-            acc[3] = 1.0;
-            const bool lin = N > 0.0 && e / pp.sigma > N;
-            if (lin) acc[5] = 1.0;
-            else acc[1] = e;
-            if (zref && mask[f]) {
-                acc[2] = hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
-                acc[7] = 1.0;
-                if (lin) acc[4] = 1.0;
+            for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + bm[i];
+            if (CHECK) {
+                need = check_due(d, o, f, d.kf_bel + (size_t)k * KBEL, bm);
+                fq = f;
+            }
+            double p[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) p[i] = ps[3 * i] * l[0] + ps[3 * i + 1] * l[1] + ps[3 * i + 2] * l[2] + ps[9 + i];
+            if (!(p[2] > pp.zmin)) {
+                inv = true;
+            } else {
+                const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
+                const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
+                valid = true;
+                s_all += e;
+                lin = N > 0.0 && e / pp.sigma > N;
+                if (!lin) s_quad += e;
+                if (zref && mask[f]) {
+                    s_ref += hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
+                    ref = true;
+                }
             }
         }
+        c_valid += __popcll(__ballot(valid));
+        c_lin += __popcll(__ballot(lin));
+        c_inv += __popcll(__ballot(inv));
+        c_ref += __popcll(__ballot(ref));
+        c_lin_ref += __popcll(__ballot(lin && ref));
+    }
+    if constexpr (CHECK) {
+        static_assert(RPL == 1, "the fused check takes one factor per thread");
+        queue_due(d, b, fq, need);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-    __shared__ double sh[RBLK / 64][8];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane < 8) {
-        double v = acc[0];
-#pragma unroll
-        for (int i = 1; i < 8; ++i) v = (lane == i) ? acc[i] : v;
-        sh[wave][lane] = v;
+    for (int off = 32; off >= 1; off >>= 1) {
+        s_all += __shfl_xor(s_all, off, 64);
+        s_quad += __shfl_xor(s_quad, off, 64);
+        s_ref += __shfl_xor(s_ref, off, 64);
+    }
+    __shared__ double sh[RTHREADS / 64][8];
+    if (lane == 0) {
+        sh[wave][0] = s_all; sh[wave][1] = s_quad; sh[wave][2] = s_ref; sh[wave][3] = (double)c_valid;
+        sh[wave][4] = (double)c_lin_ref; sh[wave][5] = (double)c_lin; sh[wave][6] = (double)c_inv;
+        sh[wave][7] = (double)c_ref;
     }
     __syncthreads();
     if (threadIdx.x < 8) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < RBLK / 64; ++w) s += sh[w][threadIdx.x];
+        for (int w = 0; w < RTHREADS / 64; ++w) s += sh[w][threadIdx.x];
         d.rblk_part[8 * (size_t)b + threadIdx.x] = s;
     }
 }
 
-// one wave per problem: lane l sums blocks l, l + 64, ... of the problem in
-// order, then a butterfly adds the lanes (a fixed order: deterministic)
+// one wave per problem (reduce_problem)
 __global__ __launch_bounds__(64) void k_reproj_reduce(const double *part, const int *prob_blk, int np,
-                                                      double *out, double *log_row, const int *t_dev) {
-    const int p = blockIdx.x;
-    if (p >= np) return;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = prob_blk[p] + (int)threadIdx.x; b < prob_blk[p + 1]; b += 64)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += part[8 * (size_t)b + i];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-    if (threadIdx.x != 0) return;
-    if (out)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) out[8 * (size_t)p + i] = acc[i];
-    if (log_row) {
-        double *r = log_row + GBP_LOG_COLS * (size_t)p;
-        r[0] = (double)t_dev[0];
-        r[1] = acc[3] > 0 ? acc[0] / acc[3] : 0.0;
-        r[2] = acc[7] > 0 ? acc[2] / acc[7] : 0.0;
-        r[3] = acc[5];
-        r[4] = acc[4];
-    }
+                                                      double *out, double *log_row, const int *t_dev, int t_off) {
+    if ((int)blockIdx.x >= np) return;
+    reduce_problem(part, prob_blk, (int)blockIdx.x, out, log_row, t_dev, t_off);
 }
 
 __global__ void k_tick(int *t_dev) { t_dev[0] = t_dev[0] + 1; }
@@ -1374,7 +1452,7 @@ void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
 // extension that records ev0 / ev1 at the kernel's own start and end.
 template <typename TS, int MODE>
 static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s,
-                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool solve = true) {
     const dim3 g(d.n_kf_slots);
     auto go = [&](auto kern, int bs) {
         if (ev0)
@@ -1387,17 +1465,21 @@ static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readou
         case 256: go(k_factor_kf<TS, 256, MODE>, 256); break;
         default: go(k_factor_kf<TS, 128, MODE>, 128); break;
     }
-    hipLaunchKernelGGL(k_kf_solve<TS>, dim3(blocks(d.nk, 64)), dim3(64), 0, s, d, o, readout);
+    if (solve) hipLaunchKernelGGL(k_kf_solve<TS>, dim3(blocks(d.nk, 64)), dim3(64), 0, s, d, o, readout);
 }
 
 template <typename TS>
 void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
-    hipLaunchKernelGGL(k_check<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(256), 0, s, d, o);
+    if (d.n_rblk > 0)
+        hipLaunchKernelGGL(k_check<TS>, dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o);
+    else
+        hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, d.t_dev);  // the clock still advances
 }
 
 template <typename TS>
-void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
-    hipLaunchKernelGGL(k_relin<TS>, dim3(blocks(d.nf > 0 ? d.nf : 1, 256)), dim3(64), 0, s, d, o);
+void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
+    const int g = d.n_rblk + (pending_log_row ? d.np : 0);
+    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(64), 0, s, d, o, d.n_rblk, pending_log_row);
 }
 
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
@@ -1406,17 +1488,20 @@ void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipS
 
 template <typename TS>
 void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1) {
-    launch_kf<TS, 0>(d, o, block, 0, s, ev0, ev1);
+                      hipEvent_t ev1, bool solve) {
+    launch_kf<TS, 0>(d, o, block, 0, s, ev0, ev1, solve);
 }
 
 template <typename TS>
-void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s) {
-    if (d.nl <= 0) return;
+void launch_belief_lm(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s, bool with_kf) {
+    const int nkb = with_kf ? blocks(d.nk, block) : 0;
+    const int nlb = d.nl > 0 ? blocks((long)d.nl * d.lm_lanes, block) : 0;
+    if (nkb + nlb == 0) return;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(nkb + nlb), dim3(block), 0, s, d, o, readout, nkb); };
     switch (d.lm_lanes) {
-        case 2: hipLaunchKernelGGL((k_belief_lm<TS, 2>), dim3(blocks(d.nl * 2, block)), dim3(block), 0, s, d, o, readout); break;
-        case 8: hipLaunchKernelGGL((k_belief_lm<TS, 8>), dim3(blocks(d.nl * 8, block)), dim3(block), 0, s, d, o, readout); break;
-        default: hipLaunchKernelGGL((k_belief_lm<TS, 4>), dim3(blocks(d.nl * 4, block)), dim3(block), 0, s, d, o, readout); break;
+        case 2: with_kf ? go(k_belief_lm<TS, 2, true>) : go(k_belief_lm<TS, 2, false>); break;
+        case 8: with_kf ? go(k_belief_lm<TS, 8, true>) : go(k_belief_lm<TS, 8, false>); break;
+        default: with_kf ? go(k_belief_lm<TS, 4, true>) : go(k_belief_lm<TS, 4, false>); break;
     }
 }
 
@@ -1431,12 +1516,23 @@ void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s)
 }
 
 template <typename TS>
-void launch_reproj(const Dev<TS> &d, double huber_k, const double *zref, const uint8_t *mask, double *log_row,
-                   hipStream_t s) {
+void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref, const uint8_t *mask,
+                   double *log_row, hipStream_t s) {
     if (d.n_rblk > 0)
-        hipLaunchKernelGGL(k_reproj_block<TS>, dim3(d.n_rblk), dim3(RBLK), 0, s, d, huber_k, zref, mask);
+        hipLaunchKernelGGL((k_reproj_block<TS, false>), dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o, huber_k, zref,
+                           mask);
     hipLaunchKernelGGL(k_reproj_reduce, dim3(d.np), dim3(64), 0, s, (const double *)d.rblk_part,
-                       d.prob_rblk, d.np, log_row ? (double *)nullptr : d.are_out, log_row, (const int *)d.t_dev);
+                       d.prob_rblk, d.np, log_row ? (double *)nullptr : d.are_out, log_row, (const int *)d.t_dev, 0);
+}
+
+template <typename TS>
+void launch_reproj_check(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref,
+                         const uint8_t *mask, hipStream_t s) {
+    if (d.n_rblk > 0)
+        hipLaunchKernelGGL((k_reproj_block<TS, true>), dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o, huber_k, zref,
+                           mask);
+    else
+        hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, d.t_dev);
 }
 
 template <typename TS>
@@ -1508,14 +1604,16 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
     template void launch_linearise<TS>(const Dev<TS> &, int, int, double, const int *, hipStream_t);               \
     template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
     template void launch_check<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
-    template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
+    template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t, double *);                      \
     template void launch_factor_kf<TS>(const Dev<TS> &, const IterOpts &, int, hipStream_t, hipEvent_t,            \
-                                       hipEvent_t);                                                              \
-    template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
+                                       hipEvent_t, bool);                                                        \
+    template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t, bool);            \
     template void launch_belief_kf<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
-    template void launch_reproj<TS>(const Dev<TS> &, double, const double *, const uint8_t *, double *,            \
-                                    hipStream_t);                                                                 \
+    template void launch_reproj<TS>(const Dev<TS> &, const IterOpts &, double, const double *, const uint8_t *,    \
+                                    double *, hipStream_t);                                                       \
+    template void launch_reproj_check<TS>(const Dev<TS> &, const IterOpts &, double, const double *,               \
+                                          const uint8_t *, hipStream_t);                                          \
     template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, float *, float *,         \
                                              hipStream_t);              \
     template void launch_depth_move<TS>(const Dev<TS> &, const int *, int, const float *, hipStream_t);            \

@@ -257,6 +257,31 @@ def test_reproj_stats_and_log(gbp):
     s.close()
 
 
+def test_logging_leaves_the_iteration_unchanged(gbp):
+    """A logged iteration runs the next iteration's relinearisation check
+    inside its residual pass and the next relinearisation launch reduces the
+    statistics; the beliefs, the relinearisation count and the clock are
+    bitwise those of unlogged iterations, for every logging period."""
+    probs = [synth.make_config3_problem(p) for p in range(3)]
+    plain = gbp.GBPSolver(probs)
+    plain.iterate(37, 0.4, 2.0)
+    ref = plain.beliefs()
+    plain.iterate(1, 0.4, 2.0)
+    n_ref = plain.last_relinearised
+    for every in (1, 2, 5, 37):
+        s = gbp.GBPSolver(probs)
+        log = s.iterate_logged(37, 0.4, 2.0, log_every=every)
+        assert log.shape == (37 // every, 3, 5)
+        assert np.array_equal(log[:, 0, 0], np.arange(1, 37 // every + 1) * every)
+        got = s.beliefs()
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (every, key)
+        s.iterate(1, 0.4, 2.0)
+        assert s.last_relinearised == n_ref and s.t == plain.t
+        s.close()
+    plain.close()
+
+
 # --------------------------------------------------------------------------
 # autotuner and incremental growth
 # --------------------------------------------------------------------------
