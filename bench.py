@@ -140,6 +140,57 @@ def time_to_target(gbp):
     return res
 
 
+def learned_kernels_leg(n_rows):
+    """The learned network's kernels at the workload's size: inference over
+    one feature row per factor (k_mlp_infer: 10496 flop and 72 B per row)
+    and training steps on batches of 8192 rows (forward, backward, gradient
+    reduction, Adam), timed with HIP events on the stream they run on."""
+    import numpy as np
+    import torch
+    import paper_2003_03134_amd as gbp
+    from paper_2003_03134_amd import learned
+    w, theta, _ = learned.load_weights()
+    wt = torch.as_tensor(w.view(np.int16)).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(n_rows, gbp.MLP_FEATURES, device="cuda", generator=gen)
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(3):
+        gbp.mlp_infer(wt, x)
+    reps = 20
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for _ in range(reps):
+        gbp.mlp_infer(wt, x)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    flop, nbytes = 2 * (16 * 64 + 64 * 64 + 64 * 2), 16 * 4 + 2 * 4
+    infer = dict(rows=n_rows, ms=round(ms, 4), tflops=round(n_rows * flop / ms / 1e9, 2),
+                 gbps=round(n_rows * nbytes / ms / 1e6, 1),
+                 frac_hbm=round(n_rows * nbytes / ms / 1e6 / HBM_PEAK_GBS, 3),
+                 frac_mfma_bf16=round(n_rows * flop / ms / 1e9 / 2500.0, 4))
+    nb, nd = 8192, 1 << 16
+    tr = gbp.MLPTrainer(theta, max_batch=nb)
+    y = torch.rand(nd, 2, device="cuda", generator=gen)
+    tr.set_data(x[:nd], y, torch.ones_like(y))
+    idx = [torch.randint(0, nd, (nb,), device="cuda", generator=gen, dtype=torch.int32) for _ in range(4)]
+    for i in range(3):
+        tr.step(idx[i % 4])
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for i in range(reps):
+        tr.step(idx[i % 4])
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms_t = ev[0].elapsed_time(ev[1]) / reps
+    train = dict(batch=nb, ms_per_step=round(ms_t, 4), samples_per_s=round(nb / ms_t * 1e3, 1),
+                 tflops=round(nb * 3 * flop / ms_t / 1e9, 3))
+    log(f"learned kernels: inference {ms:.3f} ms for {n_rows} rows ({infer['gbps']} GB/s, "
+        f"{infer['tflops']} TFLOP/s); training step {ms_t:.3f} ms for {nb} rows")
+    return dict(infer=infer, train=train)
+
+
 def studies_leg(trials):
     """The robustness and Huber studies (Sections 9.3, 9.4) at one setting
     each on the GPU, with the FP64 oracle timed on one trial of the same
@@ -184,6 +235,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--no-learned-kernels", action="store_true",
+                    help="skip timing the learned network's inference and training kernels")
     ap.add_argument("--studies", type=int, default=0,
                     help="also time the robustness / Huber studies with this many trials")
     ap.add_argument("--no-tune-cache", action="store_true")
@@ -281,6 +334,8 @@ def main():
         extra["time_to_target"] = tt
         log(f"iterations to 1 px: plain {tt['plain']['iterations']}, learned {tt['learned']['iterations']}; "
             f"wall-time speed-up {tt['speedup']}")
+    if not args.no_learned_kernels:
+        extra["learned_kernels"] = learned_kernels_leg(nf)
     if args.studies > 0:
         extra["studies"] = studies_leg(args.studies)
     cpu = None

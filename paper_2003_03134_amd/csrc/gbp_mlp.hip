@@ -7,14 +7,17 @@
 // FP32 for training): W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
 //
 // Inference (k_mlp_infer) is the only dense contraction on the path: layers 1
-// and 2 run on the matrix cores with v_mfma_f32_32x32x8_bf16 (32 rows per
-// wave, 32-column output tiles); the 64 -> 2 head is a per-lane dot product.
+// and 2 run on the matrix cores with v_mfma_f32_32x32x16_bf16 (32 rows per
+// tile, computed transposed so activations stay in registers); the 64 -> 2
+// head is a per-lane dot product.
 // Training (k_mlp_train_block, k_mlp_reduce, k_adam) evaluates the same
 // BF16-rounded forward pass per sample and back-propagates in FP32; block
 // partial gradients are summed in block order, so training is deterministic.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "gbp_mlp.h"
 
@@ -41,88 +44,137 @@ __device__ __forceinline__ void heads(float o0, float o1, float &d, float &delta
 }
 
 // --------------------------------------------------------------------------
-// inference: 4 waves x 32 rows per workgroup
+// inference: persistent waves over tiles of 32 rows
 // --------------------------------------------------------------------------
+//
+// Each layer is computed transposed, H^T = W X^T, with
+// v_mfma_f32_32x32x16_bf16: the weights are the A operand (lane l: row l % 32,
+// k slots 8 (l / 32) + 0..7) and stay in registers for the kernel's life; the
+// activations of 32 rows are the B operand (lane l: column = row l % 32 of
+// the tile, same k slots). The accumulator of a 32x32 tile holds, in lane l
+// and entry q, hidden unit 8 (q / 4) + 4 (l / 32) + q % 4 of row l % 32: the
+// 8 entries 8 c .. 8 c + 7 of one lane are exactly the 8 k slots the next
+// layer's B operand needs from that lane, once that layer's A operand (the
+// weight columns) is taken in the same hidden-unit order (hid() below). So
+// activations never leave registers and need no transpose through LDS. The
+// 64 -> 2 head is a per-lane dot product over the lane's 32 hidden units plus
+// one exchange between the two lane halves.
 
-constexpr int HS = MLP_H + 4;  // padded LDS row (bf16 elements)
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ __bf16 bf_bits(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// hidden unit held by k slot j (0..7) of k-step kk (0..3) in lane half hh,
+// i.e. accumulator entry 8 (kk % 2) + j of hidden block kk / 2
+__device__ __forceinline__ int hid(int kk, int hh, int j) {
+    return 32 * (kk >> 1) + 8 * (2 * (kk & 1) + (j >> 2)) + 4 * hh + (j & 3);
+}
+
+constexpr int INFER_WAVES_MAX = 2048;  // 256 CUs x 8 waves
+
+// one tile's features, converted to BF16 (round to nearest even) in the
+// layer-1 B operand layout: row tile * 32 + r, features 8 hh .. 8 hh + 7
+__device__ __forceinline__ bf16x8_t load_x(const float *__restrict__ X, int n, int tile, int r, int hh) {
+    const int row = tile * 32 + r;
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
+    if (row < n) {
+        const float4 *xp = reinterpret_cast<const float4 *>(X + (size_t)row * MLP_IN + 8 * hh);
+        u = xp[0];
+        v = xp[1];
+    }
+    bf16x8_t x;
+    x[0] = (__bf16)u.x; x[1] = (__bf16)u.y; x[2] = (__bf16)u.z; x[3] = (__bf16)u.w;
+    x[4] = (__bf16)v.x; x[5] = (__bf16)v.y; x[6] = (__bf16)v.z; x[7] = (__bf16)v.w;
+    return x;
+}
+
+// relu(acc + bias) of one 32x32 accumulator, rounded to BF16, as two B
+// operands
+__device__ __forceinline__ void relu_operands(const f32x16_t &acc, const f32x16_t &bias, bf16x8_t &lo,
+                                              bf16x8_t &hi) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        lo[q] = (__bf16)fmaxf(acc[q] + bias[q], 0.f);
+        hi[q] = (__bf16)fmaxf(acc[8 + q] + bias[8 + q], 0.f);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ X, int n,
                                                    const uint16_t *__restrict__ P, float *__restrict__ out_d,
                                                    float *__restrict__ out_delta) {
-    __shared__ uint16_t sW1[MLP_H * MLP_IN], sW2[MLP_H * MLP_H], sW3[MLP_OUT * MLP_H];
-    __shared__ float sb1[MLP_H], sb2[MLP_H], sb3[MLP_OUT];
-    __shared__ uint16_t sH1[4][32 * HS], sH2[4][32 * HS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < MLP_H * MLP_IN; i += 256) sW1[i] = P[O_W1 + i];
-    for (int i = tid; i < MLP_H * MLP_H; i += 256) sW2[i] = P[O_W2 + i];
-    for (int i = tid; i < MLP_OUT * MLP_H; i += 256) sW3[i] = P[O_W3 + i];
-    for (int i = tid; i < MLP_H; i += 256) { sb1[i] = bf2f(P[O_B1 + i]); sb2[i] = bf2f(P[O_B2 + i]); }
-    if (tid < MLP_OUT) sb3[tid] = bf2f(P[O_B3 + tid]);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5, r = lane & 31;
+    // weights as A operands; the head's two output rows padded to 32 with
+    // zeros so that it runs on the matrix cores as well
+    bf16x8_t w1[2], w2[2][4], w3[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w1[mt][j] = bf_bits(P[O_W1 + (32 * mt + r) * MLP_IN + 8 * hh + j]);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w2[mt][kk][j] = bf_bits(P[O_W2 + (32 * mt + r) * MLP_H + hid(kk, hh, j)]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w3[kk][j] = bf_bits(r < MLP_OUT ? P[O_W3 + r * MLP_H + hid(kk, hh, j)] : 0);
+    // biases (LDS), added to the finished sums as in the reference order
+    // (sum first, then bias): entry q of hidden block mt is unit
+    // 32 mt + 8 (q / 4) + 4 hh + q % 4, four consecutive units per float4
+    __shared__ float4 sb[2][MLP_H / 4];
+    if (tid < MLP_H) reinterpret_cast<float *>(sb[0])[tid] = bf2f(P[O_B1 + tid]);
+    else if (tid < 2 * MLP_H) reinterpret_cast<float *>(sb[1])[tid - MLP_H] = bf2f(P[O_B2 + tid - MLP_H]);
+    const float b30 = bf2f(P[O_B3]), b31 = bf2f(P[O_B3 + 1]);
     __syncthreads();
-    const int row0 = (blockIdx.x * 4 + wave) * 32;
-    const int r = lane & 31, kq = (lane >> 5) * 4;  // operand row / k offset of this lane
-    // layer 1: H1 = relu(X W1^T + b1)
-    {
-        const int xr = row0 + r;
-        bf16x4_t a[2];
+    auto bias = [&](int layer, int mt) {
+        f32x16_t acc;
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
+        for (int a = 0; a < 4; ++a) {
+            const float4 v = sb[layer][8 * mt + 2 * a + hh];
+            acc[4 * a] = v.x; acc[4 * a + 1] = v.y; acc[4 * a + 2] = v.z; acc[4 * a + 3] = v.w;
+        }
+        return acc;
+    };
+
+    const int ntiles = (n + 31) / 32;
+    const int stride = gridDim.x * (blockDim.x / 64);
+    int tile = blockIdx.x * (blockDim.x / 64) + wave;
+    bf16x8_t x = load_x(X, n, tile < ntiles ? tile : 0, r, hh);
+    for (; tile < ntiles; tile += stride) {
+        // the next tile's features are in flight while this one computes
+        const int next = tile + stride;
+        const bf16x8_t xn = load_x(X, n, next < ntiles ? next : tile, r, hh);
+        // layer 1: H1^T = relu(W1 X^T + b1)
+        bf16x8_t h1[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                a[kk][j] = (short)(xr < n ? f2bf(X[(size_t)xr * MLP_IN + kk * 8 + kq + j]) : 0);
+        for (int mt = 0; mt < 2; ++mt) {
+            const f32x16_t zero = {0};
+            const f32x16_t acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[mt], x, zero, 0, 0, 0);
+            relu_operands(acc, bias(0, mt), h1[2 * mt], h1[2 * mt + 1]);
+        }
+        // layer 2: H2^T = relu(W2 H1^T + b2)
+        bf16x8_t h2[4];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
+        for (int mt = 0; mt < 2; ++mt) {
             f32x16_t acc = {0};
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                bf16x4_t b;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = (short)sW1[(nt * 32 + r) * MLP_IN + kk * 8 + kq + j];
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[kk], b, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3), c = nt * 32 + r;
-                const float v = acc[q] + sb1[c];
-                sH1[wave][i * HS + c] = f2bf(v > 0.f ? v : 0.f);
-            }
+            for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2[mt][kk], h1[kk], acc, 0, 0, 0);
+            relu_operands(acc, bias(1, mt), h2[2 * mt], h2[2 * mt + 1]);
         }
-    }
-    __syncthreads();
-    // layer 2: H2 = relu(H1 W2^T + b2)
+        // head: O^T = W3 H2^T (rows 0 and 1 land in lanes 0..31), then b3
+        f32x16_t o = {0};
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16_t acc = {0};
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            bf16x4_t a, b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                a[j] = (short)sH1[wave][r * HS + kk * 8 + kq + j];
-                b[j] = (short)sW2[(nt * 32 + r) * MLP_H + kk * 8 + kq + j];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3[kk], h2[kk], o, 0, 0, 0);
+        const int row = tile * 32 + r;
+        if (hh == 0 && row < n) {
+            float d, delta;
+            heads(o[0] + b30, o[1] + b31, d, delta);
+            out_d[row] = d;
+            if (out_delta) out_delta[row] = delta;
         }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3), c = nt * 32 + r;
-            const float v = acc[q] + sb2[c];
-            sH2[wave][i * HS + c] = f2bf(v > 0.f ? v : 0.f);
-        }
-    }
-    __syncthreads();
-    // head: lane (r, o) computes output o of row r
-    const int o = lane >> 5;
-    float s = sb3[o];
-#pragma unroll 8
-    for (int k = 0; k < MLP_H; ++k) s += bf2f(sH2[wave][r * HS + k]) * bf2f(sW3[o * MLP_H + k]);
-    const float other = __shfl_xor(s, 32, 64);
-    const int xr = row0 + r;
-    if (xr < n && o == 0) {
-        float d, delta;
-        heads(s, other, d, delta);
-        out_d[xr] = d;
-        if (out_delta) out_delta[xr] = delta;
+        x = xn;
     }
 }
 
@@ -279,7 +331,10 @@ __global__ void k_to_bf16(const float *__restrict__ theta, uint16_t *__restrict_
 }
 
 void launch_mlp_infer(const float *X, int n, const uint16_t *P, float *out_d, float *out_delta, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_mlp_infer, dim3((n + 127) / 128), dim3(256), 0, s, X, n, P, out_d, out_delta);
+    if (n > 0) {
+        const int waves = std::min((n + 31) / 32, INFER_WAVES_MAX);
+        hipLaunchKernelGGL(k_mlp_infer, dim3((waves + 3) / 4), dim3(256), 0, s, X, n, P, out_d, out_delta);
+    }
 }
 
 void launch_mlp_train_step(const float *X, const float *Y, const float *M, int n_rows, const int *idx, int n_batch,
