@@ -56,6 +56,9 @@ def _lib():
         lib.oracle_huber_weight.argtypes = [C.c_double, C.c_double]
         lib.oracle_huber_weight.restype = C.c_double
         lib.oracle_threads.restype = C.c_int
+        lib.oracle_add_pairs.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip, _dp, _dp]
+        lib.oracle_add_pairs.restype = C.c_int
+        lib.oracle_pair_messages.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
         _LIB = lib
     return _LIB
 
@@ -214,6 +217,32 @@ class Oracle:
         inv = np.zeros(self.nf, dtype=np.uint8)
         _lib().oracle_counters(self.h, cnt.ctypes.data_as(_ip), inv.ctypes.data_as(_up))
         return cnt, inv
+
+    def add_pairs(self, kind: int, a, b, z, prec) -> None:
+        """Pairwise difference factors (kind 0: keyframes, D = 6; kind 1:
+        landmarks, D = 3): x_b - x_a ~ N(z, diag(prec)^-1)."""
+        D = 6 if kind == 0 else 3
+        a_, pa = _i(np.asarray(a).ravel())
+        b_, pb = _i(np.asarray(b).ravel())
+        z_, pz = _d(np.asarray(z, dtype=np.float64).reshape(-1, D))
+        p_, pp = _d(np.asarray(prec, dtype=np.float64).reshape(-1, D))
+        if not (len(a_) == len(b_) == len(z_) == len(p_)):
+            raise ValueError("a, b, z and prec need one entry per factor")
+        self._keep += [a_, b_, z_, p_]
+        if _lib().oracle_add_pairs(self.h, int(kind), len(a_), pa, pb, pz, pp) != 0:
+            raise ValueError("oracle_add_pairs rejected the factors")
+        self.n_pairs = getattr(self, "n_pairs", [0, 0])
+        self.n_pairs[kind] += len(a_)
+
+    def pair_messages(self, kind: int) -> dict:
+        D = 6 if kind == 0 else 3
+        n = getattr(self, "n_pairs", [0, 0])[kind]
+        ae, pa = _out((n, D))
+        al, pb = _out((n, D, D))
+        be, pc = _out((n, D))
+        bl, pd = _out((n, D, D))
+        _lib().oracle_pair_messages(self.h, int(kind), pa, pb, pc, pd)
+        return dict(a_eta=ae, a_lam=al, b_eta=be, b_lam=bl)
 
     def add(self, kf_init, lm_init, f_kf, f_lm, z, kf_anchor_info=None) -> None:
         kf_init = np.atleast_2d(np.asarray(kf_init, dtype=np.float64)).reshape(-1, 6)

@@ -29,7 +29,11 @@
  *   - hyperparameters (beta = 0.01, at most every 10 iterations, d = 0.4,
  *     undamped for 8 iterations after relinearising, priors built from the
  *     Jacobians and weakened to a hundredth over 10 iterations): Section 8;
- *   - average reprojection error: Section 9.1.
+ *   - average reprojection error: Section 9.1;
+ *   - heterogeneous factors (the outlook of Sections 9 and 10: factors from
+ *     further priors and sensors in the same graph): pairwise difference
+ *     factors between two keyframes or two landmarks, whose messages follow
+ *     the same eqs. (messageeta), (messagelambda).
  *
  * Readings where the paper is silent (documented with the design notes):
  *   - a keyframe is x = (omega, t), world->camera, R = Exp(omega);
@@ -52,7 +56,15 @@
  *     has a proper belief;
  *   - a factor whose point lies at camera depth <= zmin at the linearisation
  *     point carries no information until it is relinearised again and is
- *     excluded from the reprojection error.
+ *     excluded from the reprojection error;
+ *   - a pairwise difference factor between variables a and b of the same
+ *     kind (dimension D = 6 for keyframes, 3 for landmarks) measures
+ *     x_b - x_a ~ N(z, diag(p)^-1): it is linear, never relinearised, and
+ *     its information form is Lambda = [P, -P; -P, P], eta = [-P z; P z]
+ *     with P = diag(p); its messages are damped like a measurement factor's
+ *     (eta only unless damp_lambda; undamped for its first `undamped`
+ *     updates after it was added); belief sums take the measurement
+ *     factors' messages first, then the pairwise ones in pair order.
  *
  * Every loop runs over factors or variables in increasing index order; a
  * variable sums its incoming messages in increasing factor index order.
@@ -100,7 +112,19 @@ typedef struct {
     /* adjacency: factors of each variable, increasing factor index */
     int *k_ptr, *k_adj, *l_ptr, *l_adj;
     int adj_dirty;
+    /* pairwise difference factors: kind 0 between keyframes, 1 between
+     * landmarks; per factor: ends a, b, z and diagonal precision (D each),
+     * update count, messages to a and b (eta D, Lambda D x D) and scratch */
+    struct pairs {
+        int n, cap;
+        int *a, *b, *cnt;
+        double *z, *p;
+        double *ma_eta, *ma_lam, *mb_eta, *mb_lam;
+        double *na_eta, *na_lam, *nb_eta, *nb_lam;
+    } pr[2];
 } oracle_t;
+
+static int pair_dim(int kind) { return kind == 0 ? 6 : 3; }
 
 /* --------------------------------------------------------------------------
  * small dense linear algebra
@@ -330,11 +354,13 @@ static void lm_prior(const oracle_t *o, int m, int t, double *lam_diag, double *
 }
 
 /* Belief of every variable at clock o->t: prior plus the sum of incoming
- * factor messages (eqs. (beliefeta), (belieflambda)); mean = Lambda^-1 eta. */
+ * factor messages (eqs. (beliefeta), (belieflambda)); mean = Lambda^-1 eta.
+ * Measurement-factor messages are added first (increasing factor index),
+ * then the pairwise factors' (increasing pair index). */
 static int update_beliefs(oracle_t *o) {
     if (o->adj_dirty) build_adjacency(o);
     int bad = 0;
-#pragma omp parallel for schedule(static) reduction(+:bad)
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < o->nk; ++k) {
         double *eta = o->kf_eta + (size_t)k * KD, *lam = o->kf_lam + (size_t)k * KD * KD;
         double pd[KD], pe[KD];
@@ -348,12 +374,8 @@ static int update_beliefs(oracle_t *o) {
             for (int i = 0; i < KD; ++i) eta[i] += o->mk_eta[(size_t)f*KD + i];
             for (int i = 0; i < KD*KD; ++i) lam[i] += o->mk_lam[(size_t)f*KD*KD + i];
         }
-        double mu[KD];
-        memcpy(mu, eta, sizeof mu);
-        if (solve_dense(KD, lam, mu, 1) != 0) { bad++; continue; }
-        memcpy(o->kf_mu + (size_t)k * KD, mu, sizeof mu);
     }
-#pragma omp parallel for schedule(static) reduction(+:bad)
+#pragma omp parallel for schedule(static)
     for (int m = 0; m < o->nl; ++m) {
         double *eta = o->lm_eta + (size_t)m * LD, *lam = o->lm_lam + (size_t)m * LD * LD;
         double pd[LD], pe[LD];
@@ -367,12 +389,83 @@ static int update_beliefs(oracle_t *o) {
             for (int i = 0; i < LD; ++i) eta[i] += o->ml_eta[(size_t)f*LD + i];
             for (int i = 0; i < LD*LD; ++i) lam[i] += o->ml_lam[(size_t)f*LD*LD + i];
         }
+    }
+    for (int kind = 0; kind < 2; ++kind) {
+        const struct pairs *q = &o->pr[kind];
+        const int D = pair_dim(kind);
+        double *veta = kind == 0 ? o->kf_eta : o->lm_eta, *vlam = kind == 0 ? o->kf_lam : o->lm_lam;
+        for (int f = 0; f < q->n; ++f) {
+            for (int i = 0; i < D; ++i) {
+                veta[(size_t)q->a[f]*D + i] += q->ma_eta[(size_t)f*D + i];
+                veta[(size_t)q->b[f]*D + i] += q->mb_eta[(size_t)f*D + i];
+            }
+            for (int i = 0; i < D*D; ++i) {
+                vlam[(size_t)q->a[f]*D*D + i] += q->ma_lam[(size_t)f*D*D + i];
+                vlam[(size_t)q->b[f]*D*D + i] += q->mb_lam[(size_t)f*D*D + i];
+            }
+        }
+    }
+#pragma omp parallel for schedule(static) reduction(+:bad)
+    for (int k = 0; k < o->nk; ++k) {
+        double mu[KD];
+        memcpy(mu, o->kf_eta + (size_t)k * KD, sizeof mu);
+        if (solve_dense(KD, o->kf_lam + (size_t)k * KD * KD, mu, 1) != 0) { bad++; continue; }
+        memcpy(o->kf_mu + (size_t)k * KD, mu, sizeof mu);
+    }
+#pragma omp parallel for schedule(static) reduction(+:bad)
+    for (int m = 0; m < o->nl; ++m) {
         double mu[LD];
-        memcpy(mu, eta, sizeof mu);
-        if (solve_dense(LD, lam, mu, 1) != 0) { bad++; continue; }
+        memcpy(mu, o->lm_eta + (size_t)m * LD, sizeof mu);
+        if (solve_dense(LD, o->lm_lam + (size_t)m * LD * LD, mu, 1) != 0) { bad++; continue; }
         memcpy(o->lm_mu + (size_t)m * LD, mu, sizeof mu);
     }
     return bad;
+}
+
+/* Messages of pairwise factor f (kind: 0 keyframes, 1 landmarks) to both
+ * ends, eqs. (messageeta), (messagelambda) for the factor Lambda = [P, -P;
+ * -P, P], eta = [-P z; P z]: the message to one end marginalises the other
+ * end's block after adding that end's variable-to-factor message (its
+ * belief minus this factor's previous message to it). */
+static int pair_messages(oracle_t *o, int kind, int f, double damping) {
+    struct pairs *q = &o->pr[kind];
+    const int D = pair_dim(kind);
+    const double *veta = kind == 0 ? o->kf_eta : o->lm_eta, *vlam = kind == 0 ? o->kf_lam : o->lm_lam;
+    const double *z = q->z + (size_t)f * D, *p = q->p + (size_t)f * D;
+    const double d_eff = (q->cnt[f] < o->undamped) ? 0.0 : damping;
+    for (int side = 0; side < 2; ++side) {
+        /* side 0: message to b (marginalise a); side 1: message to a */
+        const int u = side == 0 ? q->a[f] : q->b[f];
+        const double *mu_eta = (side == 0 ? q->ma_eta : q->mb_eta) + (size_t)f * D;
+        const double *mu_lam = (side == 0 ? q->ma_lam : q->mb_lam) + (size_t)f * D * D;
+        const double *old_eta = (side == 0 ? q->mb_eta : q->ma_eta) + (size_t)f * D;
+        const double *old_lam = (side == 0 ? q->mb_lam : q->ma_lam) + (size_t)f * D * D;
+        double *out_eta = (side == 0 ? q->nb_eta : q->na_eta) + (size_t)f * D;
+        double *out_lam = (side == 0 ? q->nb_lam : q->na_lam) + (size_t)f * D * D;
+        /* factor blocks seen from the receiving end v: Lambda_vv = P,
+         * Lambda_vu = -P, Lambda_uu = P, eta_v = +-P z, eta_u = -+P z */
+        const double sv = side == 0 ? 1.0 : -1.0;
+        double A[KD*KD], X[KD*(KD+1)];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                /* Lambda_uu + (belief_u - message_u) */
+                A[r*D + c] = (r == c ? p[r] : 0.0) + vlam[(size_t)u*D*D + r*D + c] - mu_lam[r*D + c];
+                X[r*(D+1) + c] = (r == c ? -p[r] : 0.0);                      /* Lambda_uv */
+            }
+        for (int r = 0; r < D; ++r)
+            X[r*(D+1) + D] = -sv * p[r] * z[r] + veta[(size_t)u*D + r] - mu_eta[r]; /* eta_u + v_eta_u */
+        if (solve_dense(D, A, X, D + 1) != 0) return -1;
+        for (int r = 0; r < D; ++r) {
+            /* eta_v - Lambda_vu X_eta, Lambda_vv - Lambda_vu X_Lambda */
+            double se = sv * p[r] * z[r] + p[r] * X[r*(D+1) + D];
+            out_eta[r] = (1.0 - d_eff) * se + d_eff * old_eta[r];
+            for (int c = 0; c < D; ++c) {
+                double sl = (r == c ? p[r] : 0.0) + p[r] * X[r*(D+1) + c];
+                out_lam[r*D + c] = o->damp_lambda ? (1.0 - d_eff) * sl + d_eff * old_lam[r*D + c] : sl;
+            }
+        }
+    }
+    return 0;
 }
 
 /* Messages of factor f to its keyframe (block 0..5) and landmark (6..8),
@@ -568,6 +661,12 @@ void oracle_destroy(void *h) {
                    o->ml_eta, o->ml_lam, o->nk_eta, o->nk_lam, o->nl_eta, o->nl_lam,
                    o->k_ptr, o->k_adj, o->l_ptr, o->l_adj };
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; ++i) free(ps[i]);
+    for (int kind = 0; kind < 2; ++kind) {
+        struct pairs *q = &o->pr[kind];
+        void *qs[] = { q->a, q->b, q->cnt, q->z, q->p, q->ma_eta, q->ma_lam, q->mb_eta,
+                       q->mb_lam, q->na_eta, q->na_lam, q->nb_eta, q->nb_lam };
+        for (size_t i = 0; i < sizeof qs / sizeof qs[0]; ++i) free(qs[i]);
+    }
     free(o);
 }
 
@@ -597,6 +696,18 @@ int oracle_iterate(void *h, int n, double damping, double huber_k) {
         for (int f = 0; f < o->nf; ++f) {
             if (factor_messages(o, f, damping) != 0) bad++;
             o->cnt[f] += 1;
+        }
+        for (int kind = 0; kind < 2; ++kind) {
+            struct pairs *q = &o->pr[kind];
+            for (int f = 0; f < q->n; ++f) {
+                if (pair_messages(o, kind, f, damping) != 0) bad++;
+                q->cnt[f] += 1;
+            }
+            double *u;
+            u = q->ma_eta; q->ma_eta = q->na_eta; q->na_eta = u;
+            u = q->ma_lam; q->ma_lam = q->na_lam; q->na_lam = u;
+            u = q->mb_eta; q->mb_eta = q->nb_eta; q->nb_eta = u;
+            u = q->mb_lam; q->mb_lam = q->nb_lam; q->nb_lam = u;
         }
         if (bad) return -1;
         double *t;
@@ -749,6 +860,68 @@ int oracle_add(void *h, int n_new_kf, const double *kf_init, const double *kf_an
         }
     }
     return 0;
+}
+
+/* Append n pairwise difference factors of `kind` (0: keyframes, 1:
+ * landmarks) between variables a[i] and b[i], measuring x_b - x_a ~
+ * N(z[i], diag(prec[i])^-1) (D values each). Their messages start at zero
+ * and enter the beliefs from the next belief phase. Returns 0, or -1 on a
+ * bad index, a non-positive precision or an allocation failure. */
+int oracle_add_pairs(void *h, int kind, int n, const int *a, const int *b, const double *z, const double *prec) {
+    oracle_t *o = h;
+    if (kind < 0 || kind > 1 || n < 0) return -1;
+    const int D = pair_dim(kind), nv = kind == 0 ? o->nk : o->nl;
+    for (int i = 0; i < n; ++i) {
+        if (a[i] < 0 || a[i] >= nv || b[i] < 0 || b[i] >= nv || a[i] == b[i]) return -1;
+        for (int j = 0; j < D; ++j) if (!(prec[(size_t)i*D + j] > 0.0)) return -1;
+    }
+    struct pairs *q = &o->pr[kind];
+    const int nn = q->n + n;
+    if (nn > q->cap) {
+        const int cap = 2 * nn;
+        int **is[] = { &q->a, &q->b, &q->cnt };
+        for (int r = 0; r < 3; ++r) {
+            int *t = realloc(*is[r], sizeof(int) * cap);
+            if (!t) return -1;
+            *is[r] = t;
+        }
+        double **ds[] = { &q->z, &q->p, &q->ma_eta, &q->mb_eta, &q->na_eta, &q->nb_eta };
+        for (int r = 0; r < 6; ++r) {
+            double *t = realloc(*ds[r], sizeof(double) * cap * D);
+            if (!t) return -1;
+            *ds[r] = t;
+        }
+        double **ls[] = { &q->ma_lam, &q->mb_lam, &q->na_lam, &q->nb_lam };
+        for (int r = 0; r < 4; ++r) {
+            double *t = realloc(*ls[r], sizeof(double) * cap * D * D);
+            if (!t) return -1;
+            *ls[r] = t;
+        }
+        q->cap = cap;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int f = q->n + i;
+        q->a[f] = a[i]; q->b[f] = b[i]; q->cnt[f] = 0;
+        memcpy(q->z + (size_t)f*D, z + (size_t)i*D, sizeof(double) * D);
+        memcpy(q->p + (size_t)f*D, prec + (size_t)i*D, sizeof(double) * D);
+        memset(q->ma_eta + (size_t)f*D, 0, sizeof(double) * D);
+        memset(q->mb_eta + (size_t)f*D, 0, sizeof(double) * D);
+        memset(q->ma_lam + (size_t)f*D*D, 0, sizeof(double) * D * D);
+        memset(q->mb_lam + (size_t)f*D*D, 0, sizeof(double) * D * D);
+    }
+    q->n = nn;
+    return 0;
+}
+
+/* current messages of the pairwise factors of `kind` to their a and b ends */
+void oracle_pair_messages(void *h, int kind, double *a_eta, double *a_lam, double *b_eta, double *b_lam) {
+    oracle_t *o = h;
+    const struct pairs *q = &o->pr[kind];
+    const int D = pair_dim(kind);
+    if (a_eta) memcpy(a_eta, q->ma_eta, sizeof(double) * D * q->n);
+    if (a_lam) memcpy(a_lam, q->ma_lam, sizeof(double) * D * D * q->n);
+    if (b_eta) memcpy(b_eta, q->mb_eta, sizeof(double) * D * q->n);
+    if (b_lam) memcpy(b_lam, q->mb_lam, sizeof(double) * D * D * q->n);
 }
 
 int oracle_threads(void) {
