@@ -183,6 +183,31 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
                               double huber_k, int32_t log_every,
                               double *log_out);
 
+/* Heterogeneous factors (the outlook of Sections 9 and 10: factors from
+ * further priors and sensors in the same graph). Appends n pairwise
+ * difference factors between two keyframes (kind GBP_PAIR_KEYFRAMES, D = 6,
+ * on the pose vector (omega, t)) or two landmarks (GBP_PAIR_LANDMARKS,
+ * D = 3): x_b - x_a ~ N(z, diag(precision)^-1), e.g. a motion prior between
+ * consecutive keyframes or a smoothness prior between neighbouring scene
+ * points. a, b: [n] variable indices in the caller's order (problem-major
+ * for batches; a != b); z, precision: [n][D] host arrays (precision > 0),
+ * copied. The factors are linear and never relinearised; their messages
+ * follow eqs. (messageeta), (messagelambda), are damped like the
+ * measurement factors' (same d and damping mode, undamped for the first
+ * `undamped_after_relin` updates after they were added) and start at zero;
+ * they enter every later belief update. May be called at any clock and
+ * repeatedly; synchronises. Their state lives in one extra device
+ * allocation made here (outside a caller workspace). GBP_EINVAL for a bad
+ * kind, index, a == b, non-finite z or non-positive precision; GBP_ESTATE on
+ * a problem that has grown (gbp_add_keyframe), and afterwards
+ * gbp_add_keyframe (and gbp_apply_depth_model, for landmark pairs) return
+ * GBP_ESTATE. gbp_reset zeroes their messages and keeps them. */
+#define GBP_PAIR_KEYFRAMES 0
+#define GBP_PAIR_LANDMARKS 1
+gbp_status gbp_add_pair_factors(gbp_problem *p, int32_t kind, int32_t n,
+                                const int32_t *a, const int32_t *b,
+                                const double *z, const double *precision);
+
 /* Incremental growth (Section 9.2) of a single (non-batched) problem:
  * append one keyframe with initial pose `pose` (NULL: no keyframe),
  * n_new_lm landmarks and n_new_f factors whose indices refer to the grown

@@ -15,10 +15,10 @@ import numpy as np
 
 from . import _capi
 from ._capi import (GBP_FP32, GBP_FP64, GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA,
-                    HipLibraryMissing, gbp_reproj)
+                    GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS, HipLibraryMissing, gbp_reproj)
 
 __all__ = ["GBPSolver", "GBPError", "GBP_FP32", "GBP_FP64", "GBP_DAMP_ETA",
-           "GBP_DAMP_ETA_LAMBDA", "HipLibraryMissing", "load_library", "mlp_infer",
+           "GBP_DAMP_ETA_LAMBDA", "GBP_PAIR_KEYFRAMES", "GBP_PAIR_LANDMARKS", "HipLibraryMissing", "load_library", "mlp_infer",
            "MLPTrainer", "MLP_PARAMS", "MLP_FEATURES"]
 
 MLP_PARAMS = _capi.MLP_PARAMS
@@ -244,6 +244,21 @@ class GBPSolver:
         mk = np.ascontiguousarray(mask, dtype=np.uint8)
         self._check(self._lib.gbp_set_reference(self.h, _ptr(zr, C.c_double),
                                                 _ptr(mk, C.c_uint8)), self.h)
+
+    def add_pair_factors(self, kind: int, a, b, z, precision) -> None:
+        """Pairwise difference factors x_b - x_a ~ N(z, diag(precision)^-1)
+        between keyframes (GBP_PAIR_KEYFRAMES, 6 values per factor) or
+        landmarks (GBP_PAIR_LANDMARKS, 3 values); indices in the caller's
+        order (problem-major for batches)."""
+        D = 6 if kind == GBP_PAIR_KEYFRAMES else 3
+        a_, b_ = _i32(np.asarray(a).ravel()), _i32(np.asarray(b).ravel())
+        z_ = _f64(np.asarray(z, dtype=np.float64).reshape(-1, D))
+        p_ = _f64(np.asarray(precision, dtype=np.float64).reshape(-1, D))
+        if not (a_.shape[0] == b_.shape[0] == z_.shape[0] == p_.shape[0]):
+            raise ValueError("a, b, z and precision need one entry per factor")
+        self._check(self._lib.gbp_add_pair_factors(self.h, int(kind), a_.shape[0], _ptr(a_, C.c_int32),
+                                                   _ptr(b_, C.c_int32), _ptr(z_, C.c_double),
+                                                   _ptr(p_, C.c_double)), self.h)
 
     def add_keyframe(self, pose, lm_init, f_kf, f_lm, z) -> None:
         pose = None if pose is None else _f64(pose, (6,))

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libgbp_hip.so")
 GBP_OK, GBP_EINVAL, GBP_ENOMEM, GBP_EDEVICE, GBP_ENUMERIC, GBP_ESTATE = 0, -1, -2, -3, -4, -5
 GBP_FP64, GBP_FP32 = 0, 1
 GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA = 0, 1
+GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS = 0, 1
 
 STATUS_NAMES = {0: "GBP_OK", -1: "GBP_EINVAL", -2: "GBP_ENOMEM", -3: "GBP_EDEVICE",
                 -4: "GBP_ENUMERIC", -5: "GBP_ESTATE"}
@@ -57,7 +58,7 @@ class gbp_reproj(C.Structure):
 
 EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_create_batch", "gbp_relinearise", "gbp_iterate", "gbp_beliefs",
-           "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference",
+           "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference", "gbp_add_pair_factors",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
            "gbp_reset", "gbp_apply_depth_model", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
            "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step",
@@ -103,6 +104,7 @@ def load():
     lib.gbp_reproj_error.argtypes = [P, _dp, _dp, _ip]
     lib.gbp_reproj_stats.argtypes = [P, C.c_int32, C.POINTER(gbp_reproj)]
     lib.gbp_set_reference.argtypes = [P, _dp, _u8p]
+    lib.gbp_add_pair_factors.argtypes = [P, C.c_int32, C.c_int32, _ip, _ip, _dp, _dp]
     lib.gbp_add_keyframe.argtypes = [P, _dp, C.c_int32, _dp, C.c_int32, _ip, _ip, _dp]
     lib.gbp_set_damping_model.argtypes = [P, _u16p, C.c_int32, C.c_double]
     lib.gbp_reset.argtypes = [P]

@@ -95,6 +95,13 @@ struct gbp_problem {
     double *d_best = nullptr;      // [np] best mean reprojection error seen
     bool learned = false;
     bool grown = false;            // gbp_add_keyframe was called
+    // pairwise difference factors (kind 0 keyframes, 1 landmarks): host
+    // mirrors in internal indices, and one device allocation for their
+    // state, their variables' pair lists and the belief information
+    std::vector<int> h_pair_ab[2];
+    std::vector<double> h_pair_zp[2];
+    void *pair_mem = nullptr;
+    size_t pair_state_bytes = 0;   // leading bytes that hold messages and counts
     int every_k = 5;
     double fb_rise = 0.1;
     std::string err;
@@ -727,9 +734,13 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
         p->blk_lm = lb;
         d.lm_lanes = ll;
     } else {
-        void *snap = nullptr;
+        void *snap = nullptr, *psnap = nullptr;
         HIP_TRY(p, hipMalloc(&snap, p->ws_bytes));
         HIP_TRY(p, hipMemcpyAsync(snap, p->ws, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+        if (p->pair_mem) {
+            HIP_TRY(p, hipMalloc(&psnap, p->pair_state_bytes));
+            HIP_TRY(p, hipMemcpyAsync(psnap, p->pair_mem, p->pair_state_bytes, hipMemcpyDeviceToDevice, p->stream));
+        }
         double best = 1e30;
         int bk = p->blk_kf, bl = p->blk_lm, bll = 4;
         auto trial = [&](int x, int y, int z) -> gbp_status {
@@ -740,6 +751,8 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
             gbp_status st = time_config<TS>(p, n, &ms);
             if (st != GBP_OK) return st;
             HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+            if (psnap)
+                HIP_TRY(p, hipMemcpyAsync(p->pair_mem, psnap, p->pair_state_bytes, hipMemcpyDeviceToDevice, p->stream));
             if (ms < best) { best = ms; bk = x; bl = y; bll = z; }
             return GBP_OK;
         };
@@ -752,6 +765,7 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
             if (st == GBP_OK) st = trial(bk0, bl0, z);
         HIP_TRY(p, hipStreamSynchronize(p->stream));
         (void)hipFree(snap);
+        if (psnap) (void)hipFree(psnap);
         if (st != GBP_OK) return st;
         p->blk_kf = bk;
         p->blk_lm = bl;
@@ -1003,6 +1017,98 @@ gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double
     return GBP_OK;
 }
 
+// Pairwise difference factors: append n of `kind` (indices already
+// internal), rebuild the device allocation (messages and counts of the
+// existing pairs are kept, the new ones start at zero), rebuild the pair
+// lists of the variables, and recompute the beliefs so that the belief
+// information the pair update reads exists before the next iteration.
+template <typename TS>
+gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, const std::vector<double> &zp) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    HIP_TRY(p, hipStreamSynchronize(s));
+    const int n_old[2] = {d.n_pair[0], d.n_pair[1]};
+    p->h_pair_ab[kind].insert(p->h_pair_ab[kind].end(), ab.begin(), ab.end());
+    p->h_pair_zp[kind].insert(p->h_pair_zp[kind].end(), zp.begin(), zp.end());
+    const int n[2] = {(int)p->h_pair_ab[0].size() / 2, (int)p->h_pair_ab[1].size() / 2};
+    const int Ds[2] = {6, 3};
+    // layout: messages and counts first (the state that reset clears and
+    // the autotuner snapshots), then the constant data
+    Layout L;
+    double *msg[2];
+    int *cnt[2], *abd[2];
+    double *zpd[2];
+    for (int k = 0; k < 2; ++k) L.add((void **)&msg[k], (size_t)n[k] * pair_msg_doubles(Ds[k]) * 8);
+    for (int k = 0; k < 2; ++k) L.add((void **)&cnt[k], (size_t)n[k] * 4);
+    const size_t state_bytes = L.total;
+    for (int k = 0; k < 2; ++k) {
+        L.add((void **)&abd[k], (size_t)n[k] * 2 * 4);
+        L.add((void **)&zpd[k], (size_t)n[k] * 2 * Ds[k] * 8);
+    }
+    // pair lists: entry 2 i + side (side 0: end a, 1: end b), increasing i
+    std::vector<int> row[2], ent[2];
+    const int nv[2] = {p->nk, p->nl};
+    for (int k = 0; k < 2; ++k) {
+        row[k].assign(nv[k] + 1, 0);
+        for (int i = 0; i < n[k]; ++i)
+            for (int side = 0; side < 2; ++side) row[k][p->h_pair_ab[k][2 * i + side] + 1]++;
+        for (int v = 0; v < nv[k]; ++v) row[k][v + 1] += row[k][v];
+        ent[k].resize(2 * (size_t)n[k]);
+        std::vector<int> fill(row[k].begin(), row[k].end() - 1);
+        for (int i = 0; i < n[k]; ++i)
+            for (int side = 0; side < 2; ++side) ent[k][fill[p->h_pair_ab[k][2 * i + side]]++] = 2 * i + side;
+    }
+    int *rowd[2], *entd[2];
+    for (int k = 0; k < 2; ++k) {
+        L.add((void **)&rowd[k], (size_t)(nv[k] + 1) * 4);
+        L.add((void **)&entd[k], ent[k].size() * 4 + 4);
+    }
+    double *kbi = nullptr, *lbi = nullptr;
+    if (n[0] > 0) L.add((void **)&kbi, (size_t)p->cap_k * KBI * 8);
+    if (n[1] > 0) L.add((void **)&lbi, (size_t)p->cap_l * LBI * 8);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, L.total) != hipSuccess) return fail(p, GBP_ENOMEM, "cannot allocate the pairwise factors");
+    for (auto &it : L.items) *it.first = (char *)mem + it.second;
+    HIP_TRY(p, hipMemsetAsync(mem, 0, state_bytes, s));
+    for (int k = 0; k < 2; ++k) {
+        if (n_old[k] > 0) {
+            HIP_TRY(p, hipMemcpyAsync(msg[k], d.pair_msg[k], (size_t)n_old[k] * pair_msg_doubles(Ds[k]) * 8,
+                                      hipMemcpyDeviceToDevice, s));
+            HIP_TRY(p, hipMemcpyAsync(cnt[k], d.pair_cnt[k], (size_t)n_old[k] * 4, hipMemcpyDeviceToDevice, s));
+        }
+        if (n[k] > 0) {
+            HIP_TRY(p, hipMemcpyAsync(abd[k], p->h_pair_ab[k].data(), p->h_pair_ab[k].size() * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(p, hipMemcpyAsync(zpd[k], p->h_pair_zp[k].data(), p->h_pair_zp[k].size() * 8, hipMemcpyHostToDevice, s));
+        }
+        HIP_TRY(p, hipMemcpyAsync(rowd[k], row[k].data(), row[k].size() * 4, hipMemcpyHostToDevice, s));
+        if (!ent[k].empty())
+            HIP_TRY(p, hipMemcpyAsync(entd[k], ent[k].data(), ent[k].size() * 4, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(p, hipStreamSynchronize(s));
+    if (p->pair_mem) (void)hipFree(p->pair_mem);
+    p->pair_mem = mem;
+    p->pair_state_bytes = state_bytes;
+    for (int k = 0; k < 2; ++k) {
+        d.n_pair[k] = n[k];
+        d.pair_ab[k] = abd[k];
+        d.pair_zp[k] = zpd[k];
+        d.pair_cnt[k] = cnt[k];
+        d.pair_msg[k] = msg[k];
+    }
+    d.kp_row = rowd[0]; d.kp_ent = entd[0];
+    d.lp_row = rowd[1]; d.lp_ent = entd[1];
+    d.kf_binfo = kbi;
+    d.lm_binfo = lbi;
+    destroy_graphs(p);
+    // beliefs again from the current messages (the new pairs' are zero):
+    // the same beliefs, now with their information form stored
+    launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
+    launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
 // Back to the state right after creation (initial linearisation, zero
 // messages, beliefs = priors at clock 0); buffers, recorded graphs, the
 // reference and the damping model stay.
@@ -1020,6 +1126,7 @@ gbp_status reset_impl(gbp_problem *p) {
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
+    if (p->pair_mem) HIP_TRY(p, hipMemsetAsync(p->pair_mem, 0, p->pair_state_bytes, s));  // pair messages, counts
     launch_linearise<TS>(d, 0, p->nf, p->huber_k, nullptr, s);
     launch_prior_base<TS>(d, 0, 0, s);
     launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
@@ -1260,10 +1367,43 @@ gbp_status gbp_set_reference(gbp_problem *p, const double *z_ref, const uint8_t 
     return GBP_OK;
 }
 
+gbp_status gbp_add_pair_factors(gbp_problem *p, int32_t kind, int32_t n, const int32_t *a, const int32_t *b,
+                                const double *z, const double *precision) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (kind != GBP_PAIR_KEYFRAMES && kind != GBP_PAIR_LANDMARKS)
+        return fail(p, GBP_EINVAL, "gbp_add_pair_factors: kind must be GBP_PAIR_KEYFRAMES or GBP_PAIR_LANDMARKS");
+    if (n < 0 || (n > 0 && (!a || !b || !z || !precision)))
+        return fail(p, GBP_EINVAL, "gbp_add_pair_factors: need n >= 0 and the four arrays");
+    if (p->grown) return fail(p, GBP_ESTATE, "gbp_add_pair_factors: the problem has grown since creation");
+    if (n == 0) return GBP_OK;
+    const int D = kind == GBP_PAIR_KEYFRAMES ? 6 : 3, nv = kind == GBP_PAIR_KEYFRAMES ? p->nk : p->nl;
+    std::vector<int> u2i(nv);
+    for (int i = 0; i < nv; ++i) u2i[kind == GBP_PAIR_KEYFRAMES ? i : p->lm_int2user[i]] = i;
+    std::vector<int> ab(2 * (size_t)n);
+    std::vector<double> zp(2 * (size_t)D * n);
+    for (int i = 0; i < n; ++i) {
+        if (a[i] < 0 || a[i] >= nv || b[i] < 0 || b[i] >= nv || a[i] == b[i])
+            return fail(p, GBP_EINVAL, "gbp_add_pair_factors: variable index out of range or a == b");
+        ab[2 * (size_t)i] = u2i[a[i]];
+        ab[2 * (size_t)i + 1] = u2i[b[i]];
+        for (int j = 0; j < D; ++j) {
+            const double zz = z[(size_t)D * i + j], pr = precision[(size_t)D * i + j];
+            if (!std::isfinite(zz) || !(pr > 0.0) || !std::isfinite(pr))
+                return fail(p, GBP_EINVAL, "gbp_add_pair_factors: z must be finite and precisions positive");
+            zp[2 * (size_t)D * i + j] = zz;
+            zp[2 * (size_t)D * i + D + j] = pr;
+        }
+    }
+    return p->precision == GBP_FP32 ? pairs_impl<float>(p, kind, ab, zp) : pairs_impl<double>(p, kind, ab, zp);
+}
+
 gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6], int32_t n_new_lm, const double *lm_init,
                             int32_t n_new_f, const int32_t *f_kf, const int32_t *f_lm, const double *z) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
+    if (p->pair_mem)
+        return fail(p, GBP_ESTATE, "gbp_add_keyframe: problems with pairwise factors do not grow");
     return p->precision == GBP_FP32 ? add_impl<float>(p, pose, n_new_lm, lm_init, n_new_f, f_kf, f_lm, z)
                                     : add_impl<double>(p, pose, n_new_lm, lm_init, n_new_f, f_kf, f_lm, z);
 }
@@ -1287,6 +1427,8 @@ gbp_status gbp_apply_depth_model(gbp_problem *p, const int32_t *landmarks, int32
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
     if (!p->learned) return fail(p, GBP_ESTATE, "gbp_apply_depth_model: set a damping/depth model first");
+    if (!p->h_pair_ab[1].empty())
+        return fail(p, GBP_ESTATE, "gbp_apply_depth_model: landmarks with pairwise factors cannot be moved");
     if (n < 0 || (n > 0 && !landmarks)) return fail(p, GBP_EINVAL, "gbp_apply_depth_model: need n >= 0 and landmarks");
     std::vector<int> u2i(p->nl);
     for (int i = 0; i < p->nl; ++i) u2i[p->lm_int2user[i]] = i;
@@ -1421,6 +1563,7 @@ void gbp_destroy(gbp_problem *p) {
     destroy_graphs(p);
     if (p->d_log) (void)hipFree(p->d_log);
     if (p->learn_mem) (void)hipFree(p->learn_mem);
+    if (p->pair_mem) (void)hipFree(p->pair_mem);
     if (p->own_ws && p->ws) (void)hipFree(p->ws);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;

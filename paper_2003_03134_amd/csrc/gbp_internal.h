@@ -23,6 +23,11 @@ constexpr int LM_LANES = 4;  // default lanes per landmark in the landmark belie
 constexpr int NFEAT = 16;   // learned-model features per factor
 constexpr int FHIST = 12;   // floats of per-factor feature history
 constexpr int MSG_W = 16;   // floats per exported factor-message row
+// pairwise difference factors: D = 6 (keyframes) or 3 (landmarks); per pair
+// the messages to a and to b, each eta (D) then Lambda (packed, D(D+1)/2)
+constexpr int pair_msg_doubles(int D) { return 2 * (D + D * (D + 1) / 2); }
+constexpr int KBI = 32;     // doubles of keyframe belief information: Lambda packed (21), eta (6), pad
+constexpr int LBI = 12;     // doubles of landmark belief information: Lambda packed (6), eta (3), pad
 
 // keyframe-side record (TS = float | double), one per factor:
 //   [0..5]  d h / d omega (2x3, row-major)
@@ -87,6 +92,16 @@ struct Dev {
     const int *prob_rblk;                 // first block of each problem (np + 1)
     double *rblk_part;                    // per-block partial statistics (8 doubles)
     double *are_out;                      // per-problem statistics (8 doubles)
+    // pairwise difference factors (kind 0: keyframes, kind 1: landmarks),
+    // FP64, messages relative to the variables' anchors
+    int n_pair[2];
+    const int *pair_ab[2];                // ends a, b of each pair
+    const double *pair_zp[2];             // measured x_b - x_a (D) and diagonal precision (D)
+    int *pair_cnt[2];                     // updates since the pair was added
+    double *pair_msg[2];                  // pair_msg_doubles(D) per pair
+    const int *kp_row, *kp_ent;           // pair ends of each keyframe (CSR; entry 2 pair + side)
+    const int *lp_row, *lp_ent;           // pair ends of each landmark
+    double *kf_binfo, *lm_binfo;          // belief information (KBI / LBI) while pairs of that kind exist
 };
 
 struct IterOpts {

@@ -729,13 +729,101 @@ __device__ __forceinline__ void reduce_problem(const double *part, const int *pr
     }
 }
 
+// One pairwise difference factor between variables a and b of dimension D
+// (keyframes: 6, landmarks: 3), measuring x_b - x_a ~ N(z, diag(p)^-1):
+// both messages by eqs. (messageeta), (messagelambda). The factor is
+// Lambda = [P, -P; -P, P], eta = [-P z; P z] (anchor-relative: z minus the
+// anchors' difference); the message to v marginalises the other end u after
+// adding u's variable-to-factor message (u's belief in information form,
+// stored by the belief kernels, minus this factor's previous message to u):
+// S = P + Lambda_c, message Lambda = P - P S^-1 P, eta = +-P z + P S^-1 (eta_c
+// -+ P z). Damped like a measurement factor's messages (eta only in absolute
+// coordinates, or both; undamped for the first `undamped` updates).
+template <typename TS, int D>
+__device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind, const int i) {
+    constexpr int T = D * (D + 1) / 2, MS = pair_msg_doubles(D);
+    const int a = d.pair_ab[kind][2 * i], b = d.pair_ab[kind][2 * i + 1];
+    const double *zp = d.pair_zp[kind] + 2 * D * (size_t)i;
+    const double *anc = kind == 0 ? d.kf_anchor : d.lm_anchor;
+    const double *bi = kind == 0 ? d.kf_binfo : d.lm_binfo;
+    const int BI = kind == 0 ? KBI : LBI;
+    double *msg = d.pair_msg[kind] + MS * (size_t)i;
+    double zr[D], P[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        zr[j] = zp[j] - (anc[(size_t)D * b + j] - anc[(size_t)D * a + j]);
+        P[j] = zp[D + j];
+    }
+    const int c = d.pair_cnt[kind][i];
+    const double dd = c < o.undamped ? 0.0 : o.damping;
+    double out[2][D + T];  // new messages to b (side 0) and to a (side 1)
+    bool ok = true;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int u = side == 0 ? a : b, v = side == 0 ? b : a;
+        const double sv = side == 0 ? 1.0 : -1.0;
+        const double *mu = msg + (side == 0 ? 0 : D + T);   // old message to u
+        const double *mv = msg + (side == 0 ? D + T : 0);   // old message to v
+        const double *bu = bi + (size_t)BI * u;
+        double S[T], rhs[D];
+#pragma unroll
+        for (int q = 0; q < T; ++q) S[q] = bu[q] - mu[D + q];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            S[pidx<D>(j, j)] += P[j];
+            rhs[j] = -sv * P[j] * zr[j] + bu[T + j] - mu[j];
+        }
+        double L[T], inv[T], x[D];
+        if (!chol<D>(S, L)) { ok = false; break; }
+        chol_inverse_solve<D>(L, rhs, inv, x);
+        double *w = out[side];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int q = r; q < D; ++q) w[D + pidx<D>(r, q)] = (r == q ? P[r] : 0.0) - P[r] * inv[pidx<D>(r, q)] * P[q];
+#pragma unroll
+        for (int r = 0; r < D; ++r) w[r] = sv * P[r] * zr[r] + P[r] * x[r];
+        if (o.damp_mode == 1) {
+#pragma unroll
+            for (int q = 0; q < D + T; ++q) w[q] = (1.0 - dd) * w[q] + dd * mv[q];
+        } else {
+            // eta damped in absolute coordinates: anchor-relative correction
+            double corr[D];
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < D; ++q) t += (mv[D + pidx<D>(r, q)] - w[D + pidx<D>(r, q)]) * anc[(size_t)D * v + q];
+                corr[r] = t;
+            }
+#pragma unroll
+            for (int r = 0; r < D; ++r) w[r] = (1.0 - dd) * w[r] + dd * mv[r] + dd * corr[r];
+        }
+    }
+    if (!ok) { atomicOr(d.status, 1u); return; }
+#pragma unroll
+    for (int q = 0; q < D + T; ++q) {
+        msg[D + T + q] = out[0][q];  // to b
+        msg[q] = out[1][q];          // to a
+    }
+    d.pair_cnt[kind][i] = c < (1 << 30) ? c + 1 : c;
+}
+
 // Queue segment of residual block b: relinearise and send (marks done); one
 // wave per segment, since a segment holds few due factors in steady state.
-// Workgroups nseg .. nseg + np - 1, when present, reduce the residual
-// statistics of the previous iteration's fused residual pass (whose check
-// advanced the clock: t_off -1) into log_row.
+// The next nred workgroups (nred = np or 0) reduce the residual statistics
+// of the previous iteration's fused residual pass (whose check advanced the
+// clock: t_off -1) into log_row; the workgroups after them update the
+// pairwise factors, one per thread (they read only beliefs of the previous
+// iteration and their own messages, like the measurement factors here).
 template <typename TS>
-__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o, int nseg, double *log_row) {
+__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o, int nseg, int nred, double *log_row) {
+    if ((int)blockIdx.x >= nseg + nred) {
+        const int i = ((int)blockIdx.x - nseg - nred) * 64 + (int)threadIdx.x;
+        if (i < d.n_pair[0]) pair_update<TS, 6>(d, o, 0, i);
+        else if (i < d.n_pair[0] + d.n_pair[1]) pair_update<TS, 3>(d, o, 1, i - d.n_pair[0]);
+        return;
+    }
     if ((int)blockIdx.x >= nseg) {
         reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
         return;
@@ -787,6 +875,23 @@ __device__ void kf_solve(const Dev<TS> &d, const IterOpts &o, const int k, const
         const double sc = prior_scale(o, d.t_dev[0] - d.kf_t0[k]);
 #pragma unroll
         for (int i = 0; i < 6; ++i) A[pidx<6>(i, i)] += d.kf_pbase[6 * (size_t)k + i] * sc;
+    }
+    if (d.kf_binfo) {
+        // pairwise factors' messages, then the belief in information form
+        // for the next pairwise update
+        for (int q = d.kp_row[k]; q < d.kp_row[k + 1]; ++q) {
+            const int ent = d.kp_ent[q];
+            const double *m = d.pair_msg[0] + pair_msg_doubles(6) * (size_t)(ent >> 1) + (ent & 1) * 27;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) e[i] += m[i];
+#pragma unroll
+            for (int i = 0; i < 21; ++i) A[i] += m[6 + i];
+        }
+        double *bi = d.kf_binfo + KBI * (size_t)k;
+#pragma unroll
+        for (int i = 0; i < 21; ++i) bi[i] = A[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) bi[21 + i] = e[i];
     }
     if (readout) {
         double *out = d.kf_info + 36 * (size_t)k;
@@ -1223,6 +1328,21 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
     A[pidx<3>(0, 0)] += d.lm_pbase[3 * (size_t)m] * sc;
     A[pidx<3>(1, 1)] += d.lm_pbase[3 * (size_t)m + 1] * sc;
     A[pidx<3>(2, 2)] += d.lm_pbase[3 * (size_t)m + 2] * sc;
+    if (d.lm_binfo) {
+        for (int q = d.lp_row[m]; q < d.lp_row[m + 1]; ++q) {
+            const int ent = d.lp_ent[q];
+            const double *pm = d.pair_msg[1] + pair_msg_doubles(3) * (size_t)(ent >> 1) + (ent & 1) * 9;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) e[i] += pm[i];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) A[i] += pm[3 + i];
+        }
+        double *bi = d.lm_binfo + LBI * (size_t)m;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) bi[i] = A[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) bi[6 + i] = e[i];
+    }
     if (readout) {
         double *out = d.lm_info + 9 * (size_t)m;
 #pragma unroll
@@ -1478,8 +1598,9 @@ void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
 
 template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
-    const int g = d.n_rblk + (pending_log_row ? d.np : 0);
-    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(64), 0, s, d, o, d.n_rblk, pending_log_row);
+    const int nred = pending_log_row ? d.np : 0;
+    const int g = d.n_rblk + nred + blocks(d.n_pair[0] + d.n_pair[1], 64);
+    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(64), 0, s, d, o, d.n_rblk, nred, pending_log_row);
 }
 
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
