@@ -191,6 +191,54 @@ def learned_kernels_leg(n_rows):
     return dict(infer=infer, train=train)
 
 
+def pairs_leg(probs, steps=50, warmup=20):
+    """Pairwise difference factors at the workload's scale: every problem
+    gets a motion prior between consecutive keyframes and a smoothness prior
+    between consecutive landmarks (measured differences taken from the
+    initial estimate, weak precisions), and logged steps are timed with and
+    without them on otherwise identical solvers."""
+    import numpy as np
+    import torch
+    import paper_2003_03134_amd as gbp
+    out = {}
+    for with_pairs in (False, True):
+        s = gbp.GBPSolver(probs if len(probs) > 1 else probs[0], precision=gbp.GBP_FP32)
+        s.set_reference(np.concatenate([p.z_true for p in probs]), np.concatenate([p.inlier for p in probs]))
+        n_kp = n_lp = 0
+        if with_pairs:
+            ko = np.cumsum([0] + [p.n_keyframes for p in probs])
+            lo = np.cumsum([0] + [p.n_landmarks for p in probs])
+            ka, kb, kz, la, lb, lz = [], [], [], [], [], []
+            for i, p in enumerate(probs):
+                k = np.arange(p.n_keyframes - 1)
+                ka.append(ko[i] + k); kb.append(ko[i] + k + 1); kz.append(p.kf_init[k + 1] - p.kf_init[k])
+                m = np.arange(p.n_landmarks - 1)
+                la.append(lo[i] + m); lb.append(lo[i] + m + 1); lz.append(p.lm_init[m + 1] - p.lm_init[m])
+            ka, kb, kz = np.concatenate(ka), np.concatenate(kb), np.concatenate(kz)
+            la, lb, lz = np.concatenate(la), np.concatenate(lb), np.concatenate(lz)
+            s.add_pair_factors(gbp.GBP_PAIR_KEYFRAMES, ka, kb, kz, np.full(kz.shape, 1.0))
+            s.add_pair_factors(gbp.GBP_PAIR_LANDMARKS, la, lb, lz, np.full(lz.shape, 0.01))
+            n_kp, n_lp = len(ka), len(la)
+        s.iterate_logged(warmup, 0.4, 2.0, log_every=1)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate_logged(steps, 0.4, 2.0, log_every=1)
+        s.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ph = s.phase_times(10, 0.4, 2.0)
+        s.close()
+        out["with_pairs" if with_pairs else "without_pairs"] = dict(
+            ms_per_step=round(ms, 4), keyframe_pairs=n_kp, landmark_pairs=n_lp,
+            relin_phase_ms=round(ph["relin"], 4), belief_phase_ms=round(ph["belief_lm"], 4),
+            factor_phase_ms=round(ph["factor_kf"], 4))
+    d = out["with_pairs"]["ms_per_step"] - out["without_pairs"]["ms_per_step"]
+    out["added_ms_per_step"] = round(d, 4)
+    log(f"pairs: {out['with_pairs']['keyframe_pairs']} keyframe and {out['with_pairs']['landmark_pairs']} "
+        f"landmark pairs add {d * 1e3:.1f} us per step")
+    return out
+
+
 def studies_leg(trials):
     """The robustness and Huber studies (Sections 9.3, 9.4) at one setting
     each on the GPU, with the FP64 oracle timed on one trial of the same
@@ -235,6 +283,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--pairs", action="store_true",
+                    help="also time the workload with pairwise keyframe and landmark factors")
     ap.add_argument("--no-learned-kernels", action="store_true",
                     help="skip timing the learned network's inference and training kernels")
     ap.add_argument("--studies", type=int, default=0,
@@ -338,6 +388,8 @@ def main():
         extra["learned_kernels"] = learned_kernels_leg(nf)
     if args.studies > 0:
         extra["studies"] = studies_leg(args.studies)
+    if args.pairs:
+        extra["pairs"] = pairs_leg(probs)
     cpu = None
     if not args.no_cpu_baseline:
         log("FP64 oracle on a bounded sample (host cores)")
