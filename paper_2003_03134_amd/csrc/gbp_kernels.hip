@@ -809,21 +809,23 @@ __device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind,
     d.pair_cnt[kind][i] = c < (1 << 30) ? c + 1 : c;
 }
 
+// Pairwise factors, one per thread (keyframe pairs first). A kernel of its
+// own, launched only while pairs exist: inside the relinearisation launch
+// its registers halved that kernel's occupancy.
+template <typename TS>
+__global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.n_pair[0]) pair_update<TS, 6>(d, o, 0, i);
+    else if (i < d.n_pair[0] + d.n_pair[1]) pair_update<TS, 3>(d, o, 1, i - d.n_pair[0]);
+}
+
 // Queue segment of residual block b: relinearise and send (marks done); one
 // wave per segment, since a segment holds few due factors in steady state.
 // The next nred workgroups (nred = np or 0) reduce the residual statistics
 // of the previous iteration's fused residual pass (whose check advanced the
-// clock: t_off -1) into log_row; the workgroups after them update the
-// pairwise factors, one per thread (they read only beliefs of the previous
-// iteration and their own messages, like the measurement factors here).
+// clock: t_off -1) into log_row.
 template <typename TS>
 __global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o, int nseg, int nred, double *log_row) {
-    if ((int)blockIdx.x >= nseg + nred) {
-        const int i = ((int)blockIdx.x - nseg - nred) * 64 + (int)threadIdx.x;
-        if (i < d.n_pair[0]) pair_update<TS, 6>(d, o, 0, i);
-        else if (i < d.n_pair[0] + d.n_pair[1]) pair_update<TS, 3>(d, o, 1, i - d.n_pair[0]);
-        return;
-    }
     if ((int)blockIdx.x >= nseg) {
         reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
         return;
@@ -1599,8 +1601,12 @@ void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
 template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
     const int nred = pending_log_row ? d.np : 0;
-    const int g = d.n_rblk + nred + blocks(d.n_pair[0] + d.n_pair[1], 64);
+    const int g = d.n_rblk + nred;
     if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(64), 0, s, d, o, d.n_rblk, nred, pending_log_row);
+    // pairwise factors: they read the previous iteration's beliefs and
+    // their own messages only, like the relinearised factors
+    const int np = d.n_pair[0] + d.n_pair[1];
+    if (np > 0) hipLaunchKernelGGL(k_pairs<TS>, dim3(blocks(np, 128)), dim3(128), 0, s, d, o);
 }
 
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
