@@ -12,7 +12,8 @@
 // head is a per-lane dot product.
 // Training (k_mlp_train_block, k_mlp_reduce, k_adam) evaluates the same
 // BF16-rounded forward pass per sample and back-propagates in FP32; block
-// partial gradients are summed in block order, so training is deterministic.
+// partial gradients are summed in a fixed order, so training is
+// deterministic.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -196,46 +197,50 @@ __global__ __launch_bounds__(256) void k_mlp_train_block(const float *__restrict
                                                          const int *__restrict__ idx, int n_batch, const float *__restrict__ theta,
                                                          float *__restrict__ part_grad, float *__restrict__ part_loss) {
     __shared__ float w[MLP_NPARAMS];
-    // rows padded by one word: lane s walks row s, so unpadded rows of 64
-    // floats would put every lane on the same LDS bank
+    // rows padded by one word: the lanes of a wave read one column of 8
+    // samples' rows, which unpadded rows of 64 floats would put on one LDS
+    // bank
     __shared__ float sx[SB][MLP_IN + 1], sh1[SB][MLP_H + 1], sh2[SB][MLP_H + 1], sd1[SB][MLP_H + 1],
         sd2[SB][MLP_H + 1], sdo[SB][2];
-    __shared__ float sl[SB];
+    __shared__ float sl[SB], so[SB][2];
     const int tid = threadIdx.x;
     for (int i = tid; i < MLP_NPARAMS; i += 256) w[i] = bfround(theta[i]);
+    // 8 lanes per sample: lane r of sample s owns hidden units 8 r .. 8 r + 7
+    // of every layer and evaluates each of their dot products in full, in
+    // index order (the same sums as one lane per sample)
+    static_assert(SB * 8 == 256, "8 lanes per sample");
+    const int s = tid >> 3, r = tid & 7, u0 = 8 * r;
+    // samples past the batch or with an index outside [0, n_rows) count as
+    // zero-weight samples
+    const int g = blockIdx.x * SB + s;
+    const int src0 = g < n_batch ? idx[g] : -1;
+    const bool live = src0 >= 0 && src0 < n_rows;
+    const int src = live ? src0 : 0;
+#pragma unroll
+    for (int j = 2 * r; j < 2 * r + 2; ++j) sx[s][j] = live ? bfround(X[(size_t)src * MLP_IN + j]) : 0.f;
     __syncthreads();
-    const int s = tid;  // one sample per lane of the first wave
-    if (s < SB) {
-        // samples past the batch or with an index outside [0, n_rows) count
-        // as zero-weight samples
-        const int g = blockIdx.x * SB + s;
-        const int src0 = g < n_batch ? idx[g] : -1;
-        const bool live = src0 >= 0 && src0 < n_rows;
-        const int src = live ? src0 : 0;
-        float x[MLP_IN];
+    for (int i = u0; i < u0 + 8; ++i) {
+        float a = w[O_B1 + i];
 #pragma unroll
-        for (int j = 0; j < MLP_IN; ++j) {
-            x[j] = live ? bfround(X[(size_t)src * MLP_IN + j]) : 0.f;
-            sx[s][j] = x[j];
-        }
-        for (int i = 0; i < MLP_H; ++i) {
-            float a = w[O_B1 + i];
-#pragma unroll
-            for (int j = 0; j < MLP_IN; ++j) a += w[O_W1 + i * MLP_IN + j] * x[j];
-            sh1[s][i] = bfround(a > 0.f ? a : 0.f);
-        }
-        for (int i = 0; i < MLP_H; ++i) {
-            float a = w[O_B2 + i];
-            for (int j = 0; j < MLP_H; ++j) a += w[O_W2 + i * MLP_H + j] * sh1[s][j];
-            sh2[s][i] = bfround(a > 0.f ? a : 0.f);
-        }
-        float o0 = w[O_B3], o1 = w[O_B3 + 1];
-        for (int j = 0; j < MLP_H; ++j) {
-            o0 += w[O_W3 + j] * sh2[s][j];
-            o1 += w[O_W3 + MLP_H + j] * sh2[s][j];
-        }
+        for (int j = 0; j < MLP_IN; ++j) a += w[O_W1 + i * MLP_IN + j] * sx[s][j];
+        sh1[s][i] = bfround(a > 0.f ? a : 0.f);
+    }
+    __syncthreads();
+    for (int i = u0; i < u0 + 8; ++i) {
+        float a = w[O_B2 + i];
+        for (int j = 0; j < MLP_H; ++j) a += w[O_W2 + i * MLP_H + j] * sh1[s][j];
+        sh2[s][i] = bfround(a > 0.f ? a : 0.f);
+    }
+    __syncthreads();
+    if (r < 2) {
+        float o = w[O_B3 + r];
+        for (int j = 0; j < MLP_H; ++j) o += w[O_W3 + r * MLP_H + j] * sh2[s][j];
+        so[s][r] = o;
+    }
+    __syncthreads();
+    if (r == 0) {
         float d, delta;
-        heads(o0, o1, d, delta);
+        heads(so[s][0], so[s][1], d, delta);
         float m0 = 0.f, m1 = 0.f, y0 = 0.f, y1 = 0.f;
         if (live) {
             m0 = M[2 * (size_t)src]; m1 = M[2 * (size_t)src + 1];
@@ -244,19 +249,19 @@ __global__ __launch_bounds__(256) void k_mlp_train_block(const float *__restrict
         const float r0 = d - y0, r1 = delta - y1;
         sl[s] = (m0 * r0 * r0 + m1 * r1 * r1) / (float)n_batch;
         const float sig = d / MLP_DMAX, th = delta / MLP_CDELTA;
-        const float do0 = 2.f * m0 * r0 / (float)n_batch * MLP_DMAX * sig * (1.f - sig);
-        const float do1 = 2.f * m1 * r1 / (float)n_batch * MLP_CDELTA * (1.f - th * th);
-        sdo[s][0] = do0;
-        sdo[s][1] = do1;
-        for (int i = 0; i < MLP_H; ++i) {
-            const float dh = do0 * w[O_W3 + i] + do1 * w[O_W3 + MLP_H + i];
-            sd2[s][i] = sh2[s][i] > 0.f ? dh : 0.f;
-        }
-        for (int j = 0; j < MLP_H; ++j) {
-            float dh = 0.f;
-            for (int i = 0; i < MLP_H; ++i) dh += sd2[s][i] * w[O_W2 + i * MLP_H + j];
-            sd1[s][j] = sh1[s][j] > 0.f ? dh : 0.f;
-        }
+        sdo[s][0] = 2.f * m0 * r0 / (float)n_batch * MLP_DMAX * sig * (1.f - sig);
+        sdo[s][1] = 2.f * m1 * r1 / (float)n_batch * MLP_CDELTA * (1.f - th * th);
+    }
+    __syncthreads();
+    for (int i = u0; i < u0 + 8; ++i) {
+        const float dh = sdo[s][0] * w[O_W3 + i] + sdo[s][1] * w[O_W3 + MLP_H + i];
+        sd2[s][i] = sh2[s][i] > 0.f ? dh : 0.f;
+    }
+    __syncthreads();
+    for (int jj = u0; jj < u0 + 8; ++jj) {
+        float dh = 0.f;
+        for (int i = 0; i < MLP_H; ++i) dh += sd2[s][i] * w[O_W2 + i * MLP_H + jj];
+        sd1[s][jj] = sh1[s][jj] > 0.f ? dh : 0.f;
     }
     __syncthreads();
     float *pg = part_grad + (size_t)blockIdx.x * MLP_NPARAMS;
@@ -290,21 +295,32 @@ __global__ __launch_bounds__(256) void k_mlp_train_block(const float *__restrict
     }
 }
 
-// sum of the workgroups' partial gradients (and losses) in workgroup order
+// Sum of the workgroups' partial gradients: each workgroup takes 64
+// parameters, its 4 waves sum consecutive quarters of the partials in
+// workgroup order and the quarters are added in order (a fixed order:
+// deterministic). The last workgroup sums the partial losses in order.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part_grad,
                                                     const float *__restrict__ part_loss, int nb,
                                                     float *__restrict__ grad, float *__restrict__ loss) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < MLP_NPARAMS) {
-        float a = 0.f;
-        for (int b = 0; b < nb; ++b) a += part_grad[(size_t)b * MLP_NPARAMS + e];
-        grad[e] = a;
+    const int nchunk = (MLP_NPARAMS + 63) / 64;
+    if ((int)blockIdx.x == nchunk) {
+        if (threadIdx.x == 0) {
+            float a = 0.f;
+            for (int b = 0; b < nb; ++b) a += part_loss[b];
+            loss[0] = a;
+        }
+        return;
     }
-    if (e == MLP_NPARAMS) {
-        float a = 0.f;
-        for (int b = 0; b < nb; ++b) a += part_loss[b];
-        loss[0] = a;
-    }
+    __shared__ float q[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int b0 = (nb * wave) / 4, b1 = (nb * (wave + 1)) / 4;
+    float a = 0.f;
+    if (e < MLP_NPARAMS)
+        for (int b = b0; b < b1; ++b) a += part_grad[(size_t)b * MLP_NPARAMS + e];
+    q[wave][lane] = a;
+    __syncthreads();
+    if (threadIdx.x < 64 && e < MLP_NPARAMS) grad[e] = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
 }
 
 // Adam with bias correction on FP32 master weights; writes the BF16 copy
@@ -343,7 +359,7 @@ void launch_mlp_train_step(const float *X, const float *Y, const float *M, int n
     const int nb = (n_batch + SB - 1) / SB;
     hipLaunchKernelGGL(k_mlp_train_block, dim3(nb), dim3(256), 0, s, X, Y, M, n_rows, idx, n_batch, (const float *)theta,
                        part_grad, part_loss);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAMS + 256) / 256), dim3(256), 0, s, (const float *)part_grad,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAMS + 63) / 64 + 1), dim3(256), 0, s, (const float *)part_grad,
                        (const float *)part_loss, nb, grad, loss);
     if (update)
         hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAMS + 255) / 256), dim3(256), 0, s, theta, m1, m2,
