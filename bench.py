@@ -191,6 +191,31 @@ def learned_kernels_leg(n_rows):
     return dict(infer=infer, train=train)
 
 
+def learned_step_leg(probs, plain_ms, steps=100, warmup=50):
+    """The same logged steps with the learned damping model in the loop
+    (residual statistics, fallback monitor, features and inference every
+    5th iteration, inside the replayed graph): the model's cost per step."""
+    import numpy as np
+    import torch
+    import paper_2003_03134_amd as gbp
+    from paper_2003_03134_amd import learned
+    w, _, _ = learned.load_weights()
+    s = gbp.GBPSolver(probs if len(probs) > 1 else probs[0], precision=gbp.GBP_FP32)
+    s.set_reference(np.concatenate([p.z_true for p in probs]), np.concatenate([p.inlier for p in probs]))
+    s.set_damping_model(w, every_k=5, fallback_rise=0.5)
+    s.iterate_logged(warmup, 0.4, 2.0, log_every=1)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate_logged(steps, 0.4, 2.0, log_every=1)
+    s.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    s.close()
+    log(f"learned damping in the loop: {ms:.4f} ms per step ({ms - plain_ms:+.4f} ms against plain)")
+    return dict(ms_per_step=round(ms, 4), plain_ms_per_step=round(plain_ms, 4),
+                added_ms_per_step=round(ms - plain_ms, 4), every_k=5)
+
+
 def pairs_leg(probs, steps=50, warmup=20):
     """Pairwise difference factors at the workload's scale: every problem
     gets a motion prior between consecutive keyframes and a smoothness prior
@@ -386,6 +411,7 @@ def main():
             f"wall-time speed-up {tt['speedup']}")
     if not args.no_learned_kernels:
         extra["learned_kernels"] = learned_kernels_leg(nf)
+        extra["learned_kernels"]["in_the_loop"] = learned_step_leg(probs, ms_per_step)
     if args.studies > 0:
         extra["studies"] = studies_leg(args.studies)
     if args.pairs:

@@ -194,7 +194,8 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
  * copied. The factors are linear and never relinearised; their messages
  * follow eqs. (messageeta), (messagelambda), are damped like the
  * measurement factors' (same d and damping mode, undamped for the first
- * `undamped_after_relin` updates after they were added) and start at zero;
+ * `undamped_after_relin` updates after they were added; with a damping
+ * model set they keep the constant damping) and start at zero;
  * they enter every later belief update. May be called at any clock and
  * repeatedly; synchronises. Their state lives in one extra device
  * allocation made here (outside a caller workspace). GBP_EINVAL for a bad

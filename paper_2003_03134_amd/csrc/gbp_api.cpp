@@ -533,9 +533,11 @@ gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const
 // fallback monitor, then features and the network, which writes the
 // per-factor damping used by the next factor phases.
 template <typename TS>
-void record_model(gbp_problem *p, hipStream_t s) {
+void record_model(gbp_problem *p, hipStream_t s, bool stats_fresh) {
     Dev<TS> &d = dev<TS>(p);
-    launch_reproj<TS>(d, p->iopt, p->huber_k, nullptr, nullptr, nullptr, s);
+    // the monitor's per-problem statistics: the previous iteration's logged
+    // residual pass left them in are_out at the same beliefs, else compute
+    if (!stats_fresh) launch_reproj<TS>(d, p->iopt, p->huber_k, nullptr, nullptr, nullptr, s);
     launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.status, s);
     launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
     launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
@@ -552,10 +554,11 @@ gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_b
     // between) runs the next iteration's relinearisation check inside its
     // residual pass, and the next relinearisation launch reduces the
     // residual statistics: two launches fewer per logged iteration.
-    bool checked = false;
+    bool checked = false, stats_fresh = false;
     double *pending_row = nullptr;
     for (int i = 0; i < n; ++i) {
-        if (model_at(i)) record_model<TS>(p, s);
+        if (model_at(i)) record_model<TS>(p, s, stats_fresh);
+        stats_fresh = false;
         if (!checked) launch_check<TS>(d, p->iopt, s);
         launch_relin<TS>(d, p->iopt, s, pending_row);
         checked = false;
@@ -570,6 +573,7 @@ gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_b
                 pending_row = row;
             } else {
                 launch_reproj<TS>(d, p->iopt, p->huber_k, zref, mask, row, s);
+                stats_fresh = true;
             }
         }
     }

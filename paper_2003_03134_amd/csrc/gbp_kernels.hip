@@ -465,10 +465,13 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 // (Section 4) and forms the cavity through both the old and the new
 // Jacobian. k and bk are the factor's keyframe and its current belief.
 // `stage` (may be null) receives the keyframe-side Jacobian and the new
-// stored message for the keyframe belief reduction.
+// stored message for the keyframe belief reduction. fd_on: whether the
+// learned per-factor damping applies (its problem has not fallen back); -1:
+// look it up for this factor.
 template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
-                                            const double *__restrict__ bk, TS *__restrict__ stage) {
+                                            const double *__restrict__ bk, TS *__restrict__ stage,
+                                            const int fd_on = -1) {
     const int m = d.f_lm[f];
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
     load10(d.arec + (size_t)f * AREC, ar);
@@ -478,6 +481,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     load5(d.mmsg + (size_t)f * MMSG, mm);
     int c = d.cnt[f];
     const uint8_t fl = d.flags[f];
+    const bool use_fd = fd_on < 0 ? (d.fdamp && !d.fallback[d.kf_prob[k]]) : fd_on > 0;
+    const float fd = use_fd ? d.fdamp[f] : -1.f;  // issued with the record loads
 
     const double *bm = d.lm_bel + (size_t)m * LBEL;
     double dmk[6], dmm[3];
@@ -590,12 +595,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     // (per-factor value from the learned model unless its problem fell back;
     // a negative value means none has been evaluated yet)
     double dd = o.damping;
-    if (c < o.undamped) {
-        dd = 0.0;
-    } else if (d.fdamp && !d.fallback[d.kf_prob[k]]) {
-        const float fd = d.fdamp[f];
-        if (fd >= 0.f) dd = (double)fd;
-    }
+    if (c < o.undamped) dd = 0.0;
+    else if (fd >= 0.f) dd = (double)fd;
     double oSk_a, oSk_b, oSk_c, ogk0, ogk1, oSm_a, oSm_b, oSm_c, ogm0, ogm1;
     if (o.damp_mode == 1) {
         oSk_a = (1 - dd) * nSk_a + dd * Ska; oSk_b = (1 - dd) * nSk_b + dd * Skb; oSk_c = (1 - dd) * nSk_c + dd * Skc;
@@ -978,6 +979,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
 #pragma unroll
     for (int i = 0; i < 27; ++i) kb[i] = uniform_f64(d.kf_bel[(size_t)k * KBEL + i]);
     const double *bk = kb;
+    // learned damping: on unless absent or the keyframe's problem fell back
+    // (the same for the whole workgroup)
+    const int fd_on = (d.fdamp && !d.fallback[d.kf_prob[k]]) ? 1 : 0;
     const int col = tid % 27, grp = tid / 27;
     double acc = 0.0;
     for (int base = e0; base < e1; base += BS) {
@@ -988,7 +992,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
         if (f < e1) {
             const uint8_t fl = d.flags[f];
             if (MODE == 0 && !(fl & FLAG_DONE)) {
-                factor_body<TS, false>(d, o, f, k, bk, row);
+                factor_body<TS, false>(d, o, f, k, bk, row, fd_on);
             } else {
                 TS kr[KREC], km[KMSG];
                 load12(d.krec + (size_t)f * KREC, kr);
@@ -1649,7 +1653,7 @@ void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const do
         hipLaunchKernelGGL((k_reproj_block<TS, false>), dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o, huber_k, zref,
                            mask);
     hipLaunchKernelGGL(k_reproj_reduce, dim3(d.np), dim3(64), 0, s, (const double *)d.rblk_part,
-                       d.prob_rblk, d.np, log_row ? (double *)nullptr : d.are_out, log_row, (const int *)d.t_dev, 0);
+                       d.prob_rblk, d.np, d.are_out, log_row, (const int *)d.t_dev, 0);
 }
 
 template <typename TS>
