@@ -107,7 +107,8 @@ def make_workload(name):
 
 
 def cpu_baseline(probs, budget_s, iters):
-    """FP64 oracle on the first problems of the workload until ~budget_s."""
+    """FP64 oracle on the first problems of the workload until ~budget_s, on
+    all host threads; then one thread on the first problem alone."""
     import oracle
     t_total, updates, used = 0.0, 0, 0
     for p in probs:
@@ -119,10 +120,20 @@ def cpu_baseline(probs, budget_s, iters):
         used += 1
         if t_total > budget_s:
             break
-    return dict(value=updates / t_total, unit="factor-updates/s", cores=oracle.threads(),
+    cores = oracle.threads()
+    oracle.set_threads(1)
+    o = oracle.Oracle(probs[0], anneal=True)
+    n1 = max(10, iters // 5)
+    t0 = time.perf_counter()
+    o.iterate(n1, 0.4, 2.0)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    return dict(value=updates / t_total, unit="factor-updates/s", cores=cores,
                 kind="oracle",
                 sample=f"first {used} problems of the workload, {iters} iterations each "
-                       f"({updates} factor updates, {t_total:.1f} s)")
+                       f"({updates} factor updates, {t_total:.1f} s)",
+                single_thread=dict(value=round(probs[0].n_factors * n1 / t1, 1),
+                                   sample=f"first problem, {n1} iterations, one thread ({t1:.2f} s)"))
 
 
 def time_to_target(gbp):

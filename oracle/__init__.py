@@ -56,6 +56,7 @@ def _lib():
         lib.oracle_huber_weight.argtypes = [C.c_double, C.c_double]
         lib.oracle_huber_weight.restype = C.c_double
         lib.oracle_threads.restype = C.c_int
+        lib.oracle_set_threads.argtypes = [C.c_int]
         lib.oracle_add_pairs.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip, _dp, _dp]
         lib.oracle_add_pairs.restype = C.c_int
         lib.oracle_pair_messages.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
@@ -109,6 +110,11 @@ def huber_weight(M, N):
 
 def threads() -> int:
     return _lib().oracle_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (results do not depend on it)."""
+    _lib().oracle_set_threads(int(n))
 
 
 class Oracle:

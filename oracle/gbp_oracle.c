@@ -924,6 +924,15 @@ void oracle_pair_messages(void *h, int kind, double *a_eta, double *a_lam, doubl
     if (b_lam) memcpy(b_lam, q->mb_lam, sizeof(double) * D * D * q->n);
 }
 
+/* OpenMP threads for the following calls (results do not depend on it) */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
