@@ -57,6 +57,7 @@ def _lib():
         lib.oracle_huber_weight.restype = C.c_double
         lib.oracle_threads.restype = C.c_int
         lib.oracle_set_threads.argtypes = [C.c_int]
+        lib.oracle_odometry.argtypes = [_dp, _dp, _dp, _dp]
         lib.oracle_add_pairs.argtypes = [C.c_void_p, C.c_int, C.c_int, _ip, _ip, _dp, _dp]
         lib.oracle_add_pairs.restype = C.c_int
         lib.oracle_pair_messages.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
@@ -110,6 +111,17 @@ def huber_weight(M, N):
 
 def threads() -> int:
     return _lib().oracle_threads()
+
+
+def odometry(xa, xb):
+    """Odometry measurement c_b - c_a (camera centres c = -R(omega)^T t) and
+    its 3x12 Jacobian w.r.t. [x_a; x_b]."""
+    a, pa = _d(np.asarray(xa, dtype=np.float64).reshape(6))
+    b, pb = _d(np.asarray(xb, dtype=np.float64).reshape(6))
+    h, ph = _out(3)
+    J, pJ = _out((3, 12))
+    _lib().oracle_odometry(pa, pb, ph, pJ)
+    return h, J
 
 
 def set_threads(n: int) -> None:
@@ -225,8 +237,9 @@ class Oracle:
         return cnt, inv
 
     def add_pairs(self, kind: int, a, b, z, prec) -> None:
-        """Pairwise difference factors (kind 0: keyframes, D = 6; kind 1:
-        landmarks, D = 3): x_b - x_a ~ N(z, diag(prec)^-1)."""
+        """Pairwise factors: kind 0, keyframe difference x_b - x_a ~ N(z,
+        diag(prec)^-1) (6 values); kind 1, the same between landmarks (3);
+        kind 2, keyframe odometry c_b - c_a ~ N(z, diag(prec)^-1) (3)."""
         D = 6 if kind == 0 else 3
         a_, pa = _i(np.asarray(a).ravel())
         b_, pb = _i(np.asarray(b).ravel())
@@ -237,12 +250,12 @@ class Oracle:
         self._keep += [a_, b_, z_, p_]
         if _lib().oracle_add_pairs(self.h, int(kind), len(a_), pa, pb, pz, pp) != 0:
             raise ValueError("oracle_add_pairs rejected the factors")
-        self.n_pairs = getattr(self, "n_pairs", [0, 0])
+        self.n_pairs = getattr(self, "n_pairs", [0, 0, 0])
         self.n_pairs[kind] += len(a_)
 
     def pair_messages(self, kind: int) -> dict:
-        D = 6 if kind == 0 else 3
-        n = getattr(self, "n_pairs", [0, 0])[kind]
+        D = 3 if kind == 1 else 6
+        n = getattr(self, "n_pairs", [0, 0, 0])[kind]
         ae, pa = _out((n, D))
         al, pb = _out((n, D, D))
         be, pc = _out((n, D))

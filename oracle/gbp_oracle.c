@@ -64,7 +64,16 @@
  *     with P = diag(p); its messages are damped like a measurement factor's
  *     (eta only unless damp_lambda; undamped for its first `undamped`
  *     updates after it was added); belief sums take the measurement
- *     factors' messages first, then the pairwise ones in pair order.
+ *     factors' messages first, then the pairwise ones in pair order;
+ *   - an odometry factor between keyframes a and b measures the displacement
+ *     of the camera centres in the world frame, c_b - c_a ~ N(z, diag(p)^-1)
+ *     with c = -R(omega)^T t (3 values); it is nonlinear and is linearised
+ *     at the current means at every update, then treated as a pairwise
+ *     factor with information Lambda = J^T P J, eta = J^T P (z - h(x0) + J x0)
+ *     over [x_a; x_b] (J the 3x12 Jacobian at x0); relinearised at every
+ *     update, it never leaves the undamped window after a relinearisation,
+ *     so its messages are undamped; they enter the keyframe beliefs after
+ *     the difference factors'.
  *
  * Every loop runs over factors or variables in increasing index order; a
  * variable sums its incoming messages in increasing factor index order.
@@ -121,10 +130,13 @@ typedef struct {
         double *z, *p;
         double *ma_eta, *ma_lam, *mb_eta, *mb_lam;
         double *na_eta, *na_lam, *nb_eta, *nb_lam;
-    } pr[2];
+    } pr[3];
 } oracle_t;
 
-static int pair_dim(int kind) { return kind == 0 ? 6 : 3; }
+/* variable dimension of a pair kind (0: keyframe difference, 1: landmark
+ * difference, 2: keyframe odometry) and the dimension of its measurement */
+static int pair_dim(int kind) { return kind == 1 ? 3 : 6; }
+static int pair_mdim(int kind) { return kind == 0 ? 6 : 3; }
 
 /* --------------------------------------------------------------------------
  * small dense linear algebra
@@ -390,10 +402,10 @@ static int update_beliefs(oracle_t *o) {
             for (int i = 0; i < LD*LD; ++i) lam[i] += o->ml_lam[(size_t)f*LD*LD + i];
         }
     }
-    for (int kind = 0; kind < 2; ++kind) {
+    for (int kind = 0; kind < 3; ++kind) {
         const struct pairs *q = &o->pr[kind];
         const int D = pair_dim(kind);
-        double *veta = kind == 0 ? o->kf_eta : o->lm_eta, *vlam = kind == 0 ? o->kf_lam : o->lm_lam;
+        double *veta = kind == 1 ? o->lm_eta : o->kf_eta, *vlam = kind == 1 ? o->lm_lam : o->kf_lam;
         for (int f = 0; f < q->n; ++f) {
             for (int i = 0; i < D; ++i) {
                 veta[(size_t)q->a[f]*D + i] += q->ma_eta[(size_t)f*D + i];
@@ -420,6 +432,97 @@ static int update_beliefs(oracle_t *o) {
         memcpy(o->lm_mu + (size_t)m * LD, mu, sizeof mu);
     }
     return bad;
+}
+
+/* Camera centre c = -R(omega)^T t of pose x = (omega, t) and its 3x6
+ * Jacobian: with Exp(omega + d) ~ Exp(omega) Exp(J_r(omega) d),
+ * dc/domega = [c]x J_r(omega) and dc/dt = -R^T. */
+static void centre_and_jacobian(const double *x, double *c, double *Jc) {
+    double R[9], Jr[9], S[9];
+    oracle_so3_exp(x, R);
+    oracle_so3_jr(x, Jr);
+    for (int i = 0; i < 3; ++i) c[i] = -(R[0*3+i] * x[3] + R[1*3+i] * x[4] + R[2*3+i] * x[5]);
+    skew(c, S);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += S[i*3+k] * Jr[k*3+j];
+            Jc[i*6 + j] = s;
+            Jc[i*6 + 3 + j] = -R[j*3 + i];
+        }
+}
+
+/* Odometry measurement h(x_a, x_b) = c_b - c_a and its 3x12 Jacobian */
+void oracle_odometry(const double *xa, const double *xb, double *h, double *J) {
+    double ca[3], cb[3], Ja[18], Jb[18];
+    centre_and_jacobian(xa, ca, Ja);
+    centre_and_jacobian(xb, cb, Jb);
+    for (int i = 0; i < 3; ++i) {
+        h[i] = cb[i] - ca[i];
+        if (J)
+            for (int j = 0; j < 6; ++j) { J[i*12 + j] = -Ja[i*6 + j]; J[i*12 + 6 + j] = Jb[i*6 + j]; }
+    }
+}
+
+/* Messages of an odometry factor (kind 2), linearised at the current means,
+ * to both ends by eqs. (messageeta), (messagelambda) with the full 12x12
+ * factor; damping as for the other pairs. */
+static int odometry_messages(oracle_t *o, int f, double damping) {
+    struct pairs *q = &o->pr[2];
+    const int a = q->a[f], b = q->b[f];
+    const double *xa = o->kf_mu + (size_t)a * KD, *xb = o->kf_mu + (size_t)b * KD;
+    const double *z = q->z + (size_t)f * 3, *p = q->p + (size_t)f * 3;
+    double h[3], J[36], L[144], e[12], r[3];
+    oracle_odometry(xa, xb, h, J);
+    for (int i = 0; i < 3; ++i) {
+        double jx = 0.0;
+        for (int j = 0; j < 6; ++j) jx += J[i*12 + j] * xa[j] + J[i*12 + 6 + j] * xb[j];
+        r[i] = z[i] - h[i] + jx;
+    }
+    for (int u = 0; u < 12; ++u) {
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i) s += J[i*12 + u] * p[i] * r[i];
+        e[u] = s;
+        for (int v = 0; v < 12; ++v) {
+            double t = 0.0;
+            for (int i = 0; i < 3; ++i) t += J[i*12 + u] * p[i] * J[i*12 + v];
+            L[u*12 + v] = t;
+        }
+    }
+    /* relinearised at every update, the factor is always inside the
+     * undamped window that follows a relinearisation (Section 8) */
+    const double d_eff = 0.0;
+    (void)damping;
+    for (int side = 0; side < 2; ++side) {
+        /* side 0: message to b (marginalise a, block offset 0); side 1: to a */
+        const int u = side == 0 ? a : b, ou = side == 0 ? 0 : 6, ov = side == 0 ? 6 : 0;
+        const double *mu_eta = (side == 0 ? q->ma_eta : q->mb_eta) + (size_t)f * KD;
+        const double *mu_lam = (side == 0 ? q->ma_lam : q->mb_lam) + (size_t)f * KD * KD;
+        const double *old_eta = (side == 0 ? q->mb_eta : q->ma_eta) + (size_t)f * KD;
+        const double *old_lam = (side == 0 ? q->mb_lam : q->ma_lam) + (size_t)f * KD * KD;
+        double *out_eta = (side == 0 ? q->nb_eta : q->na_eta) + (size_t)f * KD;
+        double *out_lam = (side == 0 ? q->nb_lam : q->na_lam) + (size_t)f * KD * KD;
+        double A[KD*KD], X[KD*(KD+1)];
+        for (int i = 0; i < KD; ++i) {
+            for (int j = 0; j < KD; ++j) {
+                A[i*KD + j] = L[(ou+i)*12 + ou + j] + o->kf_lam[(size_t)u*KD*KD + i*KD + j] - mu_lam[i*KD + j];
+                X[i*(KD+1) + j] = L[(ou+i)*12 + ov + j];
+            }
+            X[i*(KD+1) + KD] = e[ou+i] + o->kf_eta[(size_t)u*KD + i] - mu_eta[i];
+        }
+        if (solve_dense(KD, A, X, KD + 1) != 0) return -1;
+        for (int i = 0; i < KD; ++i) {
+            double se = e[ov+i];
+            for (int k = 0; k < KD; ++k) se -= L[(ov+i)*12 + ou + k] * X[k*(KD+1) + KD];
+            out_eta[i] = (1.0 - d_eff) * se + d_eff * old_eta[i];
+            for (int j = 0; j < KD; ++j) {
+                double sl = L[(ov+i)*12 + ov + j];
+                for (int k = 0; k < KD; ++k) sl -= L[(ov+i)*12 + ou + k] * X[k*(KD+1) + j];
+                out_lam[i*KD + j] = o->damp_lambda ? (1.0 - d_eff) * sl + d_eff * old_lam[i*KD + j] : sl;
+            }
+        }
+    }
+    return 0;
 }
 
 /* Messages of pairwise factor f (kind: 0 keyframes, 1 landmarks) to both
@@ -661,7 +764,7 @@ void oracle_destroy(void *h) {
                    o->ml_eta, o->ml_lam, o->nk_eta, o->nk_lam, o->nl_eta, o->nl_lam,
                    o->k_ptr, o->k_adj, o->l_ptr, o->l_adj };
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; ++i) free(ps[i]);
-    for (int kind = 0; kind < 2; ++kind) {
+    for (int kind = 0; kind < 3; ++kind) {
         struct pairs *q = &o->pr[kind];
         void *qs[] = { q->a, q->b, q->cnt, q->z, q->p, q->ma_eta, q->ma_lam, q->mb_eta,
                        q->mb_lam, q->na_eta, q->na_lam, q->nb_eta, q->nb_lam };
@@ -697,10 +800,10 @@ int oracle_iterate(void *h, int n, double damping, double huber_k) {
             if (factor_messages(o, f, damping) != 0) bad++;
             o->cnt[f] += 1;
         }
-        for (int kind = 0; kind < 2; ++kind) {
+        for (int kind = 0; kind < 3; ++kind) {
             struct pairs *q = &o->pr[kind];
             for (int f = 0; f < q->n; ++f) {
-                if (pair_messages(o, kind, f, damping) != 0) bad++;
+                if ((kind == 2 ? odometry_messages(o, f, damping) : pair_messages(o, kind, f, damping)) != 0) bad++;
                 q->cnt[f] += 1;
             }
             double *u;
@@ -869,11 +972,11 @@ int oracle_add(void *h, int n_new_kf, const double *kf_init, const double *kf_an
  * bad index, a non-positive precision or an allocation failure. */
 int oracle_add_pairs(void *h, int kind, int n, const int *a, const int *b, const double *z, const double *prec) {
     oracle_t *o = h;
-    if (kind < 0 || kind > 1 || n < 0) return -1;
-    const int D = pair_dim(kind), nv = kind == 0 ? o->nk : o->nl;
+    if (kind < 0 || kind > 2 || n < 0) return -1;
+    const int D = pair_dim(kind), MD = pair_mdim(kind), nv = kind == 1 ? o->nl : o->nk;
     for (int i = 0; i < n; ++i) {
         if (a[i] < 0 || a[i] >= nv || b[i] < 0 || b[i] >= nv || a[i] == b[i]) return -1;
-        for (int j = 0; j < D; ++j) if (!(prec[(size_t)i*D + j] > 0.0)) return -1;
+        for (int j = 0; j < MD; ++j) if (!(prec[(size_t)i*MD + j] > 0.0)) return -1;
     }
     struct pairs *q = &o->pr[kind];
     const int nn = q->n + n;
@@ -887,7 +990,7 @@ int oracle_add_pairs(void *h, int kind, int n, const int *a, const int *b, const
         }
         double **ds[] = { &q->z, &q->p, &q->ma_eta, &q->mb_eta, &q->na_eta, &q->nb_eta };
         for (int r = 0; r < 6; ++r) {
-            double *t = realloc(*ds[r], sizeof(double) * cap * D);
+            double *t = realloc(*ds[r], sizeof(double) * cap * (r < 2 ? MD : D));
             if (!t) return -1;
             *ds[r] = t;
         }
@@ -902,8 +1005,8 @@ int oracle_add_pairs(void *h, int kind, int n, const int *a, const int *b, const
     for (int i = 0; i < n; ++i) {
         const int f = q->n + i;
         q->a[f] = a[i]; q->b[f] = b[i]; q->cnt[f] = 0;
-        memcpy(q->z + (size_t)f*D, z + (size_t)i*D, sizeof(double) * D);
-        memcpy(q->p + (size_t)f*D, prec + (size_t)i*D, sizeof(double) * D);
+        memcpy(q->z + (size_t)f*MD, z + (size_t)i*MD, sizeof(double) * MD);
+        memcpy(q->p + (size_t)f*MD, prec + (size_t)i*MD, sizeof(double) * MD);
         memset(q->ma_eta + (size_t)f*D, 0, sizeof(double) * D);
         memset(q->mb_eta + (size_t)f*D, 0, sizeof(double) * D);
         memset(q->ma_lam + (size_t)f*D*D, 0, sizeof(double) * D * D);

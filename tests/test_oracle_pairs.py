@@ -129,3 +129,87 @@ def test_bad_pairs_are_rejected(oracle_mod):
     for a, b, prec in (([0], [0], pr), ([0], [50], pr), ([-1], [2], pr), ([0], [1], np.zeros((1, 3)))):
         with pytest.raises(ValueError):
             o.add_pairs(1, a, b, z, prec)
+
+
+# --------------------------------------------------------------------------
+# odometry factors: displacement of the camera centres (kind 2)
+# --------------------------------------------------------------------------
+
+def _centre(x):
+    from scipy.spatial.transform import Rotation
+    return -Rotation.from_rotvec(x[:3]).as_matrix().T @ x[3:]
+
+
+def test_odometry_measurement_and_jacobian(oracle_mod):
+    """h = c_b - c_a against scipy's rotation, J against central
+    differences of that independent h."""
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        xa = np.r_[rng.normal(0, 0.6, 3), rng.normal(0, 2, 3)]
+        xb = np.r_[rng.normal(0, 0.6, 3), rng.normal(0, 2, 3)]
+        h, J = oracle_mod.odometry(xa, xb)
+        f = lambda x: _centre(x[6:]) - _centre(x[:6])  # noqa: E731
+        x = np.r_[xa, xb]
+        assert np.abs(h - f(x)).max() < 1e-12
+        Jn = np.zeros((3, 12))
+        for i in range(12):
+            d = np.zeros(12)
+            d[i] = 1e-6
+            Jn[:, i] = (f(x + d) - f(x - d)) / 2e-6
+        assert np.abs(J - Jn).max() < 1e-7 * max(1.0, np.abs(Jn).max())
+
+
+def _map_by_gauss_newton(x0, anchors, a, b, z, prec, iters=100):
+    """MAP of anchored keyframes plus odometry terms by dense Gauss-Newton
+    with numerical Jacobians of the scipy-based centres."""
+    nk = x0.shape[0]
+    x = x0.copy().ravel()
+    for _ in range(iters):
+        H = np.diag(np.repeat(anchors, 6)).astype(float)
+        g = np.repeat(anchors, 6) * (x0.ravel() - x)
+        for i in range(len(a)):
+            ia, ib = slice(6 * a[i], 6 * a[i] + 6), slice(6 * b[i], 6 * b[i] + 6)
+            xa, xb = x[ia], x[ib]
+            r = z[i] - (_centre(xb) - _centre(xa))
+            J = np.zeros((3, 12))
+            for k in range(6):
+                d = np.zeros(6)
+                d[k] = 1e-6
+                J[:, k] = -(_centre(xa + d) - _centre(xa - d)) / 2e-6
+                J[:, 6 + k] = (_centre(xb + d) - _centre(xb - d)) / 2e-6
+            P = np.diag(prec[i])
+            idx = np.r_[np.arange(6 * a[i], 6 * a[i] + 6), np.arange(6 * b[i], 6 * b[i] + 6)]
+            H[np.ix_(idx, idx)] += J.T @ P @ J
+            g[idx] += J.T @ P @ r
+        dx = np.linalg.solve(H, g)
+        x += dx
+        if np.abs(dx).max() < 1e-13:
+            break
+    return x.reshape(nk, 6)
+
+
+@pytest.mark.parametrize("damping", [0.0, 0.4])
+def test_odometry_chain_reaches_the_map(oracle_mod, damping):
+    """Anchored keyframes joined by odometry factors (a chain): relinearised
+    at every update (hence never damped: always inside the window that
+    follows a relinearisation), GBP settles at the MAP of the nonlinear
+    objective, whatever the damping setting."""
+    nk = 5
+    rng = np.random.default_rng(9)
+    p = keyframes_only(nk, seed=4, anchor=np.array([1e4, 2.0, 2.0, 2.0, 2.0]))
+    a, b = np.arange(nk - 1), np.arange(1, nk)
+    z = np.array([_centre(p.kf_init[j]) - _centre(p.kf_init[i]) for i, j in zip(a, b)]) \
+        + rng.normal(0, 0.3, (nk - 1, 3))
+    prec = rng.uniform(20.0, 200.0, (nk - 1, 3))
+    o = oracle_mod.Oracle(p, **FROZEN)
+    o.add_pairs(2, a, b, z, prec)
+    x_map = _map_by_gauss_newton(p.kf_init, p.kf_anchor_info, a, b, z, prec)
+    prev = None
+    for _ in range(300):
+        o.iterate(10, damping=damping)
+        cur = o.beliefs()["kf_mu"]
+        if prev is not None and np.abs(cur - prev).max() < 1e-13:
+            break
+        prev = cur
+    assert np.abs(cur - x_map).max() < 1e-8 * max(1.0, np.abs(x_map).max())
+    assert np.abs(x_map - p.kf_init).max() > 1e-2   # the odometry moved the poses
