@@ -205,6 +205,14 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
  * GBP_ESTATE. gbp_reset zeroes their messages and keeps them. */
 #define GBP_PAIR_KEYFRAMES 0
 #define GBP_PAIR_LANDMARKS 1
+/* kind GBP_PAIR_ODOMETRY: an odometry factor between keyframes a and b
+ * measuring the displacement of their camera centres in the world frame,
+ * c_b - c_a ~ N(z, diag(precision)^-1) with c = -R(omega)^T t (z,
+ * precision: [n][3]). Nonlinear: it is linearised at the current means at
+ * every update and therefore, like any factor in the window that follows a
+ * relinearisation, sends undamped messages. Same storage, rules and errors
+ * as the keyframe difference factors. */
+#define GBP_PAIR_ODOMETRY 2
 gbp_status gbp_add_pair_factors(gbp_problem *p, int32_t kind, int32_t n,
                                 const int32_t *a, const int32_t *b,
                                 const double *z, const double *precision);

@@ -15,10 +15,11 @@ import numpy as np
 
 from . import _capi
 from ._capi import (GBP_FP32, GBP_FP64, GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA,
-                    GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS, HipLibraryMissing, gbp_reproj)
+                    GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS, GBP_PAIR_ODOMETRY, HipLibraryMissing,
+                    gbp_reproj)
 
 __all__ = ["GBPSolver", "GBPError", "GBP_FP32", "GBP_FP64", "GBP_DAMP_ETA",
-           "GBP_DAMP_ETA_LAMBDA", "GBP_PAIR_KEYFRAMES", "GBP_PAIR_LANDMARKS", "HipLibraryMissing", "load_library", "mlp_infer",
+           "GBP_DAMP_ETA_LAMBDA", "GBP_PAIR_KEYFRAMES", "GBP_PAIR_LANDMARKS", "GBP_PAIR_ODOMETRY", "HipLibraryMissing", "load_library", "mlp_infer",
            "MLPTrainer", "MLP_PARAMS", "MLP_FEATURES"]
 
 MLP_PARAMS = _capi.MLP_PARAMS
@@ -248,8 +249,9 @@ class GBPSolver:
     def add_pair_factors(self, kind: int, a, b, z, precision) -> None:
         """Pairwise difference factors x_b - x_a ~ N(z, diag(precision)^-1)
         between keyframes (GBP_PAIR_KEYFRAMES, 6 values per factor) or
-        landmarks (GBP_PAIR_LANDMARKS, 3 values); indices in the caller's
-        order (problem-major for batches)."""
+        landmarks (GBP_PAIR_LANDMARKS, 3 values), or odometry factors on the
+        camera centres of two keyframes (GBP_PAIR_ODOMETRY, 3 values);
+        indices in the caller's order (problem-major for batches)."""
         D = 6 if kind == GBP_PAIR_KEYFRAMES else 3
         a_, b_ = _i32(np.asarray(a).ravel()), _i32(np.asarray(b).ravel())
         z_ = _f64(np.asarray(z, dtype=np.float64).reshape(-1, D))

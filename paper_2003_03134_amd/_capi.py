@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libgbp_hip.so")
 GBP_OK, GBP_EINVAL, GBP_ENOMEM, GBP_EDEVICE, GBP_ENUMERIC, GBP_ESTATE = 0, -1, -2, -3, -4, -5
 GBP_FP64, GBP_FP32 = 0, 1
 GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA = 0, 1
-GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS = 0, 1
+GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS, GBP_PAIR_ODOMETRY = 0, 1, 2
 
 STATUS_NAMES = {0: "GBP_OK", -1: "GBP_EINVAL", -2: "GBP_ENOMEM", -3: "GBP_EDEVICE",
                 -4: "GBP_ENUMERIC", -5: "GBP_ESTATE"}

@@ -100,6 +100,7 @@ struct gbp_problem {
     // state, their variables' pair lists and the belief information
     std::vector<int> h_pair_ab[2];
     std::vector<double> h_pair_zp[2];
+    std::vector<int> h_pair_type0;  // keyframe pairs: 0 difference, 1 odometry
     void *pair_mem = nullptr;
     size_t pair_state_bytes = 0;   // leading bytes that hold messages and counts
     int every_k = 5;
@@ -1027,13 +1028,15 @@ gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double
 // lists of the variables, and recompute the beliefs so that the belief
 // information the pair update reads exists before the next iteration.
 template <typename TS>
-gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, const std::vector<double> &zp) {
+gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, const std::vector<double> &zp,
+                      int type) {
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
     HIP_TRY(p, hipStreamSynchronize(s));
     const int n_old[2] = {d.n_pair[0], d.n_pair[1]};
     p->h_pair_ab[kind].insert(p->h_pair_ab[kind].end(), ab.begin(), ab.end());
     p->h_pair_zp[kind].insert(p->h_pair_zp[kind].end(), zp.begin(), zp.end());
+    if (kind == 0) p->h_pair_type0.insert(p->h_pair_type0.end(), ab.size() / 2, type);
     const int n[2] = {(int)p->h_pair_ab[0].size() / 2, (int)p->h_pair_ab[1].size() / 2};
     const int Ds[2] = {6, 3};
     // layout: messages and counts first (the state that reset clears and
@@ -1049,6 +1052,8 @@ gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, cons
         L.add((void **)&abd[k], (size_t)n[k] * 2 * 4);
         L.add((void **)&zpd[k], (size_t)n[k] * 2 * Ds[k] * 8);
     }
+    int *typed = nullptr;
+    L.add((void **)&typed, (size_t)n[0] * 4);
     // pair lists: entry 2 i + side (side 0: end a, 1: end b), increasing i
     std::vector<int> row[2], ent[2];
     const int nv[2] = {p->nk, p->nl};
@@ -1074,6 +1079,8 @@ gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, cons
     if (hipMalloc(&mem, L.total) != hipSuccess) return fail(p, GBP_ENOMEM, "cannot allocate the pairwise factors");
     for (auto &it : L.items) *it.first = (char *)mem + it.second;
     HIP_TRY(p, hipMemsetAsync(mem, 0, state_bytes, s));
+    if (n[0] > 0)
+        HIP_TRY(p, hipMemcpyAsync(typed, p->h_pair_type0.data(), (size_t)n[0] * 4, hipMemcpyHostToDevice, s));
     for (int k = 0; k < 2; ++k) {
         if (n_old[k] > 0) {
             HIP_TRY(p, hipMemcpyAsync(msg[k], d.pair_msg[k], (size_t)n_old[k] * pair_msg_doubles(Ds[k]) * 8,
@@ -1099,6 +1106,7 @@ gbp_status pairs_impl(gbp_problem *p, int kind, const std::vector<int> &ab, cons
         d.pair_cnt[k] = cnt[k];
         d.pair_msg[k] = msg[k];
     }
+    d.pair_type0 = typed;
     d.kp_row = rowd[0]; d.kp_ent = entd[0];
     d.lp_row = rowd[1]; d.lp_ent = entd[1];
     d.kf_binfo = kbi;
@@ -1375,31 +1383,38 @@ gbp_status gbp_add_pair_factors(gbp_problem *p, int32_t kind, int32_t n, const i
                                 const double *z, const double *precision) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
-    if (kind != GBP_PAIR_KEYFRAMES && kind != GBP_PAIR_LANDMARKS)
-        return fail(p, GBP_EINVAL, "gbp_add_pair_factors: kind must be GBP_PAIR_KEYFRAMES or GBP_PAIR_LANDMARKS");
+    if (kind != GBP_PAIR_KEYFRAMES && kind != GBP_PAIR_LANDMARKS && kind != GBP_PAIR_ODOMETRY)
+        return fail(p, GBP_EINVAL,
+                    "gbp_add_pair_factors: kind must be GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS or GBP_PAIR_ODOMETRY");
     if (n < 0 || (n > 0 && (!a || !b || !z || !precision)))
         return fail(p, GBP_EINVAL, "gbp_add_pair_factors: need n >= 0 and the four arrays");
     if (p->grown) return fail(p, GBP_ESTATE, "gbp_add_pair_factors: the problem has grown since creation");
     if (n == 0) return GBP_OK;
-    const int D = kind == GBP_PAIR_KEYFRAMES ? 6 : 3, nv = kind == GBP_PAIR_KEYFRAMES ? p->nk : p->nl;
+    // odometry factors live with the keyframe pairs (D = 6 storage, 3 values
+    // measured, the rest zero)
+    const bool kfk = kind != GBP_PAIR_LANDMARKS;
+    const int D = kfk ? 6 : 3, MD = kind == GBP_PAIR_LANDMARKS ? 3 : (kind == GBP_PAIR_ODOMETRY ? 3 : 6);
+    const int nv = kfk ? p->nk : p->nl;
     std::vector<int> u2i(nv);
-    for (int i = 0; i < nv; ++i) u2i[kind == GBP_PAIR_KEYFRAMES ? i : p->lm_int2user[i]] = i;
+    for (int i = 0; i < nv; ++i) u2i[kfk ? i : p->lm_int2user[i]] = i;
     std::vector<int> ab(2 * (size_t)n);
-    std::vector<double> zp(2 * (size_t)D * n);
+    std::vector<double> zp(2 * (size_t)D * n, 0.0);
     for (int i = 0; i < n; ++i) {
         if (a[i] < 0 || a[i] >= nv || b[i] < 0 || b[i] >= nv || a[i] == b[i])
             return fail(p, GBP_EINVAL, "gbp_add_pair_factors: variable index out of range or a == b");
         ab[2 * (size_t)i] = u2i[a[i]];
         ab[2 * (size_t)i + 1] = u2i[b[i]];
-        for (int j = 0; j < D; ++j) {
-            const double zz = z[(size_t)D * i + j], pr = precision[(size_t)D * i + j];
+        for (int j = 0; j < MD; ++j) {
+            const double zz = z[(size_t)MD * i + j], pr = precision[(size_t)MD * i + j];
             if (!std::isfinite(zz) || !(pr > 0.0) || !std::isfinite(pr))
                 return fail(p, GBP_EINVAL, "gbp_add_pair_factors: z must be finite and precisions positive");
             zp[2 * (size_t)D * i + j] = zz;
             zp[2 * (size_t)D * i + D + j] = pr;
         }
     }
-    return p->precision == GBP_FP32 ? pairs_impl<float>(p, kind, ab, zp) : pairs_impl<double>(p, kind, ab, zp);
+    const int store = kfk ? 0 : 1, type = kind == GBP_PAIR_ODOMETRY ? 1 : 0;
+    return p->precision == GBP_FP32 ? pairs_impl<float>(p, store, ab, zp, type)
+                                    : pairs_impl<double>(p, store, ab, zp, type);
 }
 
 gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6], int32_t n_new_lm, const double *lm_init,

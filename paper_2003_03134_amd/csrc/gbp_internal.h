@@ -96,6 +96,7 @@ struct Dev {
     // FP64, messages relative to the variables' anchors
     int n_pair[2];
     const int *pair_ab[2];                // ends a, b of each pair
+    const int *pair_type0;                // keyframe pairs: 0 difference, 1 odometry (camera centres)
     const double *pair_zp[2];             // measured x_b - x_a (D) and diagonal precision (D)
     int *pair_cnt[2];                     // updates since the pair was added
     double *pair_msg[2];                  // pair_msg_doubles(D) per pair

@@ -810,14 +810,150 @@ __device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind,
     d.pair_cnt[kind][i] = c < (1 << 30) ? c + 1 : c;
 }
 
+// Camera centre c = -R(omega)^T t of pose x and dc/dx (3x6, row-major):
+// dc/domega = [c]x J_r(omega) (from Exp(omega + e) ~ Exp(omega) Exp(J_r e)),
+// dc/dt = -R^T.
+__device__ __forceinline__ void centre_jacobian(const double x[6], double c[3], double Jc[18]) {
+    double R[9], Jr[9];
+    so3_exp_d(x, R);
+    so3_jr_d(x, Jr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[i] = -(R[i] * x[3] + R[3 + i] * x[4] + R[6 + i] * x[5]);
+    const double S[9] = {0.0, -c[2], c[1], c[2], 0.0, -c[0], -c[1], c[0], 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Jc[6 * i + j] = S[3 * i] * Jr[j] + S[3 * i + 1] * Jr[3 + j] + S[3 * i + 2] * Jr[6 + j];
+            Jc[6 * i + 3 + j] = -R[3 * j + i];
+        }
+}
+
+// Odometry factor between keyframes a and b: c_b - c_a ~ N(z, diag(p)^-1)
+// (3 values), linearised at the current means at every update (so always
+// inside the undamped window that follows a relinearisation: undamped).
+// With J = [J_a | J_b] = [-dc_a/dx | dc_b/dx] and r = z - h(x0) + J d0
+// (d0: the mean offsets from the anchors), the factor is Lambda = J^T P J,
+// eta = J^T P r. The message to v marginalises u: S = J_u^T P J_u + Lambda_c,
+// y = S^-1 (J_u^T P r + eta_c), Q = J_u S^-1 J_u^T; message Lambda =
+// J_v^T (P - P Q P) J_v, eta = J_v^T (P r - P J_u y).
+template <typename TS>
+__device__ void odometry_update(const Dev<TS> &d, const int i) {
+    constexpr int T = 21, MS = pair_msg_doubles(6);
+    const int a = d.pair_ab[0][2 * i], b = d.pair_ab[0][2 * i + 1];
+    const double *zp = d.pair_zp[0] + 12 * (size_t)i;
+    double *msg = d.pair_msg[0] + MS * (size_t)i;
+    double xa[6], xb[6], ca[3], cb[3], Ja[18], Jb[18];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        xa[j] = d.kf_anchor[6 * (size_t)a + j] + d.kf_bel[KBEL * (size_t)a + j];
+        xb[j] = d.kf_anchor[6 * (size_t)b + j] + d.kf_bel[KBEL * (size_t)b + j];
+    }
+    centre_jacobian(xa, ca, Ja);
+    centre_jacobian(xb, cb, Jb);
+    double r[3], P[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double jd = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            jd += -Ja[6 * q + j] * d.kf_bel[KBEL * (size_t)a + j] + Jb[6 * q + j] * d.kf_bel[KBEL * (size_t)b + j];
+        r[q] = zp[q] - (cb[q] - ca[q]) + jd;
+        P[q] = zp[6 + q];
+    }
+    double out[2][6 + T];
+    bool ok = true;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        // side 0: message to b (u = a, J_u = -Ja); side 1: message to a
+        const int u = side == 0 ? a : b;
+        const double su = side == 0 ? -1.0 : 1.0, sv = -su;
+        const double *Ju = side == 0 ? Ja : Jb, *Jv = side == 0 ? Jb : Ja;
+        const double *mu = msg + (side == 0 ? 0 : 6 + T);  // old message to u
+        const double *bu = d.kf_binfo + (size_t)KBI * u;
+        double S[T], rhs[6];
+#pragma unroll
+        for (int x = 0; x < 6; ++x) {
+#pragma unroll
+            for (int y = x; y < 6; ++y) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) t += Ju[6 * q + x] * P[q] * Ju[6 * q + y];  // signs cancel
+                S[pidx<6>(x, y)] = t + bu[pidx<6>(x, y)] - mu[6 + pidx<6>(x, y)];
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) t += su * Ju[6 * q + x] * P[q] * r[q];
+            rhs[x] = t + bu[21 + x] - mu[x];
+        }
+        double L[T], inv[T], y[6];
+        if (!chol<6>(S, L)) { ok = false; break; }
+        chol_inverse_solve<6>(L, rhs, inv, y);
+        // Q = J_u S^-1 J_u^T (the signs of J_u cancel), core = P - P Q P
+        double core[6], ce[3];
+        double JS[3][6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int x = 0; x < 6; ++x) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < 6; ++w) t += Ju[6 * q + w] * inv[pidx<6>(w, x)];
+                JS[q][x] = t;
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+            for (int s2 = q; s2 < 3; ++s2) {
+                double t = 0.0;
+#pragma unroll
+                for (int x = 0; x < 6; ++x) t += JS[q][x] * Ju[6 * s2 + x];
+                core[pidx<3>(q, s2)] = (q == s2 ? P[q] : 0.0) - P[q] * t * P[s2];
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int x = 0; x < 6; ++x) t += su * Ju[6 * q + x] * y[x];
+            ce[q] = P[q] * r[q] - P[q] * t;
+        }
+        double *w = out[side];
+#pragma unroll
+        for (int x = 0; x < 6; ++x) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) t += sv * Jv[6 * q + x] * ce[q];
+            w[x] = t;
+#pragma unroll
+            for (int y2 = x; y2 < 6; ++y2) {
+                double s3 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int q2 = 0; q2 < 3; ++q2) s3 += Jv[6 * q + x] * core[pidx<3>(q, q2)] * Jv[6 * q2 + y2];
+                w[6 + pidx<6>(x, y2)] = s3;
+            }
+        }
+    }
+    if (!ok) { atomicOr(d.status, 1u); return; }
+#pragma unroll
+    for (int q = 0; q < 6 + T; ++q) {
+        msg[6 + T + q] = out[0][q];  // to b
+        msg[q] = out[1][q];          // to a
+    }
+    d.pair_cnt[0][i] = d.pair_cnt[0][i] + 1;
+}
+
 // Pairwise factors, one per thread (keyframe pairs first). A kernel of its
 // own, launched only while pairs exist: inside the relinearisation launch
 // its registers halved that kernel's occupancy.
 template <typename TS>
 __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < d.n_pair[0]) pair_update<TS, 6>(d, o, 0, i);
-    else if (i < d.n_pair[0] + d.n_pair[1]) pair_update<TS, 3>(d, o, 1, i - d.n_pair[0]);
+    if (i < d.n_pair[0]) {
+        if (d.pair_type0[i] == 1) odometry_update<TS>(d, i);
+        else pair_update<TS, 6>(d, o, 0, i);
+    } else if (i < d.n_pair[0] + d.n_pair[1]) {
+        pair_update<TS, 3>(d, o, 1, i - d.n_pair[0]);
+    }
 }
 
 // Queue segment of residual block b: relinearise and send (marks done); one

@@ -159,7 +159,7 @@ def test_bad_pairs_and_growth_are_rejected(gbp):
     z3, one3 = np.zeros((1, 3)), np.ones((1, 3))
     bad = [(1, [0], [0], z3, one3), (1, [0], [50], z3, one3), (1, [-1], [3], z3, one3),
            (1, [0], [1], z3, np.zeros((1, 3))), (1, [0], [1], np.full((1, 3), np.nan), one3),
-           (2, [0], [1], z3, one3)]
+           (3, [0], [1], z3, one3), (2, [0], [50], z3, one3)]
     for args in bad:
         with pytest.raises(gbp.GBPError) as e:
             s.add_pair_factors(*args)
@@ -168,4 +168,78 @@ def test_bad_pairs_and_growth_are_rejected(gbp):
     with pytest.raises(gbp.GBPError) as e:
         s.add_keyframe(prob.kf_init[1], np.zeros((0, 3)), [], [], np.zeros((0, 2)))
     assert e.value.status == -5
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# odometry factors (camera-centre displacement, relinearised every update)
+# --------------------------------------------------------------------------
+
+def _centres(x):
+    from scipy.spatial.transform import Rotation
+    return np.array([-Rotation.from_rotvec(v[:3]).as_matrix().T @ v[3:] for v in x])
+
+
+def odometry_ring(p, seed=3, closed=True, prec=(10, 100)):
+    rng = np.random.default_rng(seed)
+    nk = p.n_keyframes
+    a = np.arange(nk if closed else nk - 1)
+    b = (a + 1) % nk
+    c = _centres(p.kf_true)
+    z = c[b] - c[a] + rng.normal(0, 0.02, (len(a), 3))
+    return (2, a, b, z, rng.uniform(*prec, (len(a), 3)))
+
+
+@pytest.mark.parametrize("damp_lambda", [False, True])
+def test_fp64_odometry_with_difference_and_landmark_pairs(gbp, damp_lambda):
+    """Odometry ring plus difference factors of both kinds on the circle
+    problem, forced relinearisation of the measurement factors."""
+    prob = synth.make_config0(seed=0)
+    s, o = pair(gbp, prob, gbp.GBP_FP64, damp_lambda=damp_lambda)
+    add_both(s, o, ring_and_lm_pairs(prob) + (odometry_ring(prob),))
+    for it in range(10):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        g, r = s.beliefs(info=True), o.beliefs()
+        assert mean_errs(g, r) < 1e-8, it
+        assert info_err(g, r) < 1e-8, it
+        s.relinearise(-1)
+        o.relinearise(-1)
+    s.close()
+
+
+def test_odometry_chain_without_measurements(gbp):
+    from tests.test_oracle_pairs import keyframes_only
+    p = keyframes_only(6, seed=4, anchor=np.array([1e4] + [2.0] * 5))
+    rng = np.random.default_rng(2)
+    a, b = np.arange(5), np.arange(1, 6)
+    c = _centres(p.kf_init)
+    z, pr = c[b] - c[a] + rng.normal(0, 0.3, (5, 3)), rng.uniform(20, 200, (5, 3))
+    s, o = pair(gbp, p, gbp.GBP_FP64)
+    s.add_pair_factors(gbp.GBP_PAIR_ODOMETRY, a, b, z, pr)
+    o.add_pairs(2, a, b, z, pr)
+    for it in range(4):
+        s.iterate(15, 0.4, 2.0)
+        o.iterate(15, 0.4, 2.0)
+        g, r = s.beliefs(info=True), o.beliefs()
+        assert np.abs(g["kf_mu"] - r["kf_mu"]).max() < 1e-8 * max(1.0, np.abs(r["kf_mu"]).max()), it
+        assert np.abs(g["kf_lam"] - r["kf_lam"]).max() < 1e-8 * np.abs(r["kf_lam"]).max(), it
+    assert np.abs(g["kf_mu"] - p.kf_init).max() > 1e-2
+    s.close()
+
+
+def test_fp32_odometry_on_the_paper_scale_problem(gbp):
+    prob = synth.make_config1()
+    s, o = pair(gbp, prob, gbp.GBP_FP32)
+    add_both(s, o, (odometry_ring(prob, closed=False),))
+    worst = 0.0
+    for it in range(6):
+        s.iterate(10, 0.4, 2.0)
+        o.iterate(10, 0.4, 2.0)
+        e = mean_errs(s.beliefs(), o.beliefs())
+        worst = max(worst, e)
+        assert e < 1e-4, (it, e)
+        s.relinearise(-1)
+        o.relinearise(-1)
+    print(f"config1 FP32 with odometry: worst relative mean error {worst:.2e}")
     s.close()
