@@ -956,20 +956,25 @@ __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
     }
 }
 
-// Queue segment of residual block b: relinearise and send (marks done); one
-// wave per segment, since a segment holds few due factors in steady state.
+// Queue segment of residual block b: relinearise and send (marks done); two
+// waves per segment (a segment holds ~22 due factors in most iterations, but
+// up to its 256 when a cohort of factors comes due together: one wave then
+// looped four times; with four waves the empty ones cost more than that).
 // The next nred workgroups (nred = np or 0) reduce the residual statistics
 // of the previous iteration's fused residual pass (whose check advanced the
 // clock: t_off -1) into log_row.
+constexpr int RELIN_BS = 128;
+
 template <typename TS>
-__global__ __launch_bounds__(64) void k_relin(Dev<TS> d, IterOpts o, int nseg, int nred, double *log_row) {
+__global__ __launch_bounds__(RELIN_BS) void k_relin(Dev<TS> d, IterOpts o, int nseg, int nred, double *log_row) {
     if ((int)blockIdx.x >= nseg) {
+        if (threadIdx.x >= 64) return;  // one wave per problem
         reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
         return;
     }
     const int b = xcd_remap(blockIdx.x, nseg);
     const int n = d.relin_qcount[b];
-    for (int i = threadIdx.x; i < n; i += 64) {
+    for (int i = threadIdx.x; i < n; i += RELIN_BS) {
         const int f = d.relin_queue[(size_t)b * RBLK + i];
         const int k = d.f_kf[f];
         factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
@@ -1742,7 +1747,7 @@ template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
     const int nred = pending_log_row ? d.np : 0;
     const int g = d.n_rblk + nred;
-    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(64), 0, s, d, o, d.n_rblk, nred, pending_log_row);
+    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(RELIN_BS), 0, s, d, o, d.n_rblk, nred, pending_log_row);
     // pairwise factors: they read the previous iteration's beliefs and
     // their own messages only, like the relinearised factors
     const int np = d.n_pair[0] + d.n_pair[1];
