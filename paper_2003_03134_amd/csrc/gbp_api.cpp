@@ -133,11 +133,23 @@ struct Layout {
     }
 };
 
+gbp_status put_lm_anchors(gbp_problem *p, double *lm_bel, int m0, int n, const double *src, hipStream_t s) {
+    if (n <= 0) return GBP_OK;
+    HIP_TRY(p, hipMemcpy2DAsync(lm_bel + (size_t)m0 * LBEL + LANC, LBEL * 8, src, 3 * 8, 3 * 8, (size_t)n,
+                                hipMemcpyHostToDevice, s));
+    return GBP_OK;
+}
+
+gbp_status get_lm_anchors(gbp_problem *p, const double *lm_bel, int n, double *dst, hipStream_t s) {
+    if (n <= 0) return GBP_OK;
+    HIP_TRY(p, hipMemcpy2DAsync(dst, 3 * 8, lm_bel + LANC, LBEL * 8, 3 * 8, (size_t)n, hipMemcpyDeviceToHost, s));
+    return GBP_OK;
+}
+
 template <typename TS>
 void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     const size_t K = p->cap_k, M = p->cap_l, F = p->cap_f, P = p->np;
     L.add((void **)&d.kf_anchor, K * 6 * 8);
-    L.add((void **)&d.lm_anchor, M * 3 * 8);
     L.add((void **)&d.kf_pbase, K * 6 * 8);
     L.add((void **)&d.lm_pbase, M * 3 * 8);
     L.add((void **)&d.kf_pinfo, K * 8);
@@ -256,6 +268,11 @@ template <>
 Dev<float> &dev<float>(gbp_problem *p) { return p->df; }
 template <>
 Dev<double> &dev<double>(gbp_problem *p) { return p->dd; }
+
+// landmark anchors live in the landmark belief records (offset LANC,
+// stride LBEL): strided copies to and from a packed [n][3] host array
+gbp_status put_lm_anchors(gbp_problem *p, double *lm_bel, int m0, int n, const double *src, hipStream_t s);
+gbp_status get_lm_anchors(gbp_problem *p, const double *lm_bel, int n, double *dst, hipStream_t s);
 
 // Build the internal ordering of the whole (possibly batched) graph.
 void build_order(gbp_problem *p, int n, const gbp_graph *gs, const gbp_measurements *ms,
@@ -426,7 +443,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     p->h_lm_anchor0 = lm_anchor;
 #define UP(dst, src, bytes) HIP_TRY(p, hipMemcpyAsync((void *)(dst), (const void *)(src), (bytes), hipMemcpyHostToDevice, s))
     UP(d.kf_anchor, kf_anchor.data(), kf_anchor.size() * 8);
-    UP(d.lm_anchor, lm_anchor.data(), lm_anchor.size() * 8);
+    // (landmark anchors go into the belief records after they are cleared)
     UP(d.kf_pinfo, kf_pinfo.data(), kf_pinfo.size() * 8);
     UP(d.kf_prob, kf_prob.data(), kf_prob.size() * 4);
     UP(d.lm_prob, lm_prob.data(), lm_prob.size() * 4);
@@ -448,6 +465,10 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     UP(d.z, p->h_z.data(), (size_t)nf * 2 * 8);
     HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
+    {
+        gbp_status sa = put_lm_anchors(p, d.lm_bel, 0, p->nl, p->h_lm_anchor.data(), s);
+        if (sa != GBP_OK) return sa;
+    }
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
@@ -900,10 +921,11 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
         HIP_TRY(p, hipMemsetAsync(d.kf_bel + (size_t)nk0 * KBEL, 0, KBEL * 8, s));
     }
     if (n_new_lm) {
-        UP(d.lm_anchor + 3 * (size_t)nl0, lm_init, 3 * 8 * (size_t)n_new_lm);
         UP(d.lm_t0 + nl0, tl.data(), 4 * (size_t)n_new_lm);
         UP(d.lm_prob + nl0, zl.data(), 4 * (size_t)n_new_lm);
         HIP_TRY(p, hipMemsetAsync(d.lm_bel + (size_t)nl0 * LBEL, 0, (size_t)n_new_lm * LBEL * 8, s));
+        gbp_status sa = put_lm_anchors(p, d.lm_bel, nl0, n_new_lm, lm_init, s);
+        if (sa != GBP_OK) return sa;
     }
     // permute the device factor state into the new order
     UP(p->d_perm, perm.data(), (size_t)nf1 * 4);
@@ -991,7 +1013,10 @@ gbp_status depth_impl(gbp_problem *p, const std::vector<int> &lms) {
     launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
     HIP_TRY(p, hipGetLastError());
     // the host mirror of the anchors (absolute means = anchor + offset)
-    HIP_TRY(p, hipMemcpyAsync(p->h_lm_anchor.data(), d.lm_anchor, (size_t)p->nl * 3 * 8, hipMemcpyDeviceToHost, s));
+    {
+        gbp_status sa = get_lm_anchors(p, d.lm_bel, p->nl, p->h_lm_anchor.data(), s);
+        if (sa != GBP_OK) return sa;
+    }
     HIP_TRY(p, hipStreamSynchronize(s));
     return GBP_OK;
 }
@@ -1131,9 +1156,12 @@ gbp_status reset_impl(gbp_problem *p) {
     p->huber_k = p->opt.huber_k;
     p->iopt.huber_k = p->opt.huber_k;
     p->h_lm_anchor = p->h_lm_anchor0;
-    HIP_TRY(p, hipMemcpyAsync(d.lm_anchor, p->h_lm_anchor.data(), p->h_lm_anchor.size() * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(p, hipMemsetAsync(d.kf_bel, 0, (size_t)p->cap_k * KBEL * 8, s));
     HIP_TRY(p, hipMemsetAsync(d.lm_bel, 0, (size_t)p->cap_l * LBEL * 8, s));
+    {
+        gbp_status sa = put_lm_anchors(p, d.lm_bel, 0, p->nl, p->h_lm_anchor.data(), s);
+        if (sa != GBP_OK) return sa;
+    }
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));

@@ -14,7 +14,8 @@ constexpr int MMSG = 5;   // message to the landmark (dense, rewritten every ite
 constexpr int AREC = 10;  // factor-private record read by the message update
 constexpr int DREC = 12;  // factor's linearisation point (check, features)
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
-constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), pad to 128 B
+constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), anchor 3, pad to 128 B
+constexpr int LANC = 9;   // offset of the landmark's anchor (prior mean) in its belief record
 constexpr int MAX_ANNEAL = 64;
 constexpr int RTHREADS = 256;          // threads of a residual-phase block
 constexpr int RPL = 1;                 // factors per lane in the residual phase (more: slower, latency-bound)
@@ -55,7 +56,9 @@ struct Dev {
     int nk, nl, nf, np;
     // variables
     const double *kf_anchor;              // absolute initial estimate (prior mean)
-    double *lm_anchor;                    // (moved only by the learned depth)
+    // landmark anchors live in the landmarks' belief records (LANC), so that
+    // a gather of a landmark's mean and anchor touches one 128-B line; they
+    // are moved only by the learned depth
     double *kf_pbase, *lm_pbase;          // automatic prior information (diag)
     const double *kf_pinfo;               // anchor prior information (0: automatic)
     const int *kf_t0, *lm_t0;             // iteration at which the variable was born

@@ -519,7 +519,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 #pragma unroll
         for (int i = 0; i < 6; ++i) x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + dmm[i];
+        for (int i = 0; i < 3; ++i) l[i] = bm[LANC + i] + dmm[i];
         Lin L;
         linearise(x, l, zz, pp, hk, L);
 #pragma unroll
@@ -547,7 +547,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            double a = d.lm_anchor[3 * (size_t)m + i];
+            double a = bm[LANC + i];
             jam0 += Jmn[0][i] * a;
             jam1 += Jmn[1][i] * a;
         }
@@ -745,14 +745,17 @@ __device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind,
     constexpr int T = D * (D + 1) / 2, MS = pair_msg_doubles(D);
     const int a = d.pair_ab[kind][2 * i], b = d.pair_ab[kind][2 * i + 1];
     const double *zp = d.pair_zp[kind] + 2 * D * (size_t)i;
-    const double *anc = kind == 0 ? d.kf_anchor : d.lm_anchor;
+    // anchors: keyframes' own array (stride 6), landmarks' in their belief
+    // records (stride LBEL)
+    const double *anc = kind == 0 ? d.kf_anchor : d.lm_bel + LANC;
+    const int AS = kind == 0 ? 6 : LBEL;
     const double *bi = kind == 0 ? d.kf_binfo : d.lm_binfo;
     const int BI = kind == 0 ? KBI : LBI;
     double *msg = d.pair_msg[kind] + MS * (size_t)i;
     double zr[D], P[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        zr[j] = zp[j] - (anc[(size_t)D * b + j] - anc[(size_t)D * a + j]);
+        zr[j] = zp[j] - (anc[(size_t)AS * b + j] - anc[(size_t)AS * a + j]);
         P[j] = zp[D + j];
     }
     const int c = d.pair_cnt[kind][i];
@@ -794,7 +797,7 @@ __device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind,
             for (int r = 0; r < D; ++r) {
                 double t = 0.0;
 #pragma unroll
-                for (int q = 0; q < D; ++q) t += (mv[D + pidx<D>(r, q)] - w[D + pidx<D>(r, q)]) * anc[(size_t)D * v + q];
+                for (int q = 0; q < D; ++q) t += (mv[D + pidx<D>(r, q)] - w[D + pidx<D>(r, q)]) * anc[(size_t)AS * v + q];
                 corr[r] = t;
             }
 #pragma unroll
@@ -1306,7 +1309,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
 #pragma unroll
     for (int i = 0; i < 6; ++i) { dmk[i] = d.kf_bel[(size_t)k * KBEL + i]; x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i]; }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { dmm[i] = d.lm_bel[(size_t)m * LBEL + i]; l[i] = d.lm_anchor[3 * (size_t)m + i] + dmm[i]; }
+    for (int i = 0; i < 3; ++i) { dmm[i] = d.lm_bel[(size_t)m * LBEL + i]; l[i] = d.lm_bel[(size_t)m * LBEL + LANC + i] + dmm[i]; }
     Lin L;
     linearise(x, l, zz, pp, huber_k, L);
     TS *kw = d.krec + (size_t)f * KREC, *lw = d.lrec + (size_t)f * LREC, *aw = d.arec + (size_t)f * AREC;
@@ -1343,7 +1346,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        double a = d.lm_anchor[3 * (size_t)m + i];
+        double a = d.lm_bel[(size_t)m * LBEL + LANC + i];
         jam0 += L.J[0][6 + i] * a;
         jam1 += L.J[1][6 + i] * a;
     }
@@ -1574,7 +1577,7 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
             const double *bm = d.lm_bel + (size_t)m * LBEL;
             double l[3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) l[i] = d.lm_anchor[3 * (size_t)m + i] + bm[i];
+            for (int i = 0; i < 3; ++i) l[i] = bm[LANC + i] + bm[i];
             if (CHECK) {
                 need = check_due(d, o, f, d.kf_bel + (size_t)k * KBEL, bm);
                 fq = f;
@@ -1659,8 +1662,8 @@ __global__ void k_depth_move(Dev<TS> d, const int *__restrict__ lms, int n, cons
     double *bm = d.lm_bel + (size_t)m * LBEL;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const double l = d.lm_anchor[3 * (size_t)m + j] + bm[j];
-        d.lm_anchor[3 * (size_t)m + j] = c[j] + scale * (l - c[j]);
+        const double l = bm[LANC + j] + bm[j];
+        bm[LANC + j] = c[j] + scale * (l - c[j]);
         bm[j] = 0.0;
     }
 }
