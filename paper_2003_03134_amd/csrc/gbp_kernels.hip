@@ -1417,6 +1417,25 @@ __global__ __launch_bounds__(256) void k_prior_lm(Dev<TS> d, int m0) {
 // --------------------------------------------------------------------------
 
 
+// one factor's message to its landmark, J^T S J and J^T g with the message
+// in measurement space (S packed 2x2, g), added to the landmark's sums
+template <typename TS>
+__device__ __forceinline__ void lm_edge_add(double A[6], double e[3], const TS *r, const TS *mr) {
+    double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
+    double Sa = mr[0], Sb = mr[1], Sc = mr[2], g0 = mr[3], g1 = mr[4];
+    double SJ0[3], SJ1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = i; j < 3; ++j) A[pidx<3>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
+        e[i] += J0[i] * g0 + J1[i] * g1;
+    }
+}
+
+constexpr int BEL_UNR = 2;   // landmark edges in flight per lane
+
 template <typename TS, int LANES, bool WITH_KF>
 __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int readout, int nkb) {
     // WITH_KF: the first nkb workgroups turn the keyframe message sums into
@@ -1447,22 +1466,30 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
     const bool live = m < d.nl;
     double A[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
     if (live) {
-        for (int ei = d.lm_row[m] + q; ei < d.lm_row[m + 1]; ei += LANES) {
+        // the edge gathers are a chain of two dependent loads (edge index,
+        // then records): BEL_UNR edges' records are requested before the
+        // first is used, and added in edge order as in the one-edge tail
+        const int e1 = d.lm_row[m + 1];
+        int ei = d.lm_row[m] + q;
+        for (; ei + (BEL_UNR - 1) * LANES < e1; ei += BEL_UNR * LANES) {
+            int fe[BEL_UNR];
+#pragma unroll
+            for (int u = 0; u < BEL_UNR; ++u) fe[u] = d.lm_edge[ei + u * LANES];
+            TS r[BEL_UNR][LREC], mr[BEL_UNR][MMSG];
+#pragma unroll
+            for (int u = 0; u < BEL_UNR; ++u) {
+                load8(d.lrec + (size_t)fe[u] * LREC, r[u]);
+                load5(d.mmsg + (size_t)fe[u] * MMSG, mr[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < BEL_UNR; ++u) lm_edge_add(A, e, r[u], mr[u]);
+        }
+        for (; ei < e1; ei += LANES) {
             const int fe = d.lm_edge[ei];
             TS r[LREC], mr[MMSG];
             load8(d.lrec + (size_t)fe * LREC, r);
             load5(d.mmsg + (size_t)fe * MMSG, mr);
-            double J0[3] = {r[0], r[1], r[2]}, J1[3] = {r[3], r[4], r[5]};
-            double Sa = mr[0], Sb = mr[1], Sc = mr[2], g0 = mr[3], g1 = mr[4];
-            double SJ0[3], SJ1[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                for (int j = i; j < 3; ++j) A[pidx<3>(i, j)] += J0[i] * SJ0[j] + J1[i] * SJ1[j];
-                e[i] += J0[i] * g0 + J1[i] * g1;
-            }
+            lm_edge_add(A, e, r, mr);
         }
     }
 #pragma unroll
@@ -1572,30 +1599,74 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
         const int f = f0 + r * RTHREADS + (int)threadIdx.x;
         bool valid = false, lin = false, inv = false, ref = false;
         if (f < f1) {
+            // two rounds of loads: first the factor's own words (coalesced),
+            // then the gathers they index; the linearisation point and the
+            // keyframe mean are fetched only for factors old enough to be
+            // checked
             const int k = d.f_kf[f], m = d.f_lm[f];
-            const double *ps = d.kf_pose + 12 * (size_t)k;
-            const double *bm = d.lm_bel + (size_t)m * LBEL;
-            double l[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) l[i] = bm[LANC + i] + bm[i];
+            const double z0 = d.z[2 * (size_t)f], z1 = d.z[2 * (size_t)f + 1];
+            // the mask byte is read from the flags when there is no
+            // reference (uniform choice, no branch to wait in)
+            const uint32_t want_ref = (zref ? mask : d.flags)[f];
+            double zr0 = 0.0, zr1 = 0.0;
+            if (zref) {
+                zr0 = zref[2 * (size_t)f];
+                zr1 = zref[2 * (size_t)f + 1];
+            }
+            uint8_t fl = 0;
+            int cf = 0;
             if (CHECK) {
-                need = check_due(d, o, f, d.kf_bel + (size_t)k * KBEL, bm);
+                fl = d.flags[f];
+                cf = d.cnt[f];
+            }
+            const double *ps = d.kf_pose + 12 * (size_t)k;
+            double P[12];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) P[i] = ps[i];
+            const double *bm = d.lm_bel + (size_t)m * LBEL;
+            double dm[3], l[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                dm[i] = bm[i];
+                l[i] = bm[LANC + i] + dm[i];
+            }
+            if (CHECK) {
+                // due: requested by the host, or linearised at least
+                // `interval` iterations ago and farther than beta from the
+                // current means (strictly)
+                need = (fl & FLAG_PENDING) != 0;
+                const bool old_enough = (cf >= o.interval) & !need;
+                if (old_enough) {
+                    const double *bk = d.kf_bel + (size_t)k * KBEL;
+                    const TS *dr = d.drec + (size_t)f * DREC;
+                    double dist2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) { double e = dm[i] - (double)dr[6 + i]; dist2 += e * e; }
+                    need = dist2 > o.beta2;
+                }
                 fq = f;
             }
             double p[3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) p[i] = ps[3 * i] * l[0] + ps[3 * i + 1] * l[1] + ps[3 * i + 2] * l[2] + ps[9 + i];
-            if (!(p[2] > pp.zmin)) {
-                inv = true;
-            } else {
-                const double h0 = pp.fx * p[0] / p[2] + pp.cx, h1 = pp.fy * p[1] / p[2] + pp.cy;
-                const double e = hypot(d.z[2 * (size_t)f] - h0, d.z[2 * (size_t)f + 1] - h1);
+            for (int i = 0; i < 3; ++i) p[i] = P[3 * i] * l[0] + P[3 * i + 1] * l[1] + P[3 * i + 2] * l[2] + P[9 + i];
+            // a point at or behind the depth limit is counted invalid; its
+            // projection is formed with a harmless depth and discarded
+            inv = !(p[2] > pp.zmin);
+            const double pz = inv ? 1.0 : p[2];
+            const double h0 = pp.fx * p[0] / pz + pp.cx, h1 = pp.fy * p[1] / pz + pp.cy;
+            const double e = hypot(z0 - h0, z1 - h1);
+            if (!inv) {
                 valid = true;
                 s_all += e;
                 lin = N > 0.0 && e / pp.sigma > N;
                 if (!lin) s_quad += e;
-                if (zref && mask[f]) {
-                    s_ref += hypot(zref[2 * (size_t)f] - h0, zref[2 * (size_t)f + 1] - h1);
+            }
+            if (zref) {
+                const double er = hypot(zr0 - h0, zr1 - h1);
+                if (!inv && want_ref != 0) {
+                    s_ref += er;
                     ref = true;
                 }
             }
