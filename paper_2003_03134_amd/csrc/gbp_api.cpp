@@ -183,7 +183,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.status, 4);
     L.add((void **)&d.pending_k, 8);
     // relinearisation queue: one segment per residual block (F / RBLK + P + 1)
-    L.add((void **)&d.relin_queue, (F / RBLK + P + 1) * RBLK * 4);
+    L.add((void **)&d.relin_queue, (F / RBLK + P + 1) * RBLK * sizeof(RelinEntry));
     L.add((void **)&d.relin_qcount, (F / RBLK + P + 1) * 4);
     L.add((void **)&d.kf_sums, K * 32 * 8);
     L.add((void **)&p->d_total, 8);

@@ -51,6 +51,13 @@ struct ProbParams {
 };
 
 // Device view of one problem set (a single problem or a batch).
+// one queued relinearisation: the factor and its two variables (so that the
+// relinearising kernel gathers the beliefs in the same round of loads as the
+// factor's records)
+struct alignas(16) RelinEntry {
+    int f, k, m, pad;
+};
+
 template <typename TS>
 struct Dev {
     int nk, nl, nf, np;
@@ -84,7 +91,7 @@ struct Dev {
     int *t_dev;                           // iteration clock
     unsigned *status;                     // bit 0: non-PD belief, bit 1: non-finite
     double *pending_k;                    // Huber threshold for requested relinearisations
-    int *relin_queue;                     // factors due for relinearisation, RBLK per residual block
+    RelinEntry *relin_queue;              // factors due for relinearisation, RBLK per residual block
     int *relin_qcount;                    // queue entries of each residual block
     double *kf_sums;                      // per keyframe: 21 information + 6 vector sums (32)
     double *kf_pose;                      // absolute R (9) and t (3) of each keyframe mean

@@ -467,12 +467,14 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 // `stage` (may be null) receives the keyframe-side Jacobian and the new
 // stored message for the keyframe belief reduction. fd_on: whether the
 // learned per-factor damping applies (its problem has not fallen back); -1:
-// look it up for this factor.
+// look it up for this factor. m: the factor's landmark; prob, pend_k: its
+// problem and the Huber threshold of host-requested relinearisations (read
+// by RELIN only, which needs them).
 template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
-                                            const double *__restrict__ bk, TS *__restrict__ stage,
-                                            const int fd_on = -1) {
-    const int m = d.f_lm[f];
+                                            const int m, const double *__restrict__ bk,
+                                            TS *__restrict__ stage, const int fd_on = -1,
+                                            const int prob = -1, const double pend_k = 0.0) {
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
     load10(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
@@ -513,8 +515,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     double Jkn[2][6], Jmn[2][3];
     uint8_t nfl = (uint8_t)((fl & ~FLAG_PENDING) | (RELIN ? FLAG_DONE : 0));
     if constexpr (RELIN) {
-        const ProbParams pp = d.prob[d.kf_prob[k]];
-        const double hk = (fl & FLAG_PENDING) ? d.pending_k[0] : o.huber_k;
+        const ProbParams pp = d.prob[prob];
+        const double hk = (fl & FLAG_PENDING) ? pend_k : o.huber_k;
         double x[6], l[3], zz[2] = {d.z[2 * (size_t)f], d.z[2 * (size_t)f + 1]};
 #pragma unroll
         for (int i = 0; i < 6; ++i) x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i];
@@ -650,28 +652,34 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 
 // Relinearisation check (Section 5, Section 8): a pending request, or at
 // least `interval` updates since the last linearisation and the stacked means
-// farther than beta from the linearisation point. bk, bm: the keyframe and
-// landmark mean offsets.
+// farther than beta from the linearisation point (strictly). fl, cf: the
+// factor's flags and update counter; dm: the landmark's mean offset. The
+// linearisation point and the keyframe mean are read only for factors old
+// enough to be checked.
 template <typename TS>
-__device__ __forceinline__ bool check_due(const Dev<TS> &d, const IterOpts &o, const int f,
-                                          const double *__restrict__ bk, const double *__restrict__ bm) {
-    const uint8_t fl = d.flags[f];
-    if (fl & FLAG_PENDING) return true;
-    if (d.cnt[f] < o.interval) return false;
-    const TS *dr = d.drec + (size_t)f * DREC;
-    double dist2 = 0.0;
+__device__ __forceinline__ bool check_due(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
+                                          const uint8_t fl, const int cf, const double dm[3]) {
+    bool need = (fl & FLAG_PENDING) != 0;
+    const bool old_enough = (cf >= o.interval) & !need;
+    if (old_enough) {
+        const double *bk = d.kf_bel + (size_t)k * KBEL;
+        const TS *dr = d.drec + (size_t)f * DREC;
+        double dist2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
+        for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { double e = bm[i] - (double)dr[6 + i]; dist2 += e * e; }
-    return dist2 > o.beta2;
+        for (int i = 0; i < 3; ++i) { double e = dm[i] - (double)dr[6 + i]; dist2 += e * e; }
+        need = dist2 > o.beta2;
+    }
+    return need;
 }
 
 // The due factors of residual block b (RTHREADS threads, all calling) go to
 // the block's own queue segment (wave ballots and a prefix over the block's
 // waves: no atomics).
 template <typename TS>
-__device__ __forceinline__ void queue_due(const Dev<TS> &d, const int b, const int f, const bool need) {
+__device__ __forceinline__ void queue_due(const Dev<TS> &d, const int b, const int f, const int k, const int m,
+                                          const bool need) {
     __shared__ int wcount[RTHREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(need);
@@ -683,7 +691,7 @@ __device__ __forceinline__ void queue_due(const Dev<TS> &d, const int b, const i
         base += w < wave ? wcount[w] : 0;
         tot += wcount[w];
     }
-    if (need) d.relin_queue[(size_t)b * RBLK + base + __popcll(mask & ((1ull << lane) - 1ull))] = f;
+    if (need) d.relin_queue[(size_t)b * RBLK + base + __popcll(mask & ((1ull << lane) - 1ull))] = RelinEntry{f, k, m, 0};
     if (threadIdx.x == 0) d.relin_qcount[b] = tot;
 }
 
@@ -696,9 +704,17 @@ __global__ __launch_bounds__(RTHREADS) void k_check(Dev<TS> d, IterOpts o) {
     const int f = d.rblk_start[b] + (int)threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) d.t_dev[0] = d.t_dev[0] + 1;
     bool need = false;
-    if (f < d.rblk_start[b + 1])
-        need = check_due(d, o, f, d.kf_bel + (size_t)d.f_kf[f] * KBEL, d.lm_bel + (size_t)d.f_lm[f] * LBEL);
-    queue_due(d, b, f, need);
+    int k = 0, m = 0;
+    if (f < d.rblk_start[b + 1]) {
+        k = d.f_kf[f];
+        m = d.f_lm[f];
+        const uint8_t fl = d.flags[f];
+        const int cf = d.cnt[f];
+        const double *bm = d.lm_bel + (size_t)m * LBEL;
+        const double dm[3] = {bm[0], bm[1], bm[2]};
+        need = check_due(d, o, f, k, fl, cf, dm);
+    }
+    queue_due(d, b, f, k, m, need);
 }
 
 // One problem's residual statistics from its blocks' partials (64 threads):
@@ -968,8 +984,12 @@ __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
 // clock: t_off -1) into log_row.
 constexpr int RELIN_BS = 128;
 
+// (two waves per SIMD: 256 registers, of which about 150 accumulation
+// registers the compiler uses as spill space)
 template <typename TS>
-__global__ __launch_bounds__(RELIN_BS) void k_relin(Dev<TS> d, IterOpts o, int nseg, int nred, double *log_row) {
+__global__ __launch_bounds__(RELIN_BS) __attribute__((amdgpu_waves_per_eu(2))) void k_relin(Dev<TS> d, IterOpts o,
+                                                                                            int nseg, int nred,
+                                                                                            double *log_row) {
     if ((int)blockIdx.x >= nseg) {
         if (threadIdx.x >= 64) return;  // one wave per problem
         reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
@@ -977,10 +997,14 @@ __global__ __launch_bounds__(RELIN_BS) void k_relin(Dev<TS> d, IterOpts o, int n
     }
     const int b = xcd_remap(blockIdx.x, nseg);
     const int n = d.relin_qcount[b];
+    // a residual block lies in one problem: its parameters and learned-
+    // damping switch are the same for the whole workgroup
+    const int prob = d.rblk_prob[b];
+    const int fd_on = (d.fdamp && !d.fallback[prob]) ? 1 : 0;
+    const double pend_k = d.pending_k[0];
     for (int i = threadIdx.x; i < n; i += RELIN_BS) {
-        const int f = d.relin_queue[(size_t)b * RBLK + i];
-        const int k = d.f_kf[f];
-        factor_body<TS, true>(d, o, f, k, d.kf_bel + (size_t)k * KBEL, nullptr);
+        const RelinEntry q = d.relin_queue[(size_t)b * RBLK + i];
+        factor_body<TS, true>(d, o, q.f, q.k, q.m, d.kf_bel + (size_t)q.k * KBEL, nullptr, fd_on, prob, pend_k);
     }
 }
 
@@ -1136,7 +1160,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
         if (f < e1) {
             const uint8_t fl = d.flags[f];
             if (MODE == 0 && !(fl & FLAG_DONE)) {
-                factor_body<TS, false>(d, o, f, k, bk, row, fd_on);
+                factor_body<TS, false>(d, o, f, k, d.f_lm[f], bk, row, fd_on);
             } else {
                 TS kr[KREC], km[KMSG];
                 load12(d.krec + (size_t)f * KREC, kr);
@@ -1593,7 +1617,7 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
     int c_valid = 0, c_lin_ref = 0, c_lin = 0, c_inv = 0, c_ref = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool need = false;
-    int fq = f0;
+    int fq = f0, kq = 0, mq = 0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int f = f0 + r * RTHREADS + (int)threadIdx.x;
@@ -1631,22 +1655,10 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
                 l[i] = bm[LANC + i] + dm[i];
             }
             if (CHECK) {
-                // due: requested by the host, or linearised at least
-                // `interval` iterations ago and farther than beta from the
-                // current means (strictly)
-                need = (fl & FLAG_PENDING) != 0;
-                const bool old_enough = (cf >= o.interval) & !need;
-                if (old_enough) {
-                    const double *bk = d.kf_bel + (size_t)k * KBEL;
-                    const TS *dr = d.drec + (size_t)f * DREC;
-                    double dist2 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) { double e = dm[i] - (double)dr[6 + i]; dist2 += e * e; }
-                    need = dist2 > o.beta2;
-                }
+                need = check_due(d, o, f, k, fl, cf, dm);
                 fq = f;
+                kq = k;
+                mq = m;
             }
             double p[3];
 #pragma unroll
@@ -1679,7 +1691,7 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
     }
     if constexpr (CHECK) {
         static_assert(RPL == 1, "the fused check takes one factor per thread");
-        queue_due(d, b, fq, need);
+        queue_due(d, b, fq, kq, mq, need);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
