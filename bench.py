@@ -101,6 +101,11 @@ def make_workload(name):
     elif name == "config2":
         probs = [synth.make_config2()]
         desc = "1000 keyframes, 40000 landmarks, power-law obs, 5% outliers"
+    elif name == "config2x4":
+        # one graph whose per-iteration traffic (~0.6 GB) exceeds the 256 MB
+        # last-level cache, unlike config2's
+        probs = [synth.make_random_walk("config2x4", 4, 4000, 160000, "powerlaw", 0.05, min_obs=2)]
+        desc = "4000 keyframes, 160000 landmarks, power-law obs, 5% outliers (one graph)"
     else:
         raise SystemExit(f"unknown workload {name}")
     return probs, desc
