@@ -110,17 +110,6 @@ __device__ __forceinline__ void load8(const double *__restrict__ p, double (&v)[
     for (int i = 0; i < 4; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
 }
 
-__device__ __forceinline__ void load10(const float *__restrict__ p, float (&v)[10]) {
-    const float2 *q = reinterpret_cast<const float2 *>(p);  // 40-byte records: 8-byte aligned
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { float2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
-}
-__device__ __forceinline__ void load10(const double *__restrict__ p, double (&v)[10]) {
-    const double2 *q = reinterpret_cast<const double2 *>(p);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
-}
-
 // Cholesky of a packed symmetric D x D matrix; returns false when a pivot is
 // not positive. L is stored packed by rows of the lower triangle in `L`.
 template <int D>
@@ -476,7 +465,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
                                             TS *__restrict__ stage, const int fd_on = -1,
                                             const int prob = -1, const double pend_k = 0.0) {
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
-    load10(d.arec + (size_t)f * AREC, ar);
+    load8(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
     load5(d.kmsg + (size_t)f * KMSG, km);
     load8(d.lrec + (size_t)f * LREC, lr);
@@ -494,7 +483,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     for (int i = 0; i < 3; ++i) dmm[i] = bm[i];
 
     // J d0 of both blocks (d0: linearisation point relative to the anchors)
-    double jdk0 = (double)ar[2], jdk1 = (double)ar[3], jdm0 = (double)ar[4], jdm1 = (double)ar[5];
+    double jdk0 = (double)ar[2], jdk1 = (double)ar[3], jdm0 = (double)lr[6], jdm1 = (double)lr[7];
     constexpr bool relin = RELIN;
 
     // current (old) Jacobian blocks
@@ -508,7 +497,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
     double r0[2] = {(double)ar[0], (double)ar[1]};
     double s = (double)kr[10];
-    double jak0 = (double)ar[6], jak1 = (double)ar[7], jam0 = (double)ar[8], jam1 = (double)ar[9];
+    double jak0 = (double)ar[4], jak1 = (double)ar[5], jam0 = (double)ar[6], jam1 = (double)ar[7];
     const double Ska = km[0], Skb = km[1], Skc = km[2], gk0 = km[3], gk1 = km[4];
     const double Sma = mm[0], Smb = mm[1], Smc = mm[2], gm0 = mm[3], gm1 = mm[4];
 
@@ -631,8 +620,9 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         kw[10] = (TS)s;
         TS *dw = d.drec + (size_t)f * DREC;
         aw[0] = (TS)r0[0]; aw[1] = (TS)r0[1];
-        aw[2] = (TS)jdk0; aw[3] = (TS)jdk1; aw[4] = (TS)jdm0; aw[5] = (TS)jdm1;
-        aw[6] = (TS)jak0; aw[7] = (TS)jak1; aw[8] = (TS)jam0; aw[9] = (TS)jam1;
+        aw[2] = (TS)jdk0; aw[3] = (TS)jdk1;
+        aw[4] = (TS)jak0; aw[5] = (TS)jak1; aw[6] = (TS)jam0; aw[7] = (TS)jam1;
+        lw[6] = (TS)jdm0; lw[7] = (TS)jdm1;
 #pragma unroll
         for (int i = 0; i < 6; ++i) dw[i] = (TS)dmk[i];
 #pragma unroll
@@ -1226,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     load5(d.kmsg + (size_t)f * KMSG, km);
     load8(d.lrec + (size_t)f * LREC, lr);
     load5(d.mmsg + (size_t)f * MMSG, mm);
-    load10(d.arec + (size_t)f * AREC, ar);
+    load8(d.arec + (size_t)f * AREC, ar);
     load12(d.drec + (size_t)f * DREC, dr);
     const ProbParams pp = d.prob[d.kf_prob[k]];
     const double *bk = d.kf_bel + (size_t)k * KBEL, *bm = d.lm_bel + (size_t)m * LBEL;
@@ -1315,7 +1305,7 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
     const TS *ar = d.arec + (size_t)f * AREC;
-    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[6 + c];
+    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[4 + c];
 }
 
 // --------------------------------------------------------------------------
@@ -1348,7 +1338,6 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     TS *mw = d.kmsg + (size_t)f * KMSG;
 #pragma unroll
     for (int i = 0; i < KMSG; ++i) mw[i] = (TS)0;
-    lw[6] = (TS)0; lw[7] = (TS)0;
     TS *nw = d.mmsg + (size_t)f * MMSG;
 #pragma unroll
     for (int i = 0; i < MMSG; ++i) nw[i] = (TS)0;
@@ -1360,7 +1349,8 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     for (int i = 0; i < 3; ++i) { jdm0 += L.J[0][6 + i] * dmm[i]; jdm1 += L.J[1][6 + i] * dmm[i]; dw[6 + i] = (TS)dmm[i]; }
 #pragma unroll
     for (int i = 9; i < DREC; ++i) dw[i] = (TS)0;
-    aw[2] = (TS)jdk0; aw[3] = (TS)jdk1; aw[4] = (TS)jdm0; aw[5] = (TS)jdm1;
+    aw[2] = (TS)jdk0; aw[3] = (TS)jdk1;
+    lw[6] = (TS)jdm0; lw[7] = (TS)jdm1;
     double jak0 = 0, jak1 = 0, jam0 = 0, jam1 = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -1374,7 +1364,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
         jam0 += L.J[0][6 + i] * a;
         jam1 += L.J[1][6 + i] * a;
     }
-    aw[6] = (TS)jak0; aw[7] = (TS)jak1; aw[8] = (TS)jam0; aw[9] = (TS)jam1;
+    aw[4] = (TS)jak0; aw[5] = (TS)jak1; aw[6] = (TS)jam0; aw[7] = (TS)jam1;
     d.cnt[f] = 0;
     d.flags[f] = L.valid ? 0 : FLAG_INVALID;
 }
@@ -1906,7 +1896,6 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 5: hipLaunchKernelGGL((k_gather<T, 5>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 8: hipLaunchKernelGGL((k_gather<T, 8>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
-            case 10: hipLaunchKernelGGL((k_gather<T, 10>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 16: hipLaunchKernelGGL((k_gather<T, 16>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             default: return;
