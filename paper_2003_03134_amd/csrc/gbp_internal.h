@@ -34,7 +34,9 @@ constexpr int LBI = 12;     // doubles of landmark belief information: Lambda pa
 //   [0..5]  d h / d omega (2x3, row-major)
 //   [6]     fx / pz   [7] fy / pz   [8] -fx px / pz^2   [9] -fy py / pz^2
 //           (d h / d t = [[6], 0, [8]; 0, [7], [9]])
-//   [10]    s = w / sigma^2   [11] pad
+//   [10]    s = w / sigma^2   [11] the factor's landmark index (its bit pattern
+//           in FP32 state, its value in FP64 state; fixed for the factor's
+//           lifetime, so the keyframe kernel needs no separate index stream)
 // message to the keyframe (its own dense array, so that the rewrite every
 // iteration covers whole cache lines):
 //   [0..2] S (a, b, c) = [[a b][b c]]   [3..4] g (anchor-relative information

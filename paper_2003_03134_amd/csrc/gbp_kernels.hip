@@ -110,6 +110,12 @@ __device__ __forceinline__ void load8(const double *__restrict__ p, double (&v)[
     for (int i = 0; i < 4; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
 }
 
+// a non-negative index kept in a record slot of the factor state's type
+__device__ __forceinline__ float index_to_slot(int i, float) { return __int_as_float(i); }
+__device__ __forceinline__ double index_to_slot(int i, double) { return (double)i; }
+__device__ __forceinline__ int slot_to_index(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int slot_to_index(double v) { return (int)v; }
+
 // Cholesky of a packed symmetric D x D matrix; returns false when a pivot is
 // not positive. L is stored packed by rows of the lower triangle in `L`.
 template <int D>
@@ -456,17 +462,20 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 // `stage` (may be null) receives the keyframe-side Jacobian and the new
 // stored message for the keyframe belief reduction. fd_on: whether the
 // learned per-factor damping applies (its problem has not fallen back); -1:
-// look it up for this factor. m: the factor's landmark; prob, pend_k: its
+// look it up for this factor. m_in: the factor's landmark (RELIN); prob, pend_k: its
 // problem and the Huber threshold of host-requested relinearisations (read
 // by RELIN only, which needs them).
 template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
-                                            const int m, const double *__restrict__ bk,
+                                            const int m_in, const double *__restrict__ bk,
                                             TS *__restrict__ stage, const int fd_on = -1,
                                             const int prob = -1, const double pend_k = 0.0) {
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
     load8(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
+    // the relinearising caller has the landmark from its queue entry; the
+    // keyframe kernel takes it from the keyframe-side record
+    const int m = RELIN ? m_in : slot_to_index(kr[11]);
     load5(d.kmsg + (size_t)f * KMSG, km);
     load8(d.lrec + (size_t)f * LREC, lr);
     load5(d.mmsg + (size_t)f * MMSG, mm);
@@ -1150,7 +1159,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
         if (f < e1) {
             const uint8_t fl = d.flags[f];
             if (MODE == 0 && !(fl & FLAG_DONE)) {
-                factor_body<TS, false>(d, o, f, k, d.f_lm[f], bk, row, fd_on);
+                factor_body<TS, false>(d, o, f, k, -1, bk, row, fd_on);
             } else {
                 TS kr[KREC], km[KMSG];
                 load12(d.krec + (size_t)f * KREC, kr);
@@ -1334,7 +1343,7 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
         for (int i = 0; i < 3; ++i) { kw[3 * r + i] = (TS)L.J[r][i]; lw[3 * r + i] = (TS)L.J[r][6 + i]; }
     kw[6] = (TS)L.J[0][3]; kw[7] = (TS)L.J[1][4]; kw[8] = (TS)L.J[0][5]; kw[9] = (TS)L.J[1][5];
     kw[10] = (TS)L.s;
-    kw[11] = (TS)0;
+    kw[11] = index_to_slot(m, TS(0));
     TS *mw = d.kmsg + (size_t)f * KMSG;
 #pragma unroll
     for (int i = 0; i < KMSG; ++i) mw[i] = (TS)0;
