@@ -8,6 +8,9 @@ four compute phases of the hot path). The default workload is 256 uneven
 bundle-adjustment problems (10-125 keyframes, 100-2000 landmarks, 4-12
 observations per landmark, about 2.15 M factors) run as one batched graph;
 inputs are generated on the host and resident in HBM before timing starts.
+Other workloads (--workload): config1 (125 keyframes, 1919 landmarks),
+config2 (1000 keyframes, 40000 landmarks), config2x4 (4000 keyframes,
+160000 landmarks, one graph past the last-level cache).
 
 Printed: one JSON line with the throughput, the dominant kernel's roofline
 figures (live HIP-event timing on the library's stream) and the FP64 oracle
@@ -28,11 +31,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes of the dominant kernel, k_factor_kf (one workgroup per
 # keyframe: every factor's two messages, then the keyframe's message sums),
 # with FP32 factor state (layout in paper_2003_03134_amd/csrc/gbp_internal.h):
-#   per factor: read the keyframe-side record 16 x 4 B, the landmark-side
-#     Jacobian + message 11 x 4 B, the factor-private record 10 x 4 B (r0,
-#     J times linearisation offset, J times anchor), the landmark index 4 B,
-#     counter and flags 2 x 1 B; write both new messages 2 x 5 x 4 B and the
-#     counter 1 B;
+#   per factor: read the keyframe-side Jacobian, s and message 16 x 4 B,
+#     the landmark-side Jacobian + message 11 x 4 B, the factor-private data
+#     10 x 4 B (r0, J times linearisation offset, J times anchor; two of them
+#     sit in the landmark-side record's spare slots), the landmark index 4 B
+#     (in the keyframe-side record's spare slot), counter and flags 2 x 1 B;
+#     write both new messages 2 x 5 x 4 B and the counter 1 B;
 #   per keyframe: read its belief (27 doubles), write its 27 message sums;
 #   per landmark: read its belief once (9 doubles; gathered by its factors).
 FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 10 * 4 + 4 + 2 + 2 * 5 * 4 + 1  # 195
