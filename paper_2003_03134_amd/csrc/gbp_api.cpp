@@ -349,9 +349,11 @@ void build_csr(gbp_problem *p) {
 // round-robin over the eight XCDs, so slot b runs on XCD b % 8. The
 // keyframes, in index order (problems concatenated), are cut into eight
 // contiguous runs of about equal work (factor chunks of the workgroup size),
-// one per XCD, which keeps keyframes that share landmarks in one L2; within
-// a run the largest keyframes go first, so the long workgroups start early.
-// Slots past the end of a shorter run hold -1 (the workgroup exits).
+// one per XCD, which keeps keyframes that share landmarks in one L2. Within
+// a run the problems with the largest keyframes go first, so the long
+// workgroups start early, and each problem's keyframes stay together
+// (largest first), so the landmarks they share are fetched while still in
+// L2. Slots past the end of a shorter run hold -1 (the workgroup exits).
 std::vector<int> kf_order(const gbp_problem *p) {
     constexpr int NX = 8;
     const int nk = p->nk;
@@ -370,9 +372,19 @@ std::vector<int> kf_order(const gbp_problem *p) {
         run[x].push_back(k);
         acc += w[k];
     }
+    // each keyframe's problem and each problem's largest keyframe
+    std::vector<int> kp(nk, 0);
+    for (int i = 0; i + 1 < (int)p->kf_off.size(); ++i)
+        for (int k = p->kf_off[i]; k < p->kf_off[i + 1]; ++k) kp[k] = i;
+    std::vector<double> pw(p->kf_off.size(), 0.0);
+    for (int k = 0; k < nk; ++k) pw[kp[k]] = std::max(pw[kp[k]], w[k]);
     size_t len = 0;
     for (auto &r : run) {
-        std::stable_sort(r.begin(), r.end(), [&](int a, int b) { return w[a] > w[b]; });
+        std::stable_sort(r.begin(), r.end(), [&](int a, int b) {
+            if (pw[kp[a]] != pw[kp[b]]) return pw[kp[a]] > pw[kp[b]];
+            if (kp[a] != kp[b]) return kp[a] < kp[b];
+            return w[a] > w[b];
+        });
         len = std::max(len, r.size());
     }
     std::vector<int> order(len * NX, -1);
