@@ -298,6 +298,13 @@ __device__ __forceinline__ void linearise(const double x[6], const double l[3], 
 // 2x2 measurement-space marginalisation
 // --------------------------------------------------------------------------
 
+// Structural zeros of a factor's Jacobian block (D = 6: the keyframe block,
+// whose d h / d t is [[fx/pz, 0, .], [0, fy/pz, .]]; D = 3: none).
+template <int D>
+__device__ __forceinline__ constexpr bool jac_zero(int r, int c) {
+    return D == 6 && ((r == 0 && c == 4) || (r == 1 && c == 3));
+}
+
 // Cavity of one variable (its belief divided by this factor's previous
 // message S_o, g_o expressed with Jacobian Jo) projected through the
 // factor's current Jacobian Jn about the linearisation offset d0n:
@@ -397,28 +404,29 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
                                               const double (&dmu)[D], double jdd0, double jdd1, double Sa,
                                               double Sb, double Sc, double g0, double g1, double &Pa,
                                               double &Pb, double &Pc, double &m0, double &m1) {
+    // Po = J Sigma J^T, one row of Sigma J^T at a time (products with the
+    // structural zeros of the keyframe Jacobian are skipped)
     double poa = 0, pob = 0, poc = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int j = i; j < D; ++j) {
+        for (int j = 0; j < D; ++j) {
             const double w = cov[pidx<D>(i, j)];
-            if (i == j) {
-                poa += J[0][i] * J[0][i] * w;
-                pob += J[0][i] * J[1][i] * w;
-                poc += J[1][i] * J[1][i] * w;
-            } else {
-                poa += 2.0 * J[0][i] * J[0][j] * w;
-                pob += (J[0][i] * J[1][j] + J[0][j] * J[1][i]) * w;
-                poc += 2.0 * J[1][i] * J[1][j] * w;
-            }
+            if (!jac_zero<D>(0, j)) a0 += w * J[0][j];
+            if (!jac_zero<D>(1, j)) a1 += w * J[1][j];
+        }
+        if (!jac_zero<D>(0, i)) poa += J[0][i] * a0;
+        if (!jac_zero<D>(1, i)) {
+            pob += J[1][i] * a0;
+            poc += J[1][i] * a1;
         }
     }
     double jd0 = 0, jd1 = 0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        jd0 += J[0][i] * dmu[i];
-        jd1 += J[1][i] * dmu[i];
+        if (!jac_zero<D>(0, i)) jd0 += J[0][i] * dmu[i];
+        if (!jac_zero<D>(1, i)) jd1 += J[1][i] * dmu[i];
     }
     // J (dmu - d0), with J d0 stored at linearisation
     const double jn0 = jd0 - jdd0, jn1 = jd1 - jdd1;
@@ -1101,14 +1109,21 @@ __device__ __forceinline__ void kf_contrib(const TS *row, TS *c) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) { J0[i] = (double)row[i]; J1[i] = (double)row[6 + i]; }
     const double Sa = row[12], Sb = row[13], Sc = row[14], g0 = row[15], g1 = row[16];
+    // (the keyframe Jacobian's structural zeros drop out exactly)
     double SJ0[6], SJ1[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) { SJ0[j] = Sa * J0[j] + Sb * J1[j]; SJ1[j] = Sb * J0[j] + Sc * J1[j]; }
+    for (int j = 0; j < 6; ++j) {
+        SJ0[j] = jac_zero<6>(0, j) ? Sb * J1[j] : jac_zero<6>(1, j) ? Sa * J0[j] : Sa * J0[j] + Sb * J1[j];
+        SJ1[j] = jac_zero<6>(0, j) ? Sc * J1[j] : jac_zero<6>(1, j) ? Sb * J0[j] : Sb * J0[j] + Sc * J1[j];
+    }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
 #pragma unroll
-        for (int j = i; j < 6; ++j) c[pidx<6>(i, j)] = (TS)(J0[i] * SJ0[j] + J1[i] * SJ1[j]);
-        c[21 + i] = (TS)(J0[i] * g0 + J1[i] * g1);
+        for (int j = i; j < 6; ++j)
+            c[pidx<6>(i, j)] = (TS)(jac_zero<6>(0, i)   ? J1[i] * SJ1[j]
+                                    : jac_zero<6>(1, i) ? J0[i] * SJ0[j]
+                                                        : J0[i] * SJ0[j] + J1[i] * SJ1[j]);
+        c[21 + i] = (TS)(jac_zero<6>(0, i) ? J1[i] * g1 : jac_zero<6>(1, i) ? J0[i] * g0 : J0[i] * g0 + J1[i] * g1);
     }
 }
 
