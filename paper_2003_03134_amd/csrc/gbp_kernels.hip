@@ -1188,8 +1188,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
         kf_contrib<TS>(row, red + tid * RS);
         __syncthreads();
         if (grp < G) {
+            // rows grp, grp + G, ... in order; a fixed trip count lets the
+            // LDS reads go out together instead of one round trip per row
+            static_assert(BS % G == 0, "whole rows per group");
             double s = 0.0;
-            for (int q = grp; q < BS; q += G) s += (double)red[q * RS + col];
+#pragma unroll
+            for (int r = 0; r < BS / G; ++r) s += (double)red[(grp + r * G) * RS + col];
             part[grp][col] = s;
         }
         __syncthreads();
