@@ -164,7 +164,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.f_kf, F * 4);
     L.add((void **)&d.f_lm, F * 4);
     L.add((void **)&d.kf_row, (K + 1) * 4);
-    L.add((void **)&d.kf_order, 8 * K * 4 + 4);  // at most 8 slots per keyframe (runs of unequal length)
+    L.add((void **)&d.kf_slot, (8 * K + 1) * sizeof(KfSlot));  // at most 8 slots per keyframe (runs of unequal length)
     L.add((void **)&d.lm_edge, F * 4);
     L.add((void **)&d.lm_row, (M + 1) * 4);
     L.add((void **)&d.f_row_prob, (P + 1) * 4);
@@ -393,6 +393,21 @@ std::vector<int> kf_order(const gbp_problem *p) {
     return order;
 }
 
+// the keyframe kernel's slots: keyframe, factor range and problem per
+// workgroup, in the order above
+std::vector<KfSlot> kf_slots(const gbp_problem *p) {
+    const std::vector<int> order = kf_order(p);
+    std::vector<int> kp(p->nk, 0);
+    for (int i = 0; i + 1 < (int)p->kf_off.size(); ++i)
+        for (int k = p->kf_off[i]; k < p->kf_off[i + 1]; ++k) kp[k] = i;
+    std::vector<KfSlot> slots(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int k = order[i];
+        slots[i] = k < 0 ? KfSlot{-1, 0, 0, 0} : KfSlot{k, p->h_kf_row[k], p->h_kf_row[k + 1], kp[k]};
+    }
+    return slots;
+}
+
 void destroy_graphs(gbp_problem *p) {
     for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
     p->graphs.clear();
@@ -465,9 +480,9 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     UP(d.f_kf, p->h_fkf.data(), (size_t)nf * 4);
     UP(d.f_lm, p->h_flm.data(), (size_t)nf * 4);
     UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk + 1) * 4);
-    const std::vector<int> order = kf_order(p);
-    d.n_kf_slots = (int)order.size();
-    if (!order.empty()) UP(d.kf_order, order.data(), order.size() * 4);
+    const std::vector<KfSlot> slots = kf_slots(p);
+    d.n_kf_slots = (int)slots.size();
+    if (!slots.empty()) UP(d.kf_slot, slots.data(), slots.size() * sizeof(KfSlot));
     UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf * 4);
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl + 1) * 4);
     std::vector<int> frp(p->f_off.begin(), p->f_off.end());
@@ -947,9 +962,9 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     UP(d.f_lm, p->h_flm.data(), (size_t)nf1 * 4);
     UP(d.z, p->h_z.data(), (size_t)nf1 * 2 * 8);
     UP(d.kf_row, p->h_kf_row.data(), (size_t)(nk1 + 1) * 4);
-    const std::vector<int> korder = kf_order(p);
-    d.n_kf_slots = (int)korder.size();
-    UP(d.kf_order, korder.data(), korder.size() * 4);
+    const std::vector<KfSlot> kslots = kf_slots(p);
+    d.n_kf_slots = (int)kslots.size();
+    UP(d.kf_slot, kslots.data(), kslots.size() * sizeof(KfSlot));
     UP(d.lm_row, p->h_lm_row.data(), (size_t)(nl1 + 1) * 4);
     UP(d.lm_edge, p->h_lm_edge.data(), (size_t)nf1 * 4);
     std::vector<int> frp = {0, nf1};

@@ -55,6 +55,12 @@ struct ProbParams {
 };
 
 // Device view of one problem set (a single problem or a batch).
+// one workgroup of the keyframe kernel: its keyframe (-1: none), the
+// keyframe's factor range and its problem, read in one load
+struct alignas(16) KfSlot {
+    int k, e0, e1, prob;
+};
+
 // one queued relinearisation: the factor and its two variables (so that the
 // relinearising kernel gathers the beliefs in the same round of loads as the
 // factor's records)
@@ -79,7 +85,7 @@ struct Dev {
     // graph
     const int *f_kf, *f_lm;
     const int *kf_row;                    // factors of keyframe k: [kf_row[k], kf_row[k+1])
-    const int *kf_order;                  // keyframe of each keyframe-kernel workgroup (-1: none)
+    const KfSlot *kf_slot;                // work of each keyframe-kernel workgroup
     int n_kf_slots;                       // workgroups of the keyframe kernel
     int lm_lanes;                         // lanes per landmark in the landmark belief kernel (2, 4, 8)
     const int *lm_row, *lm_edge;          // factors of each landmark (CSR, increasing)

@@ -1145,14 +1145,16 @@ template <typename TS, int BS, int MODE>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per_eu<TS, BS>()))) void k_factor_kf(
     Dev<TS> d, IterOpts o) {
     constexpr int G = BS / 32;     // row groups in the column sums
-    constexpr int RS = 29;         // padded row stride (doubles) against bank conflicts
+    constexpr int RS = 29;         // padded row stride (elements) against bank conflicts
     __shared__ TS red[BS * RS];
     __shared__ double part[G][28];
-    // slot -> keyframe (per-XCD runs, largest first; -1: no keyframe)
-    const int k = d.kf_order[blockIdx.x];
+    // slot -> keyframe, its factor range and problem (per-XCD runs; k = -1:
+    // no keyframe)
+    const KfSlot sl = d.kf_slot[blockIdx.x];
+    const int k = sl.k;
     if (k < 0) return;
     const int tid = threadIdx.x;
-    const int e0 = d.kf_row[k], e1 = d.kf_row[k + 1];
+    const int e0 = sl.e0, e1 = sl.e1;
     // the keyframe's belief is the same for every lane: broadcast it into
     // scalar registers (loaded per lane, the compiler would keep 54 vector
     // registers for it, since it cannot rule out that the record stores
@@ -1163,7 +1165,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
     const double *bk = kb;
     // learned damping: on unless absent or the keyframe's problem fell back
     // (the same for the whole workgroup)
-    const int fd_on = (d.fdamp && !d.fallback[d.kf_prob[k]]) ? 1 : 0;
+    const int fd_on = (d.fdamp && !d.fallback[sl.prob]) ? 1 : 0;
     const int col = tid % 27, grp = tid / 27;
     double acc = 0.0;
     for (int base = e0; base < e1; base += BS) {
