@@ -1821,7 +1821,7 @@ void launch_prior_base(const Dev<TS> &d, int k0, int m0, hipStream_t s) {
     if (d.nl > m0) hipLaunchKernelGGL(k_prior_lm<TS>, dim3(blocks(d.nl - m0, 256)), dim3(256), 0, s, d, m0);
 }
 
-// With events, the keyframe kernel is launched through the driver's
+// With events, the keyframe kernel is launched through the HIP runtime's
 // extension that records ev0 / ev1 at the kernel's own start and end.
 template <typename TS, int MODE>
 static void launch_kf(const Dev<TS> &d, const IterOpts &o, int block, int readout, hipStream_t s,
