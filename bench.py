@@ -340,8 +340,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(independent problems shard trivially by problem; see the design notes). "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(independent problems would shard by problem, with no exchange). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
