@@ -14,7 +14,8 @@ config2 (1000 keyframes, 40000 landmarks), config2x4 (4000 keyframes,
 
 Printed: one JSON line with the throughput, the dominant kernel's roofline
 figures (live HIP-event timing on the library's stream) and the FP64 oracle
-timed on a bounded sample of the same workload on the host cores.
+timed on a bounded sample of the same workload on the host cores, with the
+GPU path's agreement with it on the workload's first problem.
 """
 import argparse
 import hashlib
@@ -142,7 +143,36 @@ def cpu_baseline(probs, budget_s, iters):
                 sample=f"first {used} problems of the workload, {iters} iterations each "
                        f"({updates} factor updates, {t_total:.1f} s)",
                 single_thread=dict(value=round(probs[0].n_factors * n1 / t1, 1),
-                                   sample=f"first problem, {n1} iterations, one thread ({t1:.2f} s)"))
+                                   sample=f"first problem, {n1} iterations, one thread ({t1:.2f} s)"),
+                parity=parity_first_problem(probs[0], oracle))
+
+
+def parity_first_problem(prob, oracle):
+    """The GPU path (FP32 factor state) against the oracle on the workload's
+    first problem under the same forced schedule, 3 x (10 iterations, then
+    every factor relinearised): the largest per-variable mean error relative
+    to max(|mean|, 1), and the difference of the average reprojection error."""
+    import numpy as np
+    import paper_2003_03134_amd as gbp
+    s = gbp.GBPSolver(prob, precision=gbp.GBP_FP32)
+    o = oracle.Oracle(prob, anneal=True)
+    try:
+        for _ in range(3):
+            s.iterate(10, 0.4, 2.0)
+            o.iterate(10, 0.4, 2.0)
+            s.relinearise(-1)
+            o.relinearise(-1)
+        g, r = s.beliefs(), o.beliefs()
+        err = 0.0
+        for key in ("kf_mu", "lm_mu"):
+            if len(r[key]):
+                d = np.abs(g[key] - r[key]).max(axis=1)
+                err = max(err, float((d / np.maximum(np.abs(r[key]).max(axis=1), 1.0)).max()))
+        are = abs(s.reproj()["are_all"] - o.reproj()["are_all"])
+    finally:
+        s.close()
+    return dict(schedule="first problem, 3 x (10 iterations + forced relinearisation)",
+                max_rel_mean_err=err, are_diff_px=are, tolerance="1e-4 relative, 1e-3 px")
 
 
 def time_to_target(gbp):
