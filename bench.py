@@ -139,12 +139,22 @@ def cpu_baseline(probs, budget_s, iters):
     t1 = time.perf_counter() - t0
     oracle.set_threads(cores)
     return dict(value=updates / t_total, unit="factor-updates/s", cores=cores,
-                kind="oracle",
+                kind="oracle", host=host_cpu(),
                 sample=f"first {used} problems of the workload, {iters} iterations each "
                        f"({updates} factor updates, {t_total:.1f} s)",
                 single_thread=dict(value=round(probs[0].n_factors * n1 / t1, 1),
                                    sample=f"first problem, {n1} iterations, one thread ({t1:.2f} s)"),
                 parity=parity_first_problem(probs[0], oracle))
+
+
+def host_cpu():
+    """The host's CPU model and logical CPU count (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            models = [l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")]
+        return f"{models[0]} ({len(models)} logical CPUs)" if models else None
+    except OSError:
+        return None
 
 
 def parity_first_problem(prob, oracle):
