@@ -117,8 +117,10 @@ void gbp_default_options(gbp_options *opt);
 gbp_status gbp_workspace_bytes(int32_t n_problems, const gbp_graph *graphs,
                                const gbp_options *opt, size_t *bytes);
 
-/* Build one problem (Section 4): validates indices, orders factors by
- * landmark and keyframes' factors into a CSR, copies inputs to the device,
+/* Build one problem (Section 4): validates indices, orders landmarks by
+ * their first observing keyframe and factors keyframe-major (within a
+ * keyframe by landmark), builds a landmark CSR over the factors, copies
+ * inputs to the device,
  * linearises every factor at the initial estimate, builds the automatic
  * priors and sets each belief to its prior (iteration clock t = 0).
  * Returns GBP_EINVAL for out-of-range indices or sizes. */
