@@ -354,6 +354,27 @@ gbp_status gbp_mlp_train_step(const float *x, const float *y, const float *mask,
                               void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): gbp_mlp_train_step without a workspace. Same arguments,
+ * results and errors as gbp_mlp_train_step (bitwise the same results); the
+ * partial gradients live in a fixed device array inside the library of
+ * GBP_MLP_STATIC_MAX_BATCH samples' worth (about 5.5 MB, held on each GPU
+ * the library runs on until the process ends). n_batch above
+ * GBP_MLP_STATIC_MAX_BATCH: GBP_EINVAL. `stream` (NULL = default stream)
+ * must belong to the current device. Allocates nothing; the first call on a
+ * device looks up the array's address there. Every call on one GPU shares
+ * that array: calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define GBP_MLP_STATIC_MAX_BATCH 8192
+gbp_status gbp_mlp_train_step_static(const float *x, const float *y,
+                                     const float *mask, int32_t n_rows,
+                                     const int32_t *batch_idx, int32_t n_batch,
+                                     float *theta, float *adam_m, float *adam_v,
+                                     uint16_t *weights_bf16, float lr,
+                                     int32_t step, float *grad_out,
+                                     float *loss_out, void *stream);
+
 /* Per-phase timing (the compute phases of one iteration, Section 7 and
  * Fig. 3): runs n iterations with each phase launched separately and
  * bracketed by HIP events on the problem's stream, then writes the average

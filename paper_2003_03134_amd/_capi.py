@@ -61,10 +61,11 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference", "gbp_add_pair_factors",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
            "gbp_reset", "gbp_apply_depth_model", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
-           "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step",
+           "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step", "gbp_mlp_train_step_static",
            "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
 
 MLP_PARAMS = 5378
+GBP_MLP_STATIC_MAX_BATCH = 8192   # batch limit of gbp_mlp_train_step_static
 LOG_COLS = 5           # GBP_LOG_COLS: columns of a gbp_iterate_logged row
 MLP_FEATURES = 16
 
@@ -116,6 +117,8 @@ def load():
     lib.gbp_mlp_train_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
     lib.gbp_mlp_train_step.argtypes = [P, P, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_float, C.c_int32,
                                        P, P, P, C.c_size_t, P]
+    lib.gbp_mlp_train_step_static.argtypes = [P, P, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_float,
+                                              C.c_int32, P, P, P]
     lib.gbp_phase_times.argtypes = [P, C.c_int32, C.c_double, C.c_double, _dp]
     lib.gbp_counters.argtypes = [P, C.POINTER(C.c_int64)]
     lib.gbp_autotune.argtypes = [P, C.c_int32, C.c_char_p, _ip]

@@ -1586,6 +1586,51 @@ gbp_status gbp_mlp_train_step(const float *x, const float *y, const float *mask,
     return GBP_OK;
 }
 
+gbp_status gbp_mlp_train_step_static(const float *x, const float *y, const float *mask, int32_t n_rows,
+                                     const int32_t *batch_idx, int32_t n_batch, float *theta, float *adam_m,
+                                     float *adam_v, uint16_t *weights_bf16, float lr, int32_t step, float *grad_out,
+                                     float *loss_out, void *stream) {
+    if (n_batch < 1 || n_rows < 0 || !x || !y || !mask || !batch_idx || !theta || !grad_out || !loss_out ||
+        step < 0 || (step > 0 && (!adam_m || !adam_v || !weights_bf16 || !(lr > 0.f)))) {
+        g_err = "gbp_mlp_train_step_static: bad arguments";
+        return GBP_EINVAL;
+    }
+    if (n_batch > MLP_STATIC_MAX_BATCH) {
+        g_err = "gbp_mlp_train_step_static: batch of " + std::to_string(n_batch) + " exceeds the fixed scratch (at most " +
+                std::to_string(MLP_STATIC_MAX_BATCH) + " samples)";
+        return GBP_EINVAL;
+    }
+    if (stream) {
+        int cur = -1, sdev = -1;
+        if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice((hipStream_t)stream, &sdev) != hipSuccess ||
+            cur != sdev) {
+            g_err = "gbp_mlp_train_step_static: the stream must belong to the current device";
+            return GBP_EINVAL;
+        }
+    }
+    float *scr = nullptr;
+    size_t floats = 0;
+    hipError_t e = mlp_static_scratch(&scr, &floats);
+    if (e != hipSuccess) {
+        g_err = std::string("gbp_mlp_train_step_static: scratch address: ") + hipGetErrorString(e);
+        return GBP_EDEVICE;
+    }
+    const int nb = mlp_partial_blocks(n_batch);
+    if ((size_t)nb * (MLP_NPARAMS + 1) > floats) {
+        g_err = "gbp_mlp_train_step_static: scratch too small";
+        return GBP_EINVAL;
+    }
+    // every partial the reduction reads is written by this call's first
+    // kernel: nothing left by an earlier call needs clearing
+    float *part_grad = scr;
+    float *part_loss = part_grad + (size_t)nb * MLP_NPARAMS;
+    launch_mlp_train_step(x, y, mask, n_rows, batch_idx, n_batch, theta, adam_m, adam_v, grad_out, part_grad,
+                          part_loss, loss_out, weights_bf16, lr, step, step > 0, (hipStream_t)stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) { g_err = std::string("gbp_mlp_train_step_static: ") + hipGetErrorString(e); return GBP_EDEVICE; }
+    return GBP_OK;
+}
+
 gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping, double huber_k, double *ms_out) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;

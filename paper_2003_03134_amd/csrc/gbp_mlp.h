@@ -19,4 +19,11 @@ void launch_mlp_train_step(const float *X, const float *Y, const float *M, int n
 void launch_to_bf16(const float *theta, uint16_t *out, hipStream_t s);
 int mlp_partial_blocks(int n_batch);
 
+// Allocation-free training step: largest batch its fixed scratch holds, and
+// the device-side address of that scratch on the current device (looked up
+// on the first call per device; at most MLP_MAX_DEVICES devices).
+constexpr int MLP_STATIC_MAX_BATCH = 8192;
+constexpr int MLP_MAX_DEVICES = 64;
+hipError_t mlp_static_scratch(float **ptr, size_t *floats);
+
 }  // namespace gbp

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "gbp_mlp.h"
 
@@ -371,5 +372,34 @@ void launch_to_bf16(const float *theta, uint16_t *out, hipStream_t s) {
 }
 
 int mlp_partial_blocks(int n_batch) { return (n_batch + SB - 1) / SB; }
+
+// Fixed device scratch of the allocation-free training step: the partial
+// gradients and partial losses of up to MLP_STATIC_MAX_BATCH samples. Each
+// GPU the library runs on holds one copy for the life of the process. In host
+// code the array's name is not a device address: its address on a device is
+// looked up once per device (with that device current) and kept.
+constexpr size_t MLP_SCRATCH_FLOATS =
+    (size_t)((MLP_STATIC_MAX_BATCH + SB - 1) / SB) * (MLP_NPARAMS + 1);
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[MLP_MAX_DEVICES];
+
+hipError_t mlp_static_scratch(float **ptr, size_t *floats) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MLP_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *floats = MLP_SCRATCH_FLOATS;
+    return hipSuccess;
+}
 
 }  // namespace gbp

@@ -28,6 +28,8 @@ def test_header_declarations_are_exported(capi):
 
 def test_header_constants_match_the_binding(capi):
     text = open(os.path.join(ROOT, "include", "gbp.h")).read()
+    assert int(re.search(r"#define GBP_MLP_STATIC_MAX_BATCH (\d+)", text).group(1)) == \
+        capi.GBP_MLP_STATIC_MAX_BATCH
     assert int(re.search(r"#define GBP_LOG_COLS (\d+)", text).group(1)) == capi.LOG_COLS
     fields = re.search(r"typedef struct \{([^}]*)\} gbp_reproj;", text).group(1)
     names = re.findall(r"\b(?:double|int64_t)\s+(\w+);", fields)
@@ -110,3 +112,18 @@ def test_packaged_damping_weights_load():
     assert np.array_equal(bf16, expect)
     assert np.all(np.isfinite(theta))
     assert meta["samples"] > 0 and meta["val_loss"][-1] < meta["val_loss"][0]
+
+
+def test_static_training_step_rejects_oversized_batches(capi):
+    """The allocation-free training step refuses a batch beyond its fixed
+    scratch and bad arguments before touching a device (the pointers below
+    are never dereferenced)."""
+    lib = capi.load()
+    fake = C.c_void_p(0x1000)
+    n = capi.GBP_MLP_STATIC_MAX_BATCH + 1
+    st = lib.gbp_mlp_train_step_static(fake, fake, fake, 10, fake, n, fake, fake, fake, fake,
+                                       C.c_float(1e-3), 1, fake, fake, None)
+    assert st == capi.GBP_EINVAL and b"exceeds" in lib.gbp_last_error(None)
+    st = lib.gbp_mlp_train_step_static(fake, fake, fake, 10, fake, 0, fake, fake, fake, fake,
+                                       C.c_float(1e-3), 1, fake, fake, None)
+    assert st == capi.GBP_EINVAL
