@@ -29,28 +29,74 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# Algorithmic bytes of the dominant kernel, k_factor_kf (one workgroup per
-# keyframe: every factor's two messages, then the keyframe's message sums),
-# with FP32 factor state (layout in paper_2003_03134_amd/csrc/gbp_internal.h):
-#   per factor: read the keyframe-side Jacobian, s and message 16 x 4 B,
-#     the landmark-side Jacobian + message 11 x 4 B, the factor-private data
-#     10 x 4 B (r0, J times linearisation offset, J times anchor; two of them
-#     sit in the landmark-side record's spare slots), the landmark index 4 B
-#     (in the keyframe-side record's spare slot), counter and flags 2 x 1 B;
-#     write both new messages 2 x 5 x 4 B and the counter 1 B;
-#   per keyframe: read its belief (27 doubles), write its 27 message sums;
-#   per landmark: read its belief once (9 doubles; gathered by its factors).
-FACTOR_BYTES_PER_FACTOR = 16 * 4 + 11 * 4 + 10 * 4 + 4 + 2 + 2 * 5 * 4 + 1  # 195
-KF_BELIEF_BYTES = 27 * 8 + 27 * 8
+# Algorithmic bytes of the four launches of one step, FP32 factor state
+# (record layout in paper_2003_03134_amd/csrc/gbp_internal.h): every datum a
+# kernel must read or write, once per launch, without cache-line effects.
+# n_due: factors relinearised in the step.
+#
+# k_factor_kf (one workgroup per keyframe: every factor not relinearised in
+# the step sends its two messages, then the keyframe's message sums):
+#   per such factor: read the keyframe-side Jacobian, s and landmark index
+#     (12 x 4 B), its message (5 x 4 B), the landmark-side Jacobian and J d0
+#     (8 x 4 B), its message (5 x 4 B), the factor-private data (8 x 4 B),
+#     counter and flags (2 x 1 B); write both new messages (2 x 5 x 4 B) and
+#     the counter (1 B): 195 B;
+#   per relinearised factor: its flags (read and cleared, 2 x 1 B), the
+#     keyframe-side record and message it sums (12 x 4 + 5 x 4 B): 70 B;
+#   per keyframe: its slot (16 B), its belief (27 x 8 B), its 27 sums
+#     (27 x 8 B); per landmark: its belief once (9 x 8 B).
+FACTOR_BYTES_PER_FACTOR = 12 * 4 + 5 * 4 + 8 * 4 + 5 * 4 + 8 * 4 + 2 + 2 * 5 * 4 + 1  # 195
+KF_DONE_BYTES = 2 + 12 * 4 + 5 * 4                                                   # 70
+KF_BELIEF_BYTES = 16 + 27 * 8 + 27 * 8
 LM_BELIEF_BYTES = 9 * 8
+# k_relin (queued factors relinearise and send): per factor the queue entry
+# (16 B), the records and messages it replaces (12 + 5 + 8 + 5 + 8 floats and
+# 2 bytes: 154 B), its measurement (2 x 8 B); writes the new records (11 + 8
+# + 8 floats), its linearisation point (9 floats), both messages (10 floats),
+# counter and flags: 186 B; gathered once per variable touched: a keyframe's
+# belief and anchor (27 + 6 doubles), a landmark's belief and anchor (12
+# doubles).
+RELIN_BYTES_PER_FACTOR = 16 + 154 + 16 + 186                                         # 372
+RELIN_KF_BYTES, RELIN_LM_BYTES = 33 * 8, 12 * 8
+# k_belief_lm (keyframe solves in its first workgroups, then landmarks):
+#   per keyframe: sums (27 x 8 B), prior base, anchor information, birth clock
+#     and anchor (6 x 8 + 8 + 4 + 6 x 8 B); writes belief (27 x 8 B) and
+#     absolute pose (12 x 8 B): 636 B;
+#   per edge: its index (4 B), the landmark-side record (8 x 4 B) and message
+#     (5 x 4 B): 56 B; per landmark: its row (4 B), birth clock (4 B), prior
+#     base (3 x 8 B), belief written (9 x 8 B): 104 B.
+BELIEF_KF_BYTES = 27 * 8 + 6 * 8 + 8 + 4 + 6 * 8 + 27 * 8 + 12 * 8                  # 636
+BELIEF_EDGE_BYTES, BELIEF_LM_BYTES = 4 + 8 * 4 + 5 * 4, 4 + 4 + 3 * 8 + 9 * 8
+# k_reproj_block with the fused check (per factor: keyframe and landmark
+# index 2 x 4 B, measurement 2 x 8 B, flags and counter 2 x 1 B, with a
+# reference: mask 1 B and reference pixels 2 x 8 B; for factors old enough
+# to be checked, the linearisation point 9 x 4 B; per due factor its queue
+# entry 16 B; gathered once per variable: a keyframe's absolute pose and mean
+# offset (12 + 6 doubles), a landmark's mean offset and anchor (6 doubles);
+# per residual block: bounds, problem, parameters and its 8 partial sums.
+REPROJ_BYTES_PER_FACTOR = 2 * 4 + 2 * 8 + 2
+REPROJ_REF_BYTES = 1 + 2 * 8
+REPROJ_CHECK_BYTES = 9 * 4
+REPROJ_KF_BYTES, REPROJ_LM_BYTES, REPROJ_BLOCK_BYTES = 18 * 8, 6 * 8, 8 + 4 + 64 + 64
+
+
+def step_bytes(nf, nk, nl, n_due, n_old, n_blocks, with_ref):
+    """Algorithmic bytes of each launch of one logged step (dict)."""
+    touched_lm = nl * (1.0 - (1.0 - n_due / nf) ** (nf / max(nl, 1))) if nf else 0.0
+    return {
+        "k_factor_kf": (nf - n_due) * FACTOR_BYTES_PER_FACTOR + n_due * KF_DONE_BYTES
+        + nk * KF_BELIEF_BYTES + nl * LM_BELIEF_BYTES,
+        "k_relin": n_due * RELIN_BYTES_PER_FACTOR + (nk * RELIN_KF_BYTES if n_due else 0)
+        + touched_lm * RELIN_LM_BYTES,
+        "k_belief_lm": nk * BELIEF_KF_BYTES + nf * BELIEF_EDGE_BYTES + nl * BELIEF_LM_BYTES,
+        "k_reproj_block": nf * (REPROJ_BYTES_PER_FACTOR + (REPROJ_REF_BYTES if with_ref else 0))
+        + n_old * REPROJ_CHECK_BYTES + n_due * 16 + nk * REPROJ_KF_BYTES + nl * REPROJ_LM_BYTES
+        + n_blocks * REPROJ_BLOCK_BYTES,
+    }
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def factor_launch_bytes(nf, nk, nl):
-    return nf * FACTOR_BYTES_PER_FACTOR + nk * KF_BELIEF_BYTES + nl * LM_BELIEF_BYTES
 
 
 def kernel_sha():
@@ -359,10 +405,12 @@ def studies_leg(trials):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config3")
     ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--steady-from", type=int, default=50,
+                    help="first timed iteration is after this one (steady state)")
     ap.add_argument("--phase-iters", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-iters", type=int, default=150)
@@ -413,13 +461,13 @@ def main():
     K, W = args.steps, args.warmup
     c = max(1, min(args.chunk, K))
     n_chunks, rem = K // c, K % c
-    log(f"warmup: >= {W} steps in chunks of {c}")
-    done = 0
-    while done < max(W, 1):
-        solver.iterate_logged(c, 0.4, 2.0, log_every=1)
-        done += c
-    if rem:
-        solver.iterate_logged(rem, 0.4, 2.0, log_every=1)
+    # the first iterations relinearise few factors (every factor waits 10
+    # updates after creation): the timed window starts at steady state,
+    # at least --steady-from iterations in, whatever --warmup asks for
+    start = max(W, args.steady_from, 9)
+    log(f"warmup: {W} steps requested, timing from iteration {start} (steady state)")
+    while solver.t < start:
+        solver.iterate_logged(min(c, start - solver.t), 0.4, 2.0, log_every=1)
     torch.cuda.synchronize()
     solver.synchronize()
 
@@ -443,21 +491,52 @@ def main():
     log(f"{ms_per_step:.4f} ms/step wall ({ev_ms / K:.4f} ms/step by events), "
         f"{value / 1e9:.3f} G factor-updates/s")
 
+    are = last[-1] if last is not None else None
+    t_end = solver.t
     ph = solver.phase_times(args.phase_iters, 0.4, 2.0)
-    relin_frac = solver.last_relinearised / nf
-    log(f"relinearised per iteration: {100 * relin_frac:.2f}% of factors")
-    log("phase ms/launch: " + ", ".join(f"{k} {v:.4f}" for k, v in ph.items()))
-    fbytes = factor_launch_bytes(nf, nk, nl)
+    log("phase ms/launch (after the window, separate launches): " +
+        ", ".join(f"{k} {v:.4f}" for k, v in ph.items()))
+
+    # factors relinearised in each timed iteration: the run is bitwise
+    # reproducible, so it is replayed from its start one iteration at a time,
+    # reading the relinearisation count after each (untimed)
+    solver.reset()
+    while solver.t < start - 9:
+        solver.iterate_logged(min(c, start - 9 - solver.t), 0.4, 2.0, log_every=1)
+    due = []  # due[j]: factors relinearised in iteration start - 8 + j
+    while solver.t < t_end:
+        solver.iterate(1, 0.4, 2.0)
+        due.append(solver.last_relinearised)
+    due_win = due[9:]
+    n_due = float(np.mean(due_win))
+    # factors old enough to be checked in timed iteration start + 1 + j:
+    # those not relinearised in the 9 iterations before it
+    n_old = float(np.mean([nf - sum(due[j:j + 9]) for j in range(K)]))
+    relin_frac = n_due / nf
+    log(f"relinearised per timed iteration: {100 * relin_frac:.2f}% of factors "
+        f"(min {min(due_win) / nf * 100:.2f}%, max {max(due_win) / nf * 100:.2f}%)")
+    n_blocks = sum(-(-p.n_factors // 256) for p in probs)  # residual blocks: 256 factors within a problem
+    sb = step_bytes(nf, nk, nl, n_due, n_old, n_blocks, with_ref=True)
+    fbytes = sb["k_factor_kf"]
     kms = ph.pop("k_factor_kf")  # the kernel alone, driver-recorded start/end events
     achieved = fbytes / (kms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
+    step_total = sum(sb.values())
+    sweep_gbs = step_total / (ms_per_step * 1e-3) / 1e9
+    log(f"sweep: {step_total / 1e6:.1f} MB of algorithmic traffic per step, {sweep_gbs:.0f} GB/s, "
+        f"{sweep_gbs / HBM_PEAK_GBS:.3f} of HBM peak")
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel="k_factor_kf", algorithmic_bytes_per_launch=int(fbytes),
                     kernel_ms=round(kms, 5),
+                    sweep=dict(achieved=round(sweep_gbs, 2), frac=round(sweep_gbs / HBM_PEAK_GBS, 4),
+                               algorithmic_bytes_per_step=int(step_total),
+                               bytes_per_launch={k: int(v) for k, v in sb.items()},
+                               ms_per_step=round(ms_per_step, 5)),
                     phases_ms={k: round(v, 5) for k, v in ph.items()},
-                    relinearised_fraction=round(relin_frac, 5))
-    are = last[-1] if last is not None else None
+                    relinearised_fraction=round(relin_frac, 5),
+                    checked_fraction=round(n_old / nf, 4),
+                    timed_iterations=[start + 1, t_end])
     solver.close()
     if args.copy_calibration:
         copy_calibration(torch)

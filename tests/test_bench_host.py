@@ -17,13 +17,33 @@ def test_algorithmic_bytes_of_the_keyframe_kernel():
     # per factor: keyframe-side Jacobian, s and message (16 floats),
     # landmark-side Jacobian and message (11), factor-private data (10),
     # landmark index, counter and flags; both messages and the counter
-    # written: 195 B; per keyframe 27 doubles in and 27 out; per landmark
-    # 9 doubles
+    # written: 195 B; per keyframe its slot, 27 doubles in and 27 out; per
+    # landmark 9 doubles
     assert bench.FACTOR_BYTES_PER_FACTOR == 195
-    assert bench.factor_launch_bytes(1, 0, 0) == 195
-    assert bench.factor_launch_bytes(0, 1, 0) == 432
-    assert bench.factor_launch_bytes(0, 0, 1) == 72
-    assert bench.factor_launch_bytes(2151544, 17940, 269085) == 446675280
+    kf = lambda nf, nk, nl, due=0: bench.step_bytes(nf, nk, nl, due, 0, 0, False)["k_factor_kf"]  # noqa: E731
+    assert kf(1, 0, 0) == 195
+    assert kf(0, 1, 0) == 448
+    assert kf(0, 0, 1) == 72
+    assert kf(10, 0, 0, due=1) == 9 * 195 + 70
+
+
+def test_step_bytes_of_the_other_launches():
+    """Each launch's per-unit figure, one unit at a time."""
+    sb = lambda *a: bench.step_bytes(*a)  # noqa: E731
+    # relinearisation: 372 B per due factor, every keyframe's belief and
+    # anchor once, the landmarks it touches once
+    assert sb(1, 0, 0, 0, 0, 0, False)["k_relin"] == 0
+    assert sb(1, 1, 1, 1, 0, 0, False)["k_relin"] == 372 + 264 + 96
+    # landmark beliefs: 56 B per edge, 104 B per landmark, 636 B per keyframe
+    assert sb(1, 0, 0, 0, 0, 0, False)["k_belief_lm"] == 56
+    assert sb(0, 1, 1, 0, 0, 0, False)["k_belief_lm"] == 636 + 104
+    # residuals and check: 26 B per factor (43 B with a reference), 36 B per
+    # checked factor, 16 B per queued factor, 144 / 48 B per keyframe /
+    # landmark, 140 B per residual block
+    assert sb(1, 0, 0, 0, 0, 0, False)["k_reproj_block"] == 26
+    assert sb(1, 0, 0, 0, 0, 0, True)["k_reproj_block"] == 43
+    assert sb(1, 0, 0, 0, 1, 0, False)["k_reproj_block"] == 26 + 36
+    assert sb(0, 1, 1, 0, 0, 1, False)["k_reproj_block"] == 144 + 48 + 140
 
 
 def _profile(tmp_path, sha, nbytes="577144814"):
