@@ -456,7 +456,8 @@ def main():
     tuned = solver.autotune(5, None if args.no_tune_cache else
                             os.path.join(ROOT, "paper_2003_03134_amd", "tuning", "autotune_cache.txt"))
     log(f"autotuned: keyframe kernel {tuned[0]} lanes/workgroup, landmark kernel {tuned[1]} "
-        f"lanes/workgroup, {tuned[2]} lanes per landmark")
+        f"lanes/workgroup, {tuned[2]} lanes per landmark, {tuned[3]} relinearisation queue segments "
+        f"per workgroup")
 
     K, W = args.steps, args.warmup
     c = max(1, min(args.chunk, K))
@@ -586,7 +587,7 @@ def main():
                    "step": "relinearisation check + factor messages + beliefs + per-problem reprojection error",
                    "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU",
                    "autotuned": {"keyframe_kernel_block": tuned[0], "landmark_kernel_block": tuned[1],
-                                 "lanes_per_landmark": tuned[2]}},
+                                 "lanes_per_landmark": tuned[2], "relin_segments_per_workgroup": tuned[3]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

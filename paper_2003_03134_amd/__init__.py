@@ -202,12 +202,13 @@ class GBPSolver:
                     k_factor_kf=ms[5])
 
     def autotune(self, n_iters: int = 5, cache_path: str | None = None) -> tuple:
-        """Pick workgroup sizes and lanes per landmark by timing (state
-        restored); returns (kf block, lm block, lanes per landmark)."""
-        chosen = (C.c_int32 * 3)()
+        """Pick workgroup sizes, lanes per landmark and relinearisation
+        segments per workgroup by timing (state restored); returns (kf block,
+        lm block, lanes per landmark, relinearisation segments)."""
+        chosen = (C.c_int32 * 4)()
         path = cache_path.encode() if cache_path else None
         self._check(self._lib.gbp_autotune(self.h, int(n_iters), path, chosen), self.h)
-        return chosen[0], chosen[1], chosen[2]
+        return chosen[0], chosen[1], chosen[2], chosen[3]
 
     def synchronize(self):
         self.stream.synchronize()

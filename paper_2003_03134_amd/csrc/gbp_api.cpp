@@ -503,6 +503,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
 #undef UP
     p->fdamp_buf = d.fdamp;
     d.lm_lanes = LM_LANES;
+    d.relin_group = 2;  // untuned default (measured fastest on the 256-problem batch)
     d.fdamp = nullptr;
     d.fallback = nullptr;
     // initial linearisation at the initial estimate, automatic priors,
@@ -753,39 +754,73 @@ std::string tune_key(gbp_problem *p) {
 }
 
 // tiny cache: one line per key, "key kf_block lm_block lm_lanes ms"
-bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll) {
+// cache line: key, keyframe-kernel size, landmark-kernel size, lanes per
+// landmark, relinearisation segments per workgroup, iteration ms
+bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll, int &rg) {
     if (!path) return false;
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
         std::istringstream is(line);
         std::string k2;
-        int a = 0, b = 0, c = 0;
+        int a = 0, b = 0, c = 0, e = 0;
         double ms = 0;
-        if ((is >> k2 >> a >> b >> c >> ms) && k2 == key) { kb = a; lb = b; ll = c; return true; }
+        // entries of an older format (no segment count) do not match
+        if ((is >> k2 >> a >> b >> c >> e >> ms) && k2 == key && e >= 1 && e <= 16 && (c == 2 || c == 4 || c == 8)) {
+            kb = a; lb = b; ll = c; rg = e;
+            return true;
+        }
     }
     return false;
 }
 
-void cache_store(const char *path, const std::string &key, int kb, int lb, int ll, double ms) {
+void cache_store(const char *path, const std::string &key, int kb, int lb, int ll, int rg, double ms) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << kb << " " << lb << " " << ll << " " << ms << "\n";
+    out << key << " " << kb << " " << lb << " " << ll << " " << rg << " " << ms << "\n";
+}
+
+// n launches of the relinearisation kernel on a synthetic queue (every 11th
+// factor of each residual block)
+template <typename TS>
+gbp_status time_relin(gbp_problem *p, int n, double *ms) {
+    Dev<TS> &d = dev<TS>(p);
+    hipStream_t s = p->stream;
+    hipEvent_t a, b;
+    HIP_TRY(p, hipEventCreate(&a));
+    HIP_TRY(p, hipEventCreate(&b));
+    HIP_TRY(p, hipEventRecord(a, s));
+    for (int i = 0; i < n; ++i) {
+        launch_queue_every<TS>(d, 11, s);
+        launch_relin<TS>(d, p->iopt, s);
+    }
+    HIP_TRY(p, hipEventRecord(b, s));
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / n;
+    return GBP_OK;
 }
 
 // Autotuner: the workgroup sizes of the keyframe kernel and of the landmark
 // belief kernel (3 x 3, with 4 lanes per landmark), then the lanes per
-// landmark (2 / 4 / 8) with the chosen sizes; each candidate runs n
-// iterations from a snapshot of the workspace, which is restored after it.
+// landmark (2 / 4 / 8) with the chosen sizes, then the queue segments per
+// relinearisation workgroup (1 / 2 / 4) on a synthetic steady-state queue;
+// each candidate runs n iterations (or relinearisation launches) from a
+// snapshot of the workspace, which is restored after it.
 template <typename TS>
 gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t *chosen) {
     Dev<TS> &d = dev<TS>(p);
     const std::string key = tune_key(p);
-    int kb = 0, lb = 0, ll = 0;
-    if (cache_lookup(cache_path, key, kb, lb, ll) && (ll == 2 || ll == 4 || ll == 8)) {
+    int kb = 0, lb = 0, ll = 0, rg = 0;
+    if (cache_lookup(cache_path, key, kb, lb, ll, rg)) {
         p->blk_kf = kb;
         p->blk_lm = lb;
         d.lm_lanes = ll;
+        d.relin_group = rg;
     } else {
         void *snap = nullptr, *psnap = nullptr;
         HIP_TRY(p, hipMalloc(&snap, p->ws_bytes));
@@ -816,6 +851,19 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
         const int bk0 = bk, bl0 = bl;
         for (int z : {2, 8})
             if (st == GBP_OK) st = trial(bk0, bl0, z);
+        double best_r = 1e30;
+        int brg = d.relin_group;
+        for (int g : {1, 2, 4}) {
+            if (st != GBP_OK) break;
+            d.relin_group = g;
+            double ms = 0;
+            st = time_relin<TS>(p, n, &ms);
+            if (st != GBP_OK) break;
+            HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
+            if (psnap)
+                HIP_TRY(p, hipMemcpyAsync(p->pair_mem, psnap, p->pair_state_bytes, hipMemcpyDeviceToDevice, p->stream));
+            if (ms < best_r) { best_r = ms; brg = g; }
+        }
         HIP_TRY(p, hipStreamSynchronize(p->stream));
         (void)hipFree(snap);
         if (psnap) (void)hipFree(psnap);
@@ -823,10 +871,13 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
         p->blk_kf = bk;
         p->blk_lm = bl;
         d.lm_lanes = bll;
-        cache_store(cache_path, key, bk, bl, bll, best);
+        d.relin_group = brg;
+        cache_store(cache_path, key, bk, bl, bll, brg, best);
     }
     destroy_graphs(p);
-    if (chosen) { chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; chosen[2] = d.lm_lanes; }
+    if (chosen) {
+        chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; chosen[2] = d.lm_lanes; chosen[3] = d.relin_group;
+    }
     return GBP_OK;
 }
 

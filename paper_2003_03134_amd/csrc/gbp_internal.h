@@ -88,6 +88,7 @@ struct Dev {
     const KfSlot *kf_slot;                // work of each keyframe-kernel workgroup
     int n_kf_slots;                       // workgroups of the keyframe kernel
     int lm_lanes;                         // lanes per landmark in the landmark belief kernel (2, 4, 8)
+    int relin_group;                      // relinearisation queue segments per workgroup (1..16)
     const int *lm_row, *lm_edge;          // factors of each landmark (CSR, increasing)
     const int *f_row_prob;                // first factor of each problem (np + 1)
     // factor state
@@ -143,6 +144,8 @@ template <typename TS> void launch_check(const Dev<TS> &d, const IterOpts &o, hi
 template <typename TS> void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s,
                                          double *pending_log_row = nullptr);
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s);
+// tuning: queue every stride-th factor of each residual block for relinearisation
+template <typename TS> void launch_queue_every(const Dev<TS> &d, int stride, hipStream_t s);
 // solve = false leaves the keyframe solve to launch_belief_lm(..., with_kf = true)
 template <typename TS> void launch_factor_kf(const Dev<TS> &d, const IterOpts &o, int block, hipStream_t s,
                                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool solve = true);

@@ -724,6 +724,17 @@ __global__ __launch_bounds__(RTHREADS) void k_check(Dev<TS> d, IterOpts o) {
     queue_due(d, b, f, k, m, need);
 }
 
+// Tuning load for the relinearisation kernel: every stride-th factor of each
+// residual block goes to the block's queue segment, as the check queues due
+// factors (stride 11: about the share due per iteration at steady state).
+template <typename TS>
+__global__ __launch_bounds__(RTHREADS) void k_queue_every(Dev<TS> d, int stride) {
+    const int b = blockIdx.x;
+    const int f = d.rblk_start[b] + (int)threadIdx.x;
+    const bool in = f < d.rblk_start[b + 1];
+    queue_due(d, b, f, in ? d.f_kf[f] : 0, in ? d.f_lm[f] : 0, in && (int)threadIdx.x % stride == 0);
+}
+
 // One problem's residual statistics from its blocks' partials (64 threads):
 // lane l adds blocks l, l + 64, ... in order, then a butterfly adds the lanes
 // (a fixed order: deterministic). Writes the 8 sums to out (if set) and a log
@@ -990,6 +1001,7 @@ __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
 // of the previous iteration's fused residual pass (whose check advanced the
 // clock: t_off -1) into log_row.
 constexpr int RELIN_BS = 128;
+constexpr int RELIN_GROUP_MAX = 16;  // queue segments per relinearisation workgroup, at most
 
 // (two waves per SIMD: 256 registers, of which about 150 accumulation
 // registers the compiler uses as spill space)
@@ -997,20 +1009,37 @@ template <typename TS>
 __global__ __launch_bounds__(RELIN_BS) __attribute__((amdgpu_waves_per_eu(2))) void k_relin(Dev<TS> d, IterOpts o,
                                                                                             int nseg, int nred,
                                                                                             double *log_row) {
-    if ((int)blockIdx.x >= nseg) {
+    const int G = d.relin_group;
+    const int nwg = (nseg + G - 1) / G;
+    if ((int)blockIdx.x >= nwg) {
         if (threadIdx.x >= 64) return;  // one wave per problem
-        reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nseg, nullptr, log_row, d.t_dev, -1);
+        reduce_problem(d.rblk_part, d.prob_rblk, (int)blockIdx.x - nwg, nullptr, log_row, d.t_dev, -1);
         return;
     }
-    const int b = xcd_remap(blockIdx.x, nseg);
-    const int n = d.relin_qcount[b];
-    // a residual block lies in one problem: its parameters and learned-
-    // damping switch are the same for the whole workgroup
-    const int prob = d.rblk_prob[b];
-    const int fd_on = (d.fdamp && !d.fallback[prob]) ? 1 : 0;
     const double pend_k = d.pending_k[0];
-    for (int i = threadIdx.x; i < n; i += RELIN_BS) {
-        const RelinEntry q = d.relin_queue[(size_t)b * RBLK + i];
+    // G consecutive segments per workgroup, their entries dealt to the lanes
+    // in order (entry i of the group: segment g with pre[g] <= i < pre[g+1]);
+    // G = 1: one segment, whose problem is the workgroup's
+    __shared__ int pre[RELIN_GROUP_MAX + 1];
+    const int b0 = (G == 1 ? xcd_remap(blockIdx.x, nseg) : xcd_remap(blockIdx.x, nwg) * G);
+    const int gn = min(G, nseg - b0);
+    if ((int)threadIdx.x < gn) pre[threadIdx.x + 1] = d.relin_qcount[b0 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int g = 1; g <= gn; ++g) pre[g] += pre[g - 1];
+    }
+    __syncthreads();
+    const int total = pre[gn];
+    for (int i = threadIdx.x; i < total; i += RELIN_BS) {
+        int g = 0;
+        while (g + 1 < gn && pre[g + 1] <= i) ++g;
+        const int b = b0 + g;
+        // a residual block lies in one problem: its parameters and learned-
+        // damping switch hold for all of the block's entries
+        const int prob = d.rblk_prob[b];
+        const int fd_on = (d.fdamp && !d.fallback[prob]) ? 1 : 0;
+        const RelinEntry q = d.relin_queue[(size_t)b * RBLK + (i - pre[g])];
         factor_body<TS, true>(d, o, q.f, q.k, q.m, d.kf_bel + (size_t)q.k * KBEL, nullptr, fd_on, prob, pend_k);
     }
 }
@@ -1852,12 +1881,17 @@ void launch_check(const Dev<TS> &d, const IterOpts &o, hipStream_t s) {
 template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
     const int nred = pending_log_row ? d.np : 0;
-    const int g = d.n_rblk + nred;
+    const int g = (d.n_rblk + d.relin_group - 1) / d.relin_group + nred;
     if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(RELIN_BS), 0, s, d, o, d.n_rblk, nred, pending_log_row);
     // pairwise factors: they read the previous iteration's beliefs and
     // their own messages only, like the relinearised factors
     const int np = d.n_pair[0] + d.n_pair[1];
     if (np > 0) hipLaunchKernelGGL(k_pairs<TS>, dim3(blocks(np, 128)), dim3(128), 0, s, d, o);
+}
+
+template <typename TS>
+void launch_queue_every(const Dev<TS> &d, int stride, hipStream_t s) {
+    if (d.n_rblk > 0) hipLaunchKernelGGL(k_queue_every<TS>, dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, stride);
 }
 
 void launch_relin_total(const int *qcount, int nb, unsigned long long *out, hipStream_t s) {
@@ -1982,6 +2016,7 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
     template void launch_prior_base<TS>(const Dev<TS> &, int, int, hipStream_t);                                   \
     template void launch_check<TS>(const Dev<TS> &, const IterOpts &, hipStream_t);                                \
     template void launch_relin<TS>(const Dev<TS> &, const IterOpts &, hipStream_t, double *);                      \
+    template void launch_queue_every<TS>(const Dev<TS> &, int, hipStream_t);                                       \
     template void launch_factor_kf<TS>(const Dev<TS> &, const IterOpts &, int, hipStream_t, hipEvent_t,            \
                                        hipEvent_t, bool);                                                        \
     template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t, bool);            \

@@ -293,14 +293,14 @@ def test_autotune_leaves_state_unchanged(gbp, tmp_path):
     s.iterate(15, 0.4, 2.0)
     before = s.beliefs()          # stored beliefs (no recomputation)
     cache = str(tmp_path / "tune.txt")
-    kb, lb, ll = s.autotune(3, cache)
-    assert kb in (64, 128, 256) and lb in (64, 128, 256) and ll in (2, 4, 8)
+    kb, lb, ll, rg = s.autotune(3, cache)
+    assert kb in (64, 128, 256) and lb in (64, 128, 256) and ll in (2, 4, 8) and rg in (1, 2, 4)
     after = s.beliefs()
     for key in before:            # the device state was restored exactly
         assert np.array_equal(before[key], after[key]), key
     # a second problem of the same size bucket takes the cached choice
     s2 = gbp.GBPSolver(prob)
-    assert s2.autotune(3, cache) == (kb, lb, ll)
+    assert s2.autotune(3, cache) == (kb, lb, ll, rg)
     assert open(cache).read().count("\n") == 1
     o = oracle.Oracle(prob, anneal=True)
     o.iterate(15, 0.4, 2.0)
@@ -326,8 +326,8 @@ def test_every_landmark_lane_count_matches_oracle(gbp, lanes, tmp_path):
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     key = (f"{arch}/p{gbp.GBP_FP64}/f{key_bucket(nf)}/k{key_bucket(prob.n_keyframes)}"
            f"/l{key_bucket(prob.n_landmarks)}")
-    cache.write_text(f"{key} 64 64 {lanes} 0.0\n")
-    assert s.autotune(2, str(cache)) == (64, 64, lanes)
+    cache.write_text(f"{key} 64 64 {lanes} 2 0.0\n")
+    assert s.autotune(2, str(cache)) == (64, 64, lanes, 2)
     o = oracle.Oracle(prob, anneal=False)
     for _ in range(4):
         s.iterate(10, 0.4, 2.0)
@@ -335,6 +335,35 @@ def test_every_landmark_lane_count_matches_oracle(gbp, lanes, tmp_path):
         assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
         s.relinearise(-1)
         o.relinearise(-1)
+    s.close()
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_every_relin_grouping_matches_oracle(gbp, group, tmp_path):
+    """The relinearisation kernel with 1, 2 and 4 queue segments per
+    workgroup (forced through a tuning-cache entry; groups straddle the
+    problems of a batch) agrees with the FP64 oracle under the beta rule."""
+    import oracle
+    import torch
+    probs = [synth.make_config3_problem(p) for p in (3, 7, 11)]
+    s = gbp.GBPSolver(probs, precision=gbp.GBP_FP64, anneal=True)
+    lg = lambda v: max(0, int(np.floor(np.log2(v)))) if v > 1 else 0  # noqa: E731
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    nk, nl, nf = (sum(getattr(p, a) for p in probs) for a in ("n_keyframes", "n_landmarks", "n_factors"))
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch}/p{gbp.GBP_FP64}/f{lg(nf)}/k{lg(nk)}/l{lg(nl)} 64 64 4 {group} 0.0\n")
+    assert s.autotune(2, str(cache)) == (64, 64, 4, group)
+    s.iterate(60, 0.4, 2.0)
+    g = s.beliefs()
+    kf_off = np.concatenate([[0], np.cumsum([p.n_keyframes for p in probs])])
+    lm_off = np.concatenate([[0], np.cumsum([p.n_landmarks for p in probs])])
+    for i, p in enumerate(probs):
+        o = oracle.Oracle(p, anneal=True)
+        o.iterate(60, 0.4, 2.0)
+        r = o.beliefs()
+        e = max(rel_mean_err(g["kf_mu"][kf_off[i]:kf_off[i + 1]], r["kf_mu"]),
+                rel_mean_err(g["lm_mu"][lm_off[i]:lm_off[i + 1]], r["lm_mu"]))
+        assert e < 1e-8, (group, i, e)
     s.close()
 
 
