@@ -255,14 +255,29 @@ gbp_status gbp_add_keyframe(gbp_problem *p, const double pose[6],
  * whose damping head replaces the constant damping of each factor outside
  * its undamped window. Fallback: a problem whose mean reprojection error
  * exceeds (1 + fallback_rise) x the best value seen since the model was set
- * (or since its last growth), or is not finite, or any failed belief, goes
- * back to the constant damping for good (fallback_rise <= -1: never; a
+ * (or since its last growth; with a plain-GBP judge, see
+ * gbp_set_damping_judges, x the judge's error at the same iteration), or is
+ * not finite, or one of whose beliefs failed, goes back to the constant
+ * damping for good (fallback_rise <= -1: never; a
  * value in (-1, 0) switches every problem at the second evaluation). The
  * first call allocates about 116 bytes of device memory per factor of
  * capacity, owned by the problem. Errors: GBP_EINVAL for every_k outside
  * [1, 1000] or a NaN fallback_rise. Synchronises. */
 gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights,
                                  int32_t every_k, double fallback_rise);
+
+/* Plain GBP as the judge of the learned damping (for batches). judge_of[i]
+ * = j >= 0 names problem j of the batch as the judge of problem i: j must
+ * hold the same problem (same graph, measurements and initial estimate) and
+ * it runs the constant damping throughout; at every model evaluation problem
+ * i goes back to the constant damping for good when its mean reprojection
+ * error exceeds (1 + fallback_rise) x its judge's at the same iteration (in
+ * place of the best-seen rule of gbp_set_damping_model). judge_of[i] = -1:
+ * problem i keeps the best-seen rule; NULL: no judges. A judge cannot have a
+ * judge. Kept across gbp_reset and gbp_set_damping_model. Errors:
+ * GBP_ESTATE without a damping model, GBP_EINVAL for a judge index outside
+ * the batch, equal to i, or itself judged. Synchronises. */
+gbp_status gbp_set_damping_judges(gbp_problem *p, const int32_t *judge_of);
 
 /* Restart: back to the state right after creation (every factor linearised
  * at the initial estimate, zero messages, beliefs = priors at clock 0, and
@@ -288,7 +303,7 @@ gbp_status gbp_apply_depth_model(gbp_problem *p, const int32_t *landmarks,
                                  int32_t n);
 
 /* Per-problem fallback state of the damping model (flags[n_problems]: 1 =
- * switched back to the constant damping). Synchronises. */
+ * switched back to the constant damping; judges read 1). Synchronises. */
 gbp_status gbp_fallback_flags(gbp_problem *p, int32_t *flags);
 
 /* Features of the damping model, in the caller's factor order: computes the

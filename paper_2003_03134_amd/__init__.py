@@ -291,6 +291,19 @@ class GBPSolver:
         self._check(self._lib.gbp_set_damping_model(self.h, _ptr(w, C.c_uint16), int(every_k),
                                                      float(fallback_rise)), self.h)
 
+    def set_damping_judges(self, judge_of) -> None:
+        """Plain GBP as the judge of the learned damping: judge_of[i] = j names
+        problem j of the batch (the same problem, run with the constant
+        damping) as problem i's judge; -1: the best-seen rule; None: no
+        judges. Call after set_damping_model."""
+        if judge_of is None:
+            self._check(self._lib.gbp_set_damping_judges(self.h, None), self.h)
+            return
+        j = _i32(judge_of).ravel()
+        if j.size != self.n_problems:
+            raise ValueError("one judge entry per problem")
+        self._check(self._lib.gbp_set_damping_judges(self.h, _ptr(j, C.c_int32)), self.h)
+
     def reset(self) -> None:
         """Back to the state right after creation (keeps recorded graphs)."""
         self._check(self._lib.gbp_reset(self.h), self.h)

@@ -60,7 +60,7 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_create_batch", "gbp_relinearise", "gbp_iterate", "gbp_beliefs",
            "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference", "gbp_add_pair_factors",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
-           "gbp_reset", "gbp_apply_depth_model", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
+           "gbp_reset", "gbp_apply_depth_model", "gbp_set_damping_judges", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
            "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step", "gbp_mlp_train_step_static",
            "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
 
@@ -109,6 +109,7 @@ def load():
     lib.gbp_add_keyframe.argtypes = [P, _dp, C.c_int32, _dp, C.c_int32, _ip, _ip, _dp]
     lib.gbp_set_damping_model.argtypes = [P, _u16p, C.c_int32, C.c_double]
     lib.gbp_reset.argtypes = [P]
+    lib.gbp_set_damping_judges.argtypes = [P, _ip]
     lib.gbp_apply_depth_model.argtypes = [P, _ip, C.c_int32]
     lib.gbp_fallback_flags.argtypes = [P, _ip]
     lib.gbp_factor_features.argtypes = [P, P, C.c_int32, P]

@@ -92,6 +92,8 @@ struct gbp_problem {
     int *d_u2i = nullptr;          // caller factor index -> internal slot
     int *d_lms = nullptr;          // [cap_l] landmark list (learned depth)
     int *d_fallback = nullptr;     // [np]
+    int *d_judge = nullptr;        // [np] judge of each problem (monitor), -1 none, -2 is a judge
+    std::vector<int> h_judge;      // host copy (empty: no judges)
     double *d_best = nullptr;      // [np] best mean reprojection error seen
     bool learned = false;
     bool grown = false;            // gbp_add_keyframe was called
@@ -181,6 +183,7 @@ void plan(gbp_problem *p, Dev<TS> &d, Layout &L) {
     L.add((void **)&d.prob, P * sizeof(ProbParams));
     L.add((void **)&d.t_dev, 4);
     L.add((void **)&d.status, 4);
+    L.add((void **)&d.pstatus, P * 4);
     L.add((void **)&d.pending_k, 8);
     // relinearisation queue: one segment per residual block (F / RBLK + P + 1)
     L.add((void **)&d.relin_queue, (F / RBLK + P + 1) * RBLK * sizeof(RelinEntry));
@@ -498,6 +501,7 @@ gbp_status upload_and_init(gbp_problem *p, const gbp_graph *gs, const gbp_camera
     }
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.pstatus, 0, (size_t)p->np * 4, s));
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
 #undef UP
@@ -588,7 +592,7 @@ void record_model(gbp_problem *p, hipStream_t s, bool stats_fresh) {
     // the monitor's per-problem statistics: the previous iteration's logged
     // residual pass left them in are_out at the same beliefs, else compute
     if (!stats_fresh) launch_reproj<TS>(d, p->iopt, p->huber_k, nullptr, nullptr, nullptr, s);
-    launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.status, s);
+    launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.pstatus, p->d_judge, s);
     launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
     launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
 }
@@ -904,6 +908,7 @@ gbp_status ensure_learn_mem(gbp_problem *p) {
     L.add((void **)&p->d_u2i, F * 4);
     L.add((void **)&p->d_lms, (size_t)p->cap_l * 4);
     L.add((void **)&p->d_fallback, P * 4);
+    L.add((void **)&p->d_judge, P * 4);
     L.add((void **)&p->d_best, P * 8);
     void *mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess) return fail(p, GBP_ENOMEM, "cannot allocate the learned-model buffers");
@@ -912,6 +917,9 @@ gbp_status ensure_learn_mem(gbp_problem *p) {
     hipStream_t s = p->stream;
     HIP_TRY(p, hipMemsetAsync(p->d_hist, 0, F * FHIST * 4, s));
     HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, P * 4, s));
+    p->h_judge.assign(P, -1);
+    HIP_TRY(p, hipMemcpyAsync(p->d_judge, p->h_judge.data(), P * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
     std::vector<double> inf(P, HUGE_VAL);
     HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), P * 8, hipMemcpyHostToDevice, s));
     launch_fill_f32(p->fdamp_buf, -1.f, (int)F, s);
@@ -1099,6 +1107,16 @@ gbp_status depth_impl(gbp_problem *p, const std::vector<int> &lms) {
     return GBP_OK;
 }
 
+// Every problem back on the learned damping, except the plain-GBP judges
+// (they run the constant damping throughout).
+gbp_status reset_fallback(gbp_problem *p) {
+    std::vector<int> fb(p->np, 0);
+    for (int i = 0; i < p->np && i < (int)p->h_judge.size(); ++i) fb[i] = p->h_judge[i] == -2 ? 1 : 0;
+    HIP_TRY(p, hipMemcpyAsync(p->d_fallback, fb.data(), (size_t)p->np * 4, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return GBP_OK;
+}
+
 gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double rise) {
     destroy_graphs(p);
     if (!w) {
@@ -1111,7 +1129,8 @@ gbp_status set_model_impl(gbp_problem *p, const uint16_t *w, int every_k, double
     if (st != GBP_OK) return st;
     hipStream_t s = p->stream;
     HIP_TRY(p, hipMemcpyAsync(p->d_w, w, MLP_NPARAMS * 2, hipMemcpyHostToDevice, s));
-    HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, (size_t)p->np * 4, s));
+    st = reset_fallback(p);
+    if (st != GBP_OK) return st;
     std::vector<double> inf(p->np, HUGE_VAL);
     HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), (size_t)p->np * 8, hipMemcpyHostToDevice, s));
     launch_fill_f32(p->fdamp_buf, -1.f, p->cap_f, s);
@@ -1242,6 +1261,7 @@ gbp_status reset_impl(gbp_problem *p) {
     }
     HIP_TRY(p, hipMemsetAsync(d.t_dev, 0, 4, s));
     HIP_TRY(p, hipMemsetAsync(d.status, 0, 4, s));
+    HIP_TRY(p, hipMemsetAsync(d.pstatus, 0, (size_t)p->np * 4, s));
     HIP_TRY(p, hipMemsetAsync(d.relin_qcount, 0, ((size_t)p->cap_f / RBLK + p->np + 1) * 4, s));
     HIP_TRY(p, hipMemcpyAsync(d.pending_k, &p->huber_k, 8, hipMemcpyHostToDevice, s));
     if (p->pair_mem) HIP_TRY(p, hipMemsetAsync(p->pair_mem, 0, p->pair_state_bytes, s));  // pair messages, counts
@@ -1251,7 +1271,8 @@ gbp_status reset_impl(gbp_problem *p) {
     launch_belief_kf<TS>(d, p->iopt, 0, p->blk_kf, s);
     if (p->learn_mem) {
         HIP_TRY(p, hipMemsetAsync(p->d_hist, 0, (size_t)p->cap_f * FHIST * 4, s));
-        HIP_TRY(p, hipMemsetAsync(p->d_fallback, 0, (size_t)p->np * 4, s));
+        gbp_status sf = reset_fallback(p);
+        if (sf != GBP_OK) return sf;
         std::vector<double> inf(p->np, HUGE_VAL);
         HIP_TRY(p, hipMemcpyAsync(p->d_best, inf.data(), (size_t)p->np * 8, hipMemcpyHostToDevice, s));
         launch_fill_f32(p->fdamp_buf, -1.f, p->cap_f, s);
@@ -1539,6 +1560,28 @@ gbp_status gbp_set_damping_model(gbp_problem *p, const uint16_t *weights, int32_
     if (weights && (every_k < 1 || every_k > 1000 || std::isnan(fallback_rise)))
         return fail(p, GBP_EINVAL, "need 1 <= every_k <= 1000 and a fallback_rise that is not NaN");
     return set_model_impl(p, weights, every_k, fallback_rise);
+}
+
+gbp_status gbp_set_damping_judges(gbp_problem *p, const int32_t *judge_of) {
+    gbp_status st = check_live(p);
+    if (st != GBP_OK) return st;
+    if (!p->learned) return fail(p, GBP_ESTATE, "set a damping model first");
+    std::vector<int> dj(p->np, -1);
+    if (judge_of) {
+        for (int i = 0; i < p->np; ++i) {
+            const int j = judge_of[i];
+            if (j == -1) continue;
+            if (j < 0 || j >= p->np || j == i || judge_of[j] != -1)
+                return fail(p, GBP_EINVAL, "judge of problem " + std::to_string(i) +
+                                               " must be another problem of the batch that has no judge itself");
+            dj[i] = j;
+        }
+        for (int i = 0; i < p->np; ++i)
+            if (judge_of[i] >= 0) dj[judge_of[i]] = -2;
+    }
+    p->h_judge = dj;
+    HIP_TRY(p, hipMemcpyAsync(p->d_judge, dj.data(), (size_t)p->np * 4, hipMemcpyHostToDevice, p->stream));
+    return reset_fallback(p);
 }
 
 gbp_status gbp_reset(gbp_problem *p) {

@@ -101,6 +101,7 @@ struct Dev {
     const ProbParams *prob;
     int *t_dev;                           // iteration clock
     unsigned *status;                     // bit 0: non-PD belief, bit 1: non-finite
+    unsigned *pstatus;                    // the same bits per problem (np)
     double *pending_k;                    // Huber threshold for requested relinearisations
     RelinEntry *relin_queue;              // factors due for relinearisation, RBLK per residual block
     int *relin_qcount;                    // queue entries of each residual block
@@ -168,8 +169,8 @@ template <typename TS> void launch_export_messages(const Dev<TS> &d, const int *
 void launch_fill_f32(float *p, float v, int n, hipStream_t s);
 void launch_gather_rows(const float *src, float *dst, const int *idx, const int *u2i, int nf, int n, int w,
                         hipStream_t s);
-void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
-                    hipStream_t s);
+void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *pstatus,
+                    const int *judge, hipStream_t s);
 template <typename TS> void launch_depth_move(const Dev<TS> &d, const int *lms, int n, const float *delta,
                                               hipStream_t s);
 void launch_tick(int *t_dev, hipStream_t s);

@@ -110,6 +110,15 @@ __device__ __forceinline__ void load8(const double *__restrict__ p, double (&v)[
     for (int i = 0; i < 4; ++i) { double2 a = q[i]; v[2 * i] = a.x; v[2 * i + 1] = a.y; }
 }
 
+// A belief that failed (bit 0: not positive definite, bit 1: not finite):
+// the batch's status word, read by the synchronising calls, and its
+// problem's, read by the fallback monitor of the learned damping.
+template <typename TS>
+__device__ __forceinline__ void flag_failure(const Dev<TS> &d, int prob, unsigned bit) {
+    atomicOr(d.status, bit);
+    atomicOr(d.pstatus + prob, bit);
+}
+
 // a non-negative index kept in a record slot of the factor state's type
 __device__ __forceinline__ float index_to_slot(int i, float) { return __int_as_float(i); }
 __device__ __forceinline__ double index_to_slot(int i, double) { return (double)i; }
@@ -838,7 +847,7 @@ __device__ void pair_update(const Dev<TS> &d, const IterOpts &o, const int kind,
             for (int r = 0; r < D; ++r) w[r] = (1.0 - dd) * w[r] + dd * mv[r] + dd * corr[r];
         }
     }
-    if (!ok) { atomicOr(d.status, 1u); return; }
+    if (!ok) { flag_failure(d, kind == 0 ? d.kf_prob[a] : d.lm_prob[a], 1u); return; }
 #pragma unroll
     for (int q = 0; q < D + T; ++q) {
         msg[D + T + q] = out[0][q];  // to b
@@ -970,7 +979,7 @@ __device__ void odometry_update(const Dev<TS> &d, const int i) {
             }
         }
     }
-    if (!ok) { atomicOr(d.status, 1u); return; }
+    if (!ok) { flag_failure(d, d.kf_prob[a], 1u); return; }
 #pragma unroll
     for (int q = 0; q < 6 + T; ++q) {
         msg[6 + T + q] = out[0][q];  // to b
@@ -1108,12 +1117,12 @@ __device__ void kf_solve(const Dev<TS> &d, const IterOpts &o, const int k, const
             for (int j = 0; j < 6; ++j) out[6 * i + j] = A[pidx<6>(i, j)];
     }
     double L[21], inv[21], x[6];
-    if (!chol<6>(A, L)) { atomicOr(d.status, 1u); return; }
+    if (!chol<6>(A, L)) { flag_failure(d, d.kf_prob[k], 1u); return; }
     chol_inverse_solve<6>(L, e, inv, x);
     bool fin = true;
 #pragma unroll
     for (int i = 0; i < 6; ++i) fin = fin && isfinite(x[i]);
-    if (!fin) { atomicOr(d.status, 2u); return; }
+    if (!fin) { flag_failure(d, d.kf_prob[k], 2u); return; }
     double *b = d.kf_bel + (size_t)k * KBEL;
 #pragma unroll
     for (int i = 0; i < 6; ++i) b[i] = x[i];
@@ -1601,12 +1610,12 @@ __global__ __launch_bounds__(256) void k_belief_lm(Dev<TS> d, IterOpts o, int re
             for (int j = 0; j < 3; ++j) out[3 * i + j] = A[pidx<3>(i, j)];
     }
     double L[6], inv[6], x[3];
-    if (!chol<3>(A, L)) { atomicOr(d.status, 1u); return; }
+    if (!chol<3>(A, L)) { flag_failure(d, d.lm_prob[m], 1u); return; }
     chol_inverse_solve<3>(L, e, inv, x);
     bool fin = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) fin = fin && isfinite(x[i]);
-    if (!fin) { atomicOr(d.status, 2u); return; }
+    if (!fin) { flag_failure(d, d.lm_prob[m], 2u); return; }
     double *b = d.lm_bel + (size_t)m * LBEL;
 #pragma unroll
     for (int i = 0; i < 3; ++i) b[i] = x[i];
@@ -1804,13 +1813,28 @@ __global__ void k_depth_move(Dev<TS> d, const int *__restrict__ lms, int n, cons
 // problem switches to the plain constant damping for good once its mean
 // reprojection error exceeds (1 + rise) times the best seen so far, or is not
 // finite, or a belief failed.
+// Fallback monitor of the learned damping (one thread per problem), run at
+// every model evaluation on the previous iteration's mean reprojection
+// errors: a problem whose judge is plain GBP (judge[p] = j >= 0: problem j
+// of the batch runs the same problem with the constant damping) goes back to
+// the constant damping for good when its error exceeds (1 + rise) x the
+// judge's at the same iteration; without a judge (-1) the reference is the
+// best error the problem itself has reached; a judge (-2) always runs the
+// constant damping. A non-finite error or a failed belief of the problem
+// (its own status word) also switches it.
 __global__ void k_monitor(const double *are_out, int np, double rise, double *best, int *fallback,
-                          const unsigned *status) {
+                          const unsigned *pstatus, const int *judge) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const double n = are_out[8 * (size_t)p + 3];
-    const double are = n > 0.0 ? are_out[8 * (size_t)p] / n : 0.0;
-    if (!isfinite(are) || status[0] != 0u || are > (1.0 + rise) * best[p]) fallback[p] = 1;
+    const int j = judge[p];
+    if (j == -2) { fallback[p] = 1; return; }
+    auto mean_err = [&](int q) {
+        const double n = are_out[8 * (size_t)q + 3];
+        return n > 0.0 ? are_out[8 * (size_t)q] / n : 0.0;
+    };
+    const double are = mean_err(p);
+    const double ref = j >= 0 ? mean_err(j) : best[p];
+    if (!isfinite(are) || pstatus[p] != 0u || are > (1.0 + rise) * ref) fallback[p] = 1;
     if (are < best[p]) best[p] = are;
 }
 
@@ -1994,10 +2018,11 @@ void launch_depth_move(const Dev<TS> &d, const int *lms, int n, const float *del
     if (n > 0) hipLaunchKernelGGL(k_depth_move<TS>, dim3(blocks(n, 64)), dim3(64), 0, s, d, lms, n, delta);
 }
 
-void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *status,
-                    hipStream_t s) {
+void launch_monitor(const double *are_out, int np, double rise, double *best, int *fallback, const unsigned *pstatus,
+                    const int *judge, hipStream_t s) {
     if (np > 0)
-        hipLaunchKernelGGL(k_monitor, dim3(blocks(np, 256)), dim3(256), 0, s, are_out, np, rise, best, fallback, status);
+        hipLaunchKernelGGL(k_monitor, dim3(blocks(np, 256)), dim3(256), 0, s, are_out, np, rise, best, fallback,
+                           pstatus, judge);
 }
 
 void launch_fill_f32(float *p, float v, int n, hipStream_t s) {

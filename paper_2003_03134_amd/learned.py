@@ -151,7 +151,7 @@ class _Pending:
 
 
 def generate(problems, *, iters=300, every=5, frac=0.05, damping=0.4, huber_k=2.0, seed=0,
-             follow=30, undamped=1, damp_mode=GBP_DAMP_ETA_LAMBDA, log=print):
+             follow=30, undamped=1, damp_mode=GBP_DAMP_ETA_LAMBDA, depth_label="converged", log=print):
     """Run plain GBP (FP32, constant damping) on a batch of problems and
     return features X (n, 16), labels Y (n, 2) and weights M (n, 2) of a
     random `frac` of the factors at every `every`-th iteration; each sample
@@ -160,7 +160,10 @@ def generate(problems, *, iters=300, every=5, frac=0.05, damping=0.4, huber_k=2.
     (undamped=1), so that almost every sampled update reveals its undamped
     value, and damps information and vector together (both stay
     interpolations, which keeps the run stable on large graphs; the
-    information vector, and with it h, is damped linearly either way)."""
+    information vector, and with it h, is damped linearly either way).
+    depth_label: "converged" takes the depth head's label from the run's
+    final beliefs, "truth" from the problems' true poses and points (a
+    landmark started far from its depth can converge to a wrong depth)."""
     solver = GBPSolver(problems, precision=GBP_FP32, undamped=undamped, damp_mode=damp_mode)
     done = []
     try:
@@ -189,8 +192,12 @@ def generate(problems, *, iters=300, every=5, frac=0.05, damping=0.4, huber_k=2.
                 pending.append(_Pending(t, idx, x, m0, depths(b["kf_mu"], b["lm_mu"], fkf[idx], flm[idx])))
             if t < iters:
                 solver.iterate(1, damping, huber_k)
-        b = solver.beliefs()
-        depT_all = depths(b["kf_mu"], b["lm_mu"], fkf, flm)
+        if depth_label == "truth":
+            depT_all = depths(np.concatenate([p.kf_true for p in problems]),
+                              np.concatenate([p.lm_true for p in problems]), fkf, flm)
+        else:
+            b = solver.beliefs()
+            depT_all = depths(b["kf_mu"], b["lm_mu"], fkf, flm)
     finally:
         solver.close()
     X, Y, M = [], [], []
@@ -283,20 +290,27 @@ def train(X, Y, M, *, epochs=6, batch=4096, lr=2e-3, seed=0, val_frac=0.1, log=p
 # ----------------------------------------------------------------------------
 
 def time_to_target(problem, *, weights=None, every_k=5, damping=0.4, huber_k=2.0, target=1.0,
-                   max_iters=300, fallback_rise=0.5, damp_mode=GBP_DAMP_ETA):
+                   max_iters=300, fallback_rise=0.5, damp_mode=GBP_DAMP_ETA, judge=False):
     """Plain (weights None) or learned GBP on one problem (FP32): the first
     iteration at which the mean error of inliers against their noise-free
     projections is <= target px, and the GPU wall time to get there. The
     run is made twice: the first records the iteration graph, the second
     (after gbp_reset) is timed as one replay with the error logged on the
     device every iteration; the time to target is the timed run's per
-    iteration time (model evaluations included) times the iterations."""
+    iteration time (model evaluations included) times the iterations.
+    judge: the learned run carries its plain-GBP judge (the same problem
+    with the constant damping) in the same launches, and its fallback
+    compares with that run's error (gbp_set_damping_judges)."""
     import torch
-    s = GBPSolver(problem, precision=GBP_FP32, damp_mode=damp_mode)
+    probs = [problem, problem] if judge else problem
+    s = GBPSolver(probs, precision=GBP_FP32, damp_mode=damp_mode)
     try:
-        s.set_reference(problem.z_true, problem.inlier)
+        n = 2 if judge else 1
+        s.set_reference(np.concatenate([problem.z_true] * n), np.concatenate([problem.inlier] * n))
         if weights is not None:
             s.set_damping_model(weights, every_k=every_k, fallback_rise=fallback_rise)
+            if judge:
+                s.set_damping_judges([1, -1])
         s.iterate_logged(max_iters, damping, huber_k, log_every=1)
         s.reset()
         s.synchronize()
@@ -314,7 +328,8 @@ def time_to_target(problem, *, weights=None, every_k=5, damping=0.4, huber_k=2.0
     return dict(iterations=it, ms=(wall * 1e3 * it / max_iters) if it else None,
                 ms_per_iter=wall * 1e3 / max_iters, final_are_ref=float(are_ref[-1]),
                 final_are_all=float(are_all[-1]), fallback=fb, max_iters=max_iters,
-                damping=damping, damp_mode=int(damp_mode), are_ref_at={i: round(float(are_ref[i - 1]), 4) for i in marks})
+                damping=damping, damp_mode=int(damp_mode), judged=bool(judge),
+                are_ref_at={i: round(float(are_ref[i - 1]), 4) for i in marks})
 
 
 def incremental_run(stream, *, weights=None, use_depth=False, every_k=5, damping=0.4, huber_k=2.0,
@@ -401,16 +416,30 @@ def incremental_run(stream, *, weights=None, use_depth=False, every_k=5, damping
 
 
 def compare(problem, weights, *, undamped_too=False, **kw) -> dict:
+    """Time to target of plain GBP as the paper runs it (damping 0.4 on the
+    information vector), of the learned damping (its own error history as
+    fallback rule) and of the learned damping with its plain-GBP judge in the
+    same launches; with undamped_too also plain GBP undamped and with
+    information and vector damped, and the learned damping under the latter.
+    speedup: against the paper's plain run; speedup_vs_best_plain: against
+    the fastest plain variant measured (None when a run misses the target)."""
     plain = time_to_target(problem, weights=None, **kw)
     learned = time_to_target(problem, weights=weights, **kw)
+    judged = time_to_target(problem, weights=weights, judge=True, **kw)
     sp = (plain["ms"] / learned["ms"]) if plain["ms"] and learned["ms"] else None
-    out = dict(plain=plain, learned=learned, speedup=sp)
+    out = dict(plain=plain, learned=learned, learned_judged=judged, speedup=sp)
     if undamped_too:
         out["plain_undamped"] = time_to_target(problem, weights=None, **dict(kw, damping=0.0))
         out["plain_damp_both"] = time_to_target(problem, weights=None,
                                                 **dict(kw, damp_mode=GBP_DAMP_ETA_LAMBDA))
         out["learned_damp_both"] = time_to_target(problem, weights=weights,
                                                   **dict(kw, damp_mode=GBP_DAMP_ETA_LAMBDA))
+    plains = {k: v for k, v in out.items() if k.startswith("plain") and v["ms"]}
+    if plains:
+        best = min(plains, key=lambda k: plains[k]["ms"])
+        out["best_plain"] = best
+        out["speedup_vs_best_plain"] = (plains[best]["ms"] / learned["ms"]) if learned["ms"] else None
+        out["judged_speedup_vs_best_plain"] = (plains[best]["ms"] / judged["ms"]) if judged["ms"] else None
     return out
 
 
@@ -436,6 +465,8 @@ def main(argv=None):
     ap.add_argument("--frac", type=float, default=0.05)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--depth-label", default="converged", choices=["converged", "truth"],
+                    help="label of the depth head: the run's converged depth or the true depth")
     ap.add_argument("--eval", action="store_true", help="compare plain and learned damping instead")
     ap.add_argument("--eval-seeds", default="1,2,3,4")
     ap.add_argument("--eval-large", action="store_true", help="also the 1000-keyframe problem")
@@ -464,18 +495,21 @@ def main(argv=None):
     for b0 in range(0, a.problems, a.batch_problems):
         seeds = range(a.seed0 + b0, a.seed0 + min(a.problems, b0 + a.batch_problems))
         probs = [synth.make_config1(s) for s in seeds]
-        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=b0))
+        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=b0,
+                              depth_label=a.depth_label))
     for i in range(a.large):
         parts.append(generate([synth.make_config2(a.seed0 + 5000 + i)], iters=a.iters, every=a.every,
-                              frac=a.frac, seed=5000 + i))
+                              frac=a.frac, seed=5000 + i, depth_label=a.depth_label))
     for b0 in range(0, a.depth_init, a.batch_problems):
         probs = [synth.reinit_at_depth(synth.make_config1(a.seed0 + 9000 + i))
                  for i in range(b0, min(a.depth_init, b0 + a.batch_problems))]
-        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=9000 + b0))
+        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=9000 + b0,
+                              depth_label=a.depth_label))
     for b0 in range(0, a.mixed, a.batch_problems):
         probs = [synth.make_config3_problem(p, base_seed=a.seed0 + 7000)
                  for p in range(b0, min(a.mixed, b0 + a.batch_problems))]
-        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=7000 + b0))
+        parts.append(generate(probs, iters=a.iters, every=a.every, frac=a.frac, seed=7000 + b0,
+                              depth_label=a.depth_label))
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
     M = np.concatenate([p[2] for p in parts])
@@ -484,6 +518,7 @@ def main(argv=None):
     meta = dict(problems=a.problems, seeds=[a.seed0, a.seed0 + a.problems - 1], iters=a.iters,
                 every=a.every, frac=a.frac, damping=0.4, generator="125 keyframes / 1919 landmarks random walk",
                 large_problems=a.large, mixed_problems=a.mixed, depth_init_problems=a.depth_init,
+                depth_label=a.depth_label,
                 label_mean_damping=float(Y[M[:, 0] > 0, 0].mean()), data_seconds=t_gen, **rep)
     save_weights(a.out, theta, meta)
     print(json.dumps(meta))
