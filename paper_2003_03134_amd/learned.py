@@ -41,7 +41,7 @@ import time
 
 import numpy as np
 
-from . import (GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA, GBP_FP32, GBPError, GBPSolver, MLP_FEATURES,
+from . import (GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA, GBP_FP32, GBP_FP64, GBPError, GBPSolver, MLP_FEATURES,
                MLP_PARAMS, MLPTrainer, bf16_bits)
 from ._capi import GBP_ENUMERIC
 
@@ -334,7 +334,7 @@ def time_to_target(problem, *, weights=None, every_k=5, damping=0.4, huber_k=2.0
 
 def incremental_run(stream, *, weights=None, use_depth=False, every_k=5, damping=0.4, huber_k=2.0,
                     iters_per_kf=20, depth_delay=5, target=1.0, fallback_rise=0.5, damp_mode=GBP_DAMP_ETA,
-                    trace=False):
+                    trace=False, precision=GBP_FP64):
     """The SLAM protocol of Section 9.2 on an incremental stream: start from
     the base problem, and for every later keyframe add it (initialised at
     the previous keyframe's current estimate) with its new landmarks and
@@ -342,11 +342,12 @@ def incremental_run(stream, *, weights=None, use_depth=False, every_k=5, damping
     learned depth head moves the new landmarks (and, in the first window,
     the base problem's) `depth_delay` iterations after they join. Returns per-addition iterations to the inlier target,
     final errors and the GPU wall time of the whole run (host work for the
-    additions included)."""
+    additions included). FP64 factor state by default: the beliefs of a long,
+    unconverged chain become too ill-conditioned for FP32 messages."""
     import torch
     full, base = stream.full, stream.base
     cap = (full.n_keyframes, full.n_landmarks, full.n_factors)
-    s = GBPSolver(base, precision=GBP_FP32, capacity=cap, damp_mode=damp_mode)
+    s = GBPSolver(base, precision=precision, capacity=cap, damp_mode=damp_mode, anneal=True)
     try:
         if weights is not None:
             s.set_damping_model(weights, every_k=every_k, fallback_rise=fallback_rise)
@@ -459,6 +460,9 @@ def main(argv=None):
                     help="125-keyframe problems with landmarks started at 1 m depth added to the data")
     ap.add_argument("--eval-incremental", type=int, default=0,
                     help="also the incremental run up to this many keyframes")
+    ap.add_argument("--incremental-precision", default="fp64", choices=["fp32", "fp64"],
+                    help="factor state of the incremental runs")
+    ap.add_argument("--incremental-seed", type=int, default=20000)
     ap.add_argument("--seed0", type=int, default=10000)
     ap.add_argument("--iters", type=int, default=300)
     ap.add_argument("--every", type=int, default=5)
@@ -478,12 +482,13 @@ def main(argv=None):
             out[f"random_walk_125kf_seed{sd}"] = compare(synth.make_config1(sd), w, undamped_too=True)
             print(json.dumps({f"seed{sd}": out[f"random_walk_125kf_seed{sd}"]}), flush=True)
         if a.eval_incremental:
+            prec = GBP_FP64 if a.incremental_precision == "fp64" else GBP_FP32
             for tag, init in (("landmarks_at_1m", 1.0), ("landmarks_noisy", None)):
-                st = synth.make_incremental_stream(seed=20000, n_kf=a.eval_incremental, init_depth=init)
-                res = {"plain": incremental_run(st),
-                       "plain_damp_both": incremental_run(st, damp_mode=GBP_DAMP_ETA_LAMBDA),
-                       "learned_damping": incremental_run(st, weights=w),
-                       "learned_damping_and_depth": incremental_run(st, weights=w, use_depth=True)}
+                st = synth.make_incremental_stream(seed=a.incremental_seed, n_kf=a.eval_incremental, init_depth=init)
+                res = {"plain": incremental_run(st, precision=prec),
+                       "plain_damp_both": incremental_run(st, damp_mode=GBP_DAMP_ETA_LAMBDA, precision=prec),
+                       "learned_damping": incremental_run(st, weights=w, precision=prec),
+                       "learned_damping_and_depth": incremental_run(st, weights=w, use_depth=True, precision=prec)}
                 out[f"incremental_{tag}"] = res
                 print(json.dumps({f"incremental_{tag}": res}), flush=True)
         if a.eval_large:

@@ -65,6 +65,35 @@ def test_mlp_infer_matches_bf16_oracle(gbp, n):
     assert np.all((d.cpu().numpy() >= 0) & (d.cpu().numpy() <= 0.9))
 
 
+@pytest.mark.parametrize("weights", ["random", "packaged"])
+def test_mlp_infer_within_bf16_bound_of_fp64_network(gbp, weights):
+    """The MFMA network against the plain FP64 network (no emulation of the
+    kernel's rounding): every row of both heads within the bound that BF16
+    storage and FP32 sums allow (`bf16_bound`, derived from the arithmetic);
+    4133 rows (129 tiles of 32 and a ragged tail of 5)."""
+    import torch
+    from tests.bf16_bound import forward_error_bound
+    from paper_2003_03134_amd import learned
+    if weights == "random":
+        theta = _theta(12)
+    else:
+        theta = learned.load_weights()[1].astype(np.float64)
+    theta = theta.astype(np.float32).astype(np.float64)   # the FP32 master
+    rng = np.random.default_rng(4133)
+    x = rng.normal(0, 1.5, (4133, 16)).astype(np.float32)
+    w = _dev(omlp.to_bf16_bits(theta).view(np.int16))
+    d, delta = gbp.mlp_infer(w, _dev(x))
+    torch.cuda.synchronize()
+    ref, _ = omlp.forward(theta, x.astype(np.float64))
+    bound = forward_error_bound(theta, x.astype(np.float64))
+    err = np.abs(np.stack([d.cpu().numpy(), delta.cpu().numpy()], axis=1) - ref)
+    ratio = err / bound
+    print(f"{weights}: max |d err| {err[:, 0].max():.2e} (bound median {np.median(bound[:, 0]):.1e}), "
+          f"max |delta err| {err[:, 1].max():.2e} (bound median {np.median(bound[:, 1]):.1e}), "
+          f"largest err / bound {ratio.max():.3f}, median {np.median(ratio):.3f}")
+    assert np.all(err <= bound), np.unravel_index(np.argmax(ratio), ratio.shape)
+
+
 def test_mlp_infer_empty_and_bad_arguments(gbp):
     import torch
     w = torch.zeros(gbp.MLP_PARAMS, dtype=torch.int16, device="cuda")

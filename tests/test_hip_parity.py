@@ -417,30 +417,52 @@ def test_incremental_growth_matches_oracle(gbp, precision):
 
 def test_long_incremental_stream_fp64_keeps_every_belief_positive_definite(gbp):
     """The 300-keyframe stream of Section 9.2 (one keyframe and 15 landmarks
-    at 1 m along the ray every 20 iterations): with FP64 factor state every
-    window ends with all beliefs positive definite, in both damping modes, as
-    in the FP64 oracle on the same stream (whose smallest belief information
-    eigenvalue falls to about 1e-3). The chain is far from converged at
-    20 iterations per keyframe (window-end errors of 10-50 px)."""
+    at 1 m along the ray every 20 iterations), seed 20000: with FP64 factor
+    state the GPU path follows the FP64 oracle (window-end means within 1e-6
+    relative at keyframes 10 and 20; measured 1e-13 to 2e-8 absolute) and,
+    like the oracle on this stream, ends every window with all beliefs
+    positive definite, in both damping modes. Past keyframe 20 the two
+    trajectories part: the chain is far from converged (window-end errors of
+    5-60 px) and its beliefs ill-conditioned (condition numbers up to 1e7),
+    so rounding differences grow about tenfold every window or two in either
+    damping mode. Positive definiteness is not a property of GBP on such
+    streams: the oracle itself loses it on seed 20004 (both parts damped,
+    keyframe 156)."""
+    import oracle
     st = synth.make_incremental_stream(seed=20000, n_kf=300, n0=5, new_lm_per_kf=15)
     full, base = st.full, st.base
     cap = (full.n_keyframes, full.n_landmarks, full.n_factors)
     base_ids = sorted(set(range(full.n_landmarks)) - set(np.concatenate([x["lm"] for x in st.steps]).tolist()))
     for dm in (gbp.GBP_DAMP_ETA, gbp.GBP_DAMP_ETA_LAMBDA):
         s = gbp.GBPSolver(base, precision=gbp.GBP_FP64, capacity=cap, damp_mode=dm, anneal=True)
+        o = oracle.Oracle(base, anneal=True, damp_lambda=dm == gbp.GBP_DAMP_ETA_LAMBDA)
         user_of = {int(j): i for i, j in enumerate(base_ids)}
         n_lm = base.n_landmarks
         s.iterate(20, 0.4, 2.0)
+        o.iterate(20, 0.4, 2.0)
         for step in st.steps:
             b = s.beliefs()   # raises on a failed belief
+            k = step["kf"]
+            if o is not None and k in (10, 20):
+                r = o.beliefs()
+                e = max(np.abs(b["kf_mu"] - r["kf_mu"]).max() / np.abs(r["kf_mu"]).max(),
+                        np.abs(b["lm_mu"] - r["lm_mu"]).max() / np.abs(r["lm_mu"]).max())
+                print(f"damp mode {dm}, keyframe {k}: largest relative mean error {e:.1e}", flush=True)
+                assert e < 1e-6, (dm, k, e)
+                if k == 20:
+                    o = None
             for j in step["lm"]:
                 user_of[int(j)] = n_lm
                 n_lm += 1
             fs = step["factors"]
             flm = np.array([user_of[int(j)] for j in full.factor_lm[fs]], dtype=np.int32)
-            s.add_keyframe(b["kf_mu"][step["kf"] - 1].copy(), full.lm_init[step["lm"]], full.factor_kf[fs],
+            s.add_keyframe(b["kf_mu"][k - 1].copy(), full.lm_init[step["lm"]], full.factor_kf[fs],
                            flm, full.z[fs])
             s.iterate(20, 0.4, 2.0)
+            if o is not None:
+                o.add(o.beliefs()["kf_mu"][k - 1].copy(), full.lm_init[step["lm"]], full.factor_kf[fs], flm,
+                      full.z[fs])
+                o.iterate(20, 0.4, 2.0)
         b = s.beliefs(info=True)
         assert np.linalg.eigvalsh(b["kf_lam"]).min() > 0 and np.linalg.eigvalsh(b["lm_lam"]).min() > 0
         assert s.sizes[0] == 300

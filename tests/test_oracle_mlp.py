@@ -91,3 +91,22 @@ def test_adam_first_step_is_signed_learning_rate():
     for k in range(1, 6):
         th, m, v = mlp.adam_step(th, m, v, np.full(4, 2.0), k, 0.1)
     assert np.allclose(th, -0.5, rtol=1e-6)
+
+
+def test_bf16_error_bound_covers_the_storage_rounding_and_is_not_vacuous():
+    """The bound the GPU inference is held to (`bf16_bound`): the emulated
+    BF16 forward (a realisation of the same roundings, in FP64) stays inside
+    it on every row, and a bound built for a rounding 8x finer fails, so it
+    is not loose by more than that factor."""
+    from tests.bf16_bound import U_BF16, forward_error_bound
+    rng = np.random.default_rng(21)
+    for seed in (3, 4):
+        theta = mlp.init_params(seed)
+        p = mlp.unpack(theta)
+        for b in ("b1", "b2", "b3"):
+            p[b][:] = rng.normal(0, 0.3, p[b].shape)
+        theta = mlp.pack(p).astype(np.float32).astype(np.float64)
+        x = rng.normal(0, 1.5, (600, mlp.N_IN)).astype(np.float32).astype(np.float64)
+        err = np.abs(mlp.forward_bf16(theta, x) - mlp.forward(theta, x)[0])
+        assert np.all(err <= forward_error_bound(theta, x))
+        assert np.any(err > forward_error_bound(theta, x, u=U_BF16 / 8))
