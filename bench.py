@@ -69,13 +69,13 @@ BELIEF_KF_BYTES = 27 * 8 + 6 * 8 + 8 + 4 + 6 * 8 + 27 * 8 + 12 * 8              
 BELIEF_EDGE_BYTES, BELIEF_LM_BYTES = 4 + 8 * 4 + 5 * 4, 4 + 4 + 3 * 8 + 9 * 8
 # k_reproj_block with the fused check (per factor: keyframe and landmark
 # index 2 x 4 B, measurement 2 x 8 B, flags and counter 2 x 1 B, with a
-# reference: mask 1 B and reference pixels 2 x 8 B; for factors old enough
+# reference: mask 1 B and reference pixels 2 x 4 B; for factors old enough
 # to be checked, the linearisation point 9 x 4 B; per due factor its queue
 # entry 16 B; gathered once per variable: a keyframe's absolute pose and mean
 # offset (12 + 6 doubles), a landmark's mean offset and anchor (6 doubles);
 # per residual block: bounds, problem, parameters and its 8 partial sums.
 REPROJ_BYTES_PER_FACTOR = 2 * 4 + 2 * 8 + 2
-REPROJ_REF_BYTES = 1 + 2 * 8
+REPROJ_REF_BYTES = 1 + 2 * 4
 REPROJ_CHECK_BYTES = 9 * 4
 REPROJ_KF_BYTES, REPROJ_LM_BYTES, REPROJ_BLOCK_BYTES = 18 * 8, 6 * 8, 8 + 4 + 64 + 64
 

@@ -38,9 +38,12 @@ typedef enum {
     GBP_ESTATE = -5    /* call not valid in the problem's current state   */
 } gbp_status;
 
-/* Storage precision of per-factor state and messages. Beliefs (covariance
- * and mean offsets), belief sums and the 6x6 / 3x3 solves are FP64 in both
- * modes; the per-factor 2x2 marginalisation arithmetic is FP64 as well. */
+/* Storage precision of per-factor state and messages, and of the stored
+ * reference pixels of gbp_set_reference (passed in FP64; in FP32 their
+ * rounding is below 1e-4 px for pixels under 2048). Measurements are kept
+ * in FP64. Beliefs (covariance and mean offsets), belief sums and the
+ * 6x6 / 3x3 solves are FP64 in both modes; the per-factor 2x2
+ * marginalisation arithmetic is FP64 as well. */
 enum { GBP_FP64 = 0, GBP_FP32 = 1 };
 
 /* Message damping (Section 5, last paragraph): the paper damps the eta

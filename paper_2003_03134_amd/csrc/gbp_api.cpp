@@ -69,7 +69,7 @@ struct gbp_problem {
     Dev<double> dd{};
     int *d_count = nullptr;
     unsigned long long *d_total = nullptr;
-    double *d_zref = nullptr;
+    void *d_zref = nullptr;   // reference pixels in the factor-state precision
     uint8_t *d_mask = nullptr;
     bool has_ref = false;
     int *d_perm = nullptr;
@@ -601,7 +601,7 @@ template <typename TS>
 gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_base) {
     Dev<TS> &d = dev<TS>(p);
     hipStream_t s = p->stream;
-    const double *zref = p->has_ref ? p->d_zref : nullptr;
+    const TS *zref = p->has_ref ? (const TS *)p->d_zref : nullptr;
     const uint8_t *mask = p->has_ref ? p->d_mask : nullptr;
     auto model_at = [&](int i) { return p->learned && (p->t + i) % p->every_k == 0; };
     // A logged iteration followed by another (with no model evaluation in
@@ -695,7 +695,7 @@ gbp_status phase_times_impl(gbp_problem *p, int n, double damping, double huber_
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 3], s));
         launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 4], s));
-        launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? p->d_zref : nullptr,
+        launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? (const TS *)p->d_zref : nullptr,
                           p->has_ref ? p->d_mask : nullptr, nullptr, s);
         HIP_TRY(p, hipEventRecord(ev[NPH * i + 5], s));
     }
@@ -1335,7 +1335,8 @@ gbp_status beliefs_impl(gbp_problem *p, double *kf_mean, double *lm_mean, double
 template <typename TS>
 gbp_status reproj_impl(gbp_problem *p, std::vector<double> &sums) {
     Dev<TS> &d = dev<TS>(p);
-    launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? p->d_zref : nullptr, p->has_ref ? p->d_mask : nullptr, nullptr,
+    launch_reproj<TS>(d, p->iopt, p->huber_k, p->has_ref ? (const TS *)p->d_zref : nullptr,
+                      p->has_ref ? p->d_mask : nullptr, nullptr,
                       p->stream);
     HIP_TRY(p, hipGetLastError());
     sums.resize((size_t)p->np * 8);
@@ -1498,7 +1499,14 @@ gbp_status gbp_set_reference(gbp_problem *p, const double *z_ref, const uint8_t 
         zr[2 * (size_t)f + 1] = z_ref[2 * (size_t)u + 1];
         mk[f] = mask[u] ? 1 : 0;
     }
-    HIP_TRY(p, hipMemcpyAsync(p->d_zref, zr.data(), zr.size() * 8, hipMemcpyHostToDevice, p->stream));
+    // in the factor-state precision (used for statistics only: in FP32 the
+    // rounding is below 1e-4 px for pixels under 2048)
+    std::vector<float> zf;
+    if (p->precision == GBP_FP32) zf.assign(zr.begin(), zr.end());
+    if (p->precision == GBP_FP32)
+        HIP_TRY(p, hipMemcpyAsync(p->d_zref, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, p->stream));
+    else
+        HIP_TRY(p, hipMemcpyAsync(p->d_zref, zr.data(), zr.size() * 8, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(p, hipMemcpyAsync(p->d_mask, mk.data(), mk.size(), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     if (!p->has_ref) destroy_graphs(p);

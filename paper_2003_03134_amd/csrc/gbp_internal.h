@@ -155,12 +155,12 @@ template <typename TS> void launch_belief_lm(const Dev<TS> &d, const IterOpts &o
                                              bool with_kf = false);
 template <typename TS> void launch_belief_kf(const Dev<TS> &d, const IterOpts &o, int readout, int block, hipStream_t s);
 template <typename TS> void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s);
-template <typename TS> void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref,
+template <typename TS> void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const TS *zref,
                                           const uint8_t *mask, double *log_row, hipStream_t s);
 // residual partials of every block plus the next iteration's check (the
 // statistics are reduced by the next launch_relin)
 template <typename TS> void launch_reproj_check(const Dev<TS> &d, const IterOpts &o, double huber_k,
-                                                const double *zref, const uint8_t *mask, hipStream_t s);
+                                                const TS *zref, const uint8_t *mask, hipStream_t s);
 template <typename TS> void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf,
                                                    void *scratch, float *fdamp, float *hist, hipStream_t s);
 template <typename TS> void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist,

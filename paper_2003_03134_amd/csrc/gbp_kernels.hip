@@ -1682,7 +1682,7 @@ __global__ __launch_bounds__(256) void k_flag_relin(Dev<TS> d, double beta, int 
 // iteration needs no separate check.
 template <typename TS, bool CHECK>
 __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o, double huber_k,
-                                                           const double *zref, const uint8_t *mask) {
+                                                           const TS *zref, const uint8_t *mask) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int f0 = d.rblk_start[b], f1 = d.rblk_start[b + 1];
     const ProbParams pp = d.prob[d.rblk_prob[b]];
@@ -1709,8 +1709,8 @@ __global__ __launch_bounds__(RTHREADS) void k_reproj_block(Dev<TS> d, IterOpts o
             const uint32_t want_ref = (zref ? mask : d.flags)[f];
             double zr0 = 0.0, zr1 = 0.0;
             if (zref) {
-                zr0 = zref[2 * (size_t)f];
-                zr1 = zref[2 * (size_t)f + 1];
+                zr0 = (double)zref[2 * (size_t)f];
+                zr1 = (double)zref[2 * (size_t)f + 1];
             }
             uint8_t fl = 0;
             int cf = 0;
@@ -1969,7 +1969,7 @@ void launch_flag_relin(const Dev<TS> &d, double beta, int *count, hipStream_t s)
 }
 
 template <typename TS>
-void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref, const uint8_t *mask,
+void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const TS *zref, const uint8_t *mask,
                    double *log_row, hipStream_t s) {
     if (d.n_rblk > 0)
         hipLaunchKernelGGL((k_reproj_block<TS, false>), dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o, huber_k, zref,
@@ -1979,7 +1979,7 @@ void launch_reproj(const Dev<TS> &d, const IterOpts &o, double huber_k, const do
 }
 
 template <typename TS>
-void launch_reproj_check(const Dev<TS> &d, const IterOpts &o, double huber_k, const double *zref,
+void launch_reproj_check(const Dev<TS> &d, const IterOpts &o, double huber_k, const TS *zref,
                          const uint8_t *mask, hipStream_t s) {
     if (d.n_rblk > 0)
         hipLaunchKernelGGL((k_reproj_block<TS, true>), dim3(d.n_rblk), dim3(RTHREADS), 0, s, d, o, huber_k, zref,
@@ -2067,9 +2067,9 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
     template void launch_belief_lm<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t, bool);            \
     template void launch_belief_kf<TS>(const Dev<TS> &, const IterOpts &, int, int, hipStream_t);                  \
     template void launch_flag_relin<TS>(const Dev<TS> &, double, int *, hipStream_t);                              \
-    template void launch_reproj<TS>(const Dev<TS> &, const IterOpts &, double, const double *, const uint8_t *,    \
+    template void launch_reproj<TS>(const Dev<TS> &, const IterOpts &, double, const TS *, const uint8_t *,        \
                                     double *, hipStream_t);                                                       \
-    template void launch_reproj_check<TS>(const Dev<TS> &, const IterOpts &, double, const double *,               \
+    template void launch_reproj_check<TS>(const Dev<TS> &, const IterOpts &, double, const TS *,                   \
                                           const uint8_t *, hipStream_t);                                          \
     template void launch_permute_factors<TS>(const Dev<TS> &, const int *, int, void *, float *, float *,         \
                                              hipStream_t);              \

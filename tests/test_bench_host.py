@@ -37,11 +37,11 @@ def test_step_bytes_of_the_other_launches():
     # landmark beliefs: 56 B per edge, 104 B per landmark, 636 B per keyframe
     assert sb(1, 0, 0, 0, 0, 0, False)["k_belief_lm"] == 56
     assert sb(0, 1, 1, 0, 0, 0, False)["k_belief_lm"] == 636 + 104
-    # residuals and check: 26 B per factor (43 B with a reference), 36 B per
-    # checked factor, 16 B per queued factor, 144 / 48 B per keyframe /
-    # landmark, 140 B per residual block
+    # residuals and check: 26 B per factor (35 B with a reference in FP32),
+    # 36 B per checked factor, 16 B per queued factor, 144 / 48 B per
+    # keyframe / landmark, 140 B per residual block
     assert sb(1, 0, 0, 0, 0, 0, False)["k_reproj_block"] == 26
-    assert sb(1, 0, 0, 0, 0, 0, True)["k_reproj_block"] == 43
+    assert sb(1, 0, 0, 0, 0, 0, True)["k_reproj_block"] == 35
     assert sb(1, 0, 0, 0, 1, 0, False)["k_reproj_block"] == 26 + 36
     assert sb(0, 1, 1, 0, 0, 1, False)["k_reproj_block"] == 144 + 48 + 140
 
