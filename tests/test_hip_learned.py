@@ -538,7 +538,9 @@ def test_packaged_model_keeps_the_fixed_point_and_reaches_target_sooner(gbp):
     equal plain GBP's within 1e-3 px (information and vector damped
     together, where both runs converge); and under the paper's damping of
     the information vector alone the learned run reaches the inlier target
-    of 1 px no later than plain GBP."""
+    of 1 px in fewer iterations and less GPU time (HIP events over exactly
+    the iterations to the target) than plain GBP with that damping (11
+    against 29 iterations; 0.33 against 0.84 ms measured)."""
     from paper_2003_03134_amd import learned
     w, _, _ = learned.load_weights()
     prob = synth.make_config1(1)
@@ -551,8 +553,9 @@ def test_packaged_model_keeps_the_fixed_point_and_reaches_target_sooner(gbp):
     assert lrn["fallback"] == 0
     p_eta = learned.time_to_target(prob, weights=None)
     l_eta = learned.time_to_target(prob, weights=w)
-    print("iterations to 1 px:", p_eta["iterations"], l_eta["iterations"])
-    assert l_eta["iterations"] is not None and l_eta["iterations"] <= p_eta["iterations"]
+    print("iterations to 1 px:", p_eta["iterations"], l_eta["iterations"], "ms:", p_eta["ms"], l_eta["ms"])
+    assert l_eta["iterations"] is not None and l_eta["iterations"] < p_eta["iterations"]
+    assert l_eta["ms"] < p_eta["ms"]
 
 
 def test_learned_form_against_the_best_plain_variant_on_a_large_graph(gbp):
