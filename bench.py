@@ -459,7 +459,7 @@ def main():
                             os.path.join(ROOT, "paper_2003_03134_amd", "tuning", "autotune_cache.txt"))
     log(f"autotuned: keyframe kernel {tuned[0]} lanes/workgroup, landmark kernel {tuned[1]} "
         f"lanes/workgroup, {tuned[2]} lanes per landmark, {tuned[3]} relinearisation queue segments "
-        f"per workgroup")
+        f"per workgroup, keyframe solves {'in the landmark launch' if tuned[4] else 'in their own launch'}")
 
     K, W = args.steps, args.warmup
     c = max(1, min(args.chunk, K))
@@ -591,7 +591,8 @@ def main():
                    "step": "relinearisation check + factor messages + beliefs + per-problem reprojection error",
                    "damping": 0.4, "huber_k_px": 2.0, "parallelism": "single GPU",
                    "autotuned": {"keyframe_kernel_block": tuned[0], "landmark_kernel_block": tuned[1],
-                                 "lanes_per_landmark": tuned[2], "relin_segments_per_workgroup": tuned[3]}},
+                                 "lanes_per_landmark": tuned[2], "relin_segments_per_workgroup": tuned[3],
+                                 "keyframe_solves_in_landmark_launch": bool(tuned[4])}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -412,17 +412,20 @@ gbp_status gbp_counters(gbp_problem *p, int64_t *relinearisations);
 
 /* Autotuner: picks the workgroup sizes of the keyframe factor kernel and of
  * the landmark belief kernel (64/128/256 each, with 4 lanes per landmark),
- * then the lanes per landmark (2/4/8), by timing n_iters iterations of every
- * candidate with HIP events on this problem, then the relinearisation queue
- * segments per workgroup (1/2/4) by timing n_iters relinearisation launches
- * on a synthetic queue holding every 11th factor (about the share due per
- * iteration at steady state); the device state is restored after each
- * candidate (the problem's results are unchanged). The choice is cached in
- * the text file cache_path (may be NULL: no cache), keyed by GPU
+ * then the lanes per landmark (2/4/8), then whether the keyframe solves run
+ * in the first workgroups of the landmark-belief launch or in a launch of
+ * their own (same arithmetic, bit for bit), by timing n_iters iterations of
+ * every candidate with HIP events on this problem, then the relinearisation
+ * queue segments per workgroup (1/2/4) by timing n_iters relinearisation
+ * launches on a synthetic queue holding every 11th factor (about the share
+ * due per iteration at steady state); the device state is restored after
+ * each candidate (the problem's results are unchanged). The choice is
+ * cached in the text file cache_path (may be NULL: no cache), keyed by GPU
  * architecture, precision and size bucket; a cached entry is used without
- * timing. chosen[4] (may be NULL) receives the two sizes, the lane count and
- * the segment count. Allocates a temporary copy of the workspace.
- * Synchronises. */
+ * timing (entries of an older format are ignored). chosen[5] (may be NULL)
+ * receives the two sizes, the lane count, the segment count and the
+ * keyframe-solve placement (1: inside the landmark-belief launch). Allocates
+ * a temporary copy of the workspace. Synchronises. */
 gbp_status gbp_autotune(gbp_problem *p, int32_t n_iters, const char *cache_path,
                         int32_t *chosen);
 

@@ -204,13 +204,15 @@ class GBPSolver:
                     k_factor_kf=ms[5])
 
     def autotune(self, n_iters: int = 5, cache_path: str | None = None) -> tuple:
-        """Pick workgroup sizes, lanes per landmark and relinearisation
-        segments per workgroup by timing (state restored); returns (kf block,
-        lm block, lanes per landmark, relinearisation segments)."""
-        chosen = (C.c_int32 * 4)()
+        """Pick workgroup sizes, lanes per landmark, where the keyframe
+        solves run and relinearisation segments per workgroup by timing
+        (state restored); returns (kf block, lm block, lanes per landmark,
+        relinearisation segments, keyframe solves fused into the landmark
+        launch: 1 or 0)."""
+        chosen = (C.c_int32 * 5)()
         path = cache_path.encode() if cache_path else None
         self._check(self._lib.gbp_autotune(self.h, int(n_iters), path, chosen), self.h)
-        return chosen[0], chosen[1], chosen[2], chosen[3]
+        return tuple(int(v) for v in chosen)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -82,6 +82,9 @@ struct gbp_problem {
     std::vector<GraphEntry> graphs;
     bool use_graph = true;
     int blk_lm = 256, blk_kf = 128;
+    // keyframe solves in the first workgroups of the landmark-belief launch
+    // (1) or in a launch of their own after the keyframe kernel (0): tuned
+    int kf_fused = 1;
     // learned damping (one allocation, made on first use)
     float *fdamp_buf = nullptr;    // per-factor damping, in the workspace
     void *learn_mem = nullptr;
@@ -617,8 +620,8 @@ gbp_status record_iterations(gbp_problem *p, int n, int log_every, double *log_b
         launch_relin<TS>(d, p->iopt, s, pending_row);
         checked = false;
         pending_row = nullptr;
-        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, false);
-        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, true);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, !p->kf_fused);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, p->kf_fused != 0);
         if (log_every > 0 && (i + 1) % log_every == 0) {
             double *row = log_base + (size_t)((i + 1) / log_every - 1) * p->np * GBP_LOG_COLS;
             if (i + 1 < n && !model_at(i + 1)) {
@@ -730,8 +733,8 @@ gbp_status time_config(gbp_problem *p, int n, double *ms) {
     for (int i = 0; i < n; ++i) {
         launch_check<TS>(d, p->iopt, s);
         launch_relin<TS>(d, p->iopt, s);
-        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, false);
-        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, true);
+        launch_factor_kf<TS>(d, p->iopt, p->blk_kf, s, nullptr, nullptr, !p->kf_fused);
+        launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s, p->kf_fused != 0);
     }
     HIP_TRY(p, hipEventRecord(b, s));
     HIP_TRY(p, hipGetLastError());
@@ -760,28 +763,43 @@ std::string tune_key(gbp_problem *p) {
 // tiny cache: one line per key, "key kf_block lm_block lm_lanes ms"
 // cache line: key, keyframe-kernel size, landmark-kernel size, lanes per
 // landmark, relinearisation segments per workgroup, iteration ms
-bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll, int &rg) {
+// a whole token as a decimal integer (no trailing characters)
+static bool parse_int(const std::string &t, int &v) {
+    if (t.empty()) return false;
+    char *end = nullptr;
+    const long x = std::strtol(t.c_str(), &end, 10);
+    if (*end != '\0' || x < INT32_MIN || x > INT32_MAX) return false;
+    v = (int)x;
+    return true;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll, int &rg, int &fu) {
     if (!path) return false;
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
         std::istringstream is(line);
-        std::string k2;
-        int a = 0, b = 0, c = 0, e = 0;
-        double ms = 0;
-        // entries of an older format (no segment count) do not match
-        if ((is >> k2 >> a >> b >> c >> e >> ms) && k2 == key && e >= 1 && e <= 16 && (c == 2 || c == 4 || c == 8)) {
-            kb = a; lb = b; ll = c; rg = e;
+        std::vector<std::string> tok;
+        for (std::string t; is >> t;) tok.push_back(t);
+        // key, five integers, the time: entries of an older format (fewer
+        // fields) do not match
+        int a = 0, b = 0, c = 0, e = 0, g = -1;
+        if (tok.size() != 7 || tok[0] != key || !parse_int(tok[1], a) || !parse_int(tok[2], b) ||
+            !parse_int(tok[3], c) || !parse_int(tok[4], e) || !parse_int(tok[5], g))
+            continue;
+        if (e >= 1 && e <= 16 && (c == 2 || c == 4 || c == 8) && (g == 0 || g == 1) &&
+            (a == 64 || a == 128 || a == 256) && (b == 64 || b == 128 || b == 256)) {
+            kb = a; lb = b; ll = c; rg = e; fu = g;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char *path, const std::string &key, int kb, int lb, int ll, int rg, double ms) {
+void cache_store(const char *path, const std::string &key, int kb, int lb, int ll, int rg, int fu, double ms) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << kb << " " << lb << " " << ll << " " << rg << " " << ms << "\n";
+    out << key << " " << kb << " " << lb << " " << ll << " " << rg << " " << fu << " " << ms << "\n";
 }
 
 // n launches of the relinearisation kernel on a synthetic queue (every 11th
@@ -811,20 +829,22 @@ gbp_status time_relin(gbp_problem *p, int n, double *ms) {
 
 // Autotuner: the workgroup sizes of the keyframe kernel and of the landmark
 // belief kernel (3 x 3, with 4 lanes per landmark), then the lanes per
-// landmark (2 / 4 / 8) with the chosen sizes, then the queue segments per
-// relinearisation workgroup (1 / 2 / 4) on a synthetic steady-state queue;
-// each candidate runs n iterations (or relinearisation launches) from a
-// snapshot of the workspace, which is restored after it.
+// landmark (2 / 4 / 8) with the chosen sizes, then whether the keyframe
+// solves run inside the landmark-belief launch or in their own, then the
+// queue segments per relinearisation workgroup (1 / 2 / 4) on a synthetic
+// steady-state queue; each candidate runs n iterations (or relinearisation
+// launches) from a snapshot of the workspace, which is restored after it.
 template <typename TS>
 gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t *chosen) {
     Dev<TS> &d = dev<TS>(p);
     const std::string key = tune_key(p);
-    int kb = 0, lb = 0, ll = 0, rg = 0;
-    if (cache_lookup(cache_path, key, kb, lb, ll, rg)) {
+    int kb = 0, lb = 0, ll = 0, rg = 0, fu = 1;
+    if (cache_lookup(cache_path, key, kb, lb, ll, rg, fu)) {
         p->blk_kf = kb;
         p->blk_lm = lb;
         d.lm_lanes = ll;
         d.relin_group = rg;
+        p->kf_fused = fu;
     } else {
         void *snap = nullptr, *psnap = nullptr;
         HIP_TRY(p, hipMalloc(&snap, p->ws_bytes));
@@ -834,27 +854,30 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
             HIP_TRY(p, hipMemcpyAsync(psnap, p->pair_mem, p->pair_state_bytes, hipMemcpyDeviceToDevice, p->stream));
         }
         double best = 1e30;
-        int bk = p->blk_kf, bl = p->blk_lm, bll = 4;
-        auto trial = [&](int x, int y, int z) -> gbp_status {
+        int bk = p->blk_kf, bl = p->blk_lm, bll = 4, bfu = 1;
+        auto trial = [&](int x, int y, int z, int f) -> gbp_status {
             p->blk_kf = x;
             p->blk_lm = y;
             d.lm_lanes = z;
+            p->kf_fused = f;
             double ms = 0;
             gbp_status st = time_config<TS>(p, n, &ms);
             if (st != GBP_OK) return st;
             HIP_TRY(p, hipMemcpyAsync(p->ws, snap, p->ws_bytes, hipMemcpyDeviceToDevice, p->stream));
             if (psnap)
                 HIP_TRY(p, hipMemcpyAsync(p->pair_mem, psnap, p->pair_state_bytes, hipMemcpyDeviceToDevice, p->stream));
-            if (ms < best) { best = ms; bk = x; bl = y; bll = z; }
+            if (ms < best) { best = ms; bk = x; bl = y; bll = z; bfu = f; }
             return GBP_OK;
         };
         gbp_status st = GBP_OK;
         for (int x : {64, 128, 256})
             for (int y : {64, 128, 256})
-                if (st == GBP_OK) st = trial(x, y, 4);
+                if (st == GBP_OK) st = trial(x, y, 4, 1);
         const int bk0 = bk, bl0 = bl;
         for (int z : {2, 8})
-            if (st == GBP_OK) st = trial(bk0, bl0, z);
+            if (st == GBP_OK) st = trial(bk0, bl0, z, 1);
+        if (st == GBP_OK) st = trial(bk, bl, bll, 0);
+        p->kf_fused = bfu;
         double best_r = 1e30;
         int brg = d.relin_group;
         for (int g : {1, 2, 4}) {
@@ -876,11 +899,13 @@ gbp_status autotune_impl(gbp_problem *p, int n, const char *cache_path, int32_t 
         p->blk_lm = bl;
         d.lm_lanes = bll;
         d.relin_group = brg;
-        cache_store(cache_path, key, bk, bl, bll, brg, best);
+        p->kf_fused = bfu;
+        cache_store(cache_path, key, bk, bl, bll, brg, bfu, best);
     }
     destroy_graphs(p);
     if (chosen) {
         chosen[0] = p->blk_kf; chosen[1] = p->blk_lm; chosen[2] = d.lm_lanes; chosen[3] = d.relin_group;
+        chosen[4] = p->kf_fused;
     }
     return GBP_OK;
 }

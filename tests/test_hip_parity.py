@@ -293,15 +293,17 @@ def test_autotune_leaves_state_unchanged(gbp, tmp_path):
     s.iterate(15, 0.4, 2.0)
     before = s.beliefs()          # stored beliefs (no recomputation)
     cache = str(tmp_path / "tune.txt")
-    kb, lb, ll, rg = s.autotune(3, cache)
+    kb, lb, ll, rg, fu = s.autotune(3, cache)
     assert kb in (64, 128, 256) and lb in (64, 128, 256) and ll in (2, 4, 8) and rg in (1, 2, 4)
+    assert fu in (0, 1)
     after = s.beliefs()
     for key in before:            # the device state was restored exactly
         assert np.array_equal(before[key], after[key]), key
     # a second problem of the same size bucket takes the cached choice
     s2 = gbp.GBPSolver(prob)
-    assert s2.autotune(3, cache) == (kb, lb, ll, rg)
-    assert open(cache).read().count("\n") == 1
+    assert s2.autotune(3, cache) == (kb, lb, ll, rg, fu)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and len(lines[0].split()) == 7
     o = oracle.Oracle(prob, anneal=True)
     o.iterate(15, 0.4, 2.0)
     s.iterate(20, 0.4, 2.0)
@@ -326,8 +328,8 @@ def test_every_landmark_lane_count_matches_oracle(gbp, lanes, tmp_path):
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     key = (f"{arch}/p{gbp.GBP_FP64}/f{key_bucket(nf)}/k{key_bucket(prob.n_keyframes)}"
            f"/l{key_bucket(prob.n_landmarks)}")
-    cache.write_text(f"{key} 64 64 {lanes} 2 0.0\n")
-    assert s.autotune(2, str(cache)) == (64, 64, lanes, 2)
+    cache.write_text(f"{key} 64 64 {lanes} 2 1 0.0\n")
+    assert s.autotune(2, str(cache)) == (64, 64, lanes, 2, 1)
     o = oracle.Oracle(prob, anneal=False)
     for _ in range(4):
         s.iterate(10, 0.4, 2.0)
@@ -351,8 +353,8 @@ def test_every_relin_grouping_matches_oracle(gbp, group, tmp_path):
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     nk, nl, nf = (sum(getattr(p, a) for p in probs) for a in ("n_keyframes", "n_landmarks", "n_factors"))
     cache = tmp_path / "tune.txt"
-    cache.write_text(f"{arch}/p{gbp.GBP_FP64}/f{lg(nf)}/k{lg(nk)}/l{lg(nl)} 64 64 4 {group} 0.0\n")
-    assert s.autotune(2, str(cache)) == (64, 64, 4, group)
+    cache.write_text(f"{arch}/p{gbp.GBP_FP64}/f{lg(nf)}/k{lg(nk)}/l{lg(nl)} 64 64 4 {group} 1 0.0\n")
+    assert s.autotune(2, str(cache)) == (64, 64, 4, group, 1)
     s.iterate(60, 0.4, 2.0)
     g = s.beliefs()
     kf_off = np.concatenate([[0], np.cumsum([p.n_keyframes for p in probs])])
@@ -364,6 +366,41 @@ def test_every_relin_grouping_matches_oracle(gbp, group, tmp_path):
         e = max(rel_mean_err(g["kf_mu"][kf_off[i]:kf_off[i + 1]], r["kf_mu"]),
                 rel_mean_err(g["lm_mu"][lm_off[i]:lm_off[i + 1]], r["lm_mu"]))
         assert e < 1e-8, (group, i, e)
+    s.close()
+
+
+def test_keyframe_solves_fused_or_apart_give_identical_results(gbp, tmp_path):
+    """The tuned switch between keyframe solves inside the landmark-belief
+    launch and in a launch of their own (forced through tuning-cache
+    entries): the same arithmetic either way, so the beliefs, the error log
+    and the relinearisation count agree bit for bit over 40 logged
+    iterations under the beta rule; an entry of the older six-field format
+    is not used (the problem is tuned again and a new entry appended)."""
+    import torch
+    prob = synth.make_config1(2)
+    lg = lambda v: max(0, int(np.floor(np.log2(v)))) if v > 1 else 0  # noqa: E731
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/p{gbp.GBP_FP32}/f{lg(prob.n_factors)}/k{lg(prob.n_keyframes)}/l{lg(prob.n_landmarks)}"
+    out = {}
+    for fused in (1, 0):
+        cache = tmp_path / f"tune{fused}.txt"
+        cache.write_text(f"{key} 128 256 4 2 {fused} 0.0\n")
+        s = gbp.GBPSolver(prob, precision=gbp.GBP_FP32, anneal=True)
+        s.set_reference(prob.z_true, prob.inlier)
+        assert s.autotune(2, str(cache)) == (128, 256, 4, 2, fused)
+        log = s.iterate_logged(40, 0.4, 2.0, log_every=1)
+        out[fused] = (s.beliefs(), log, s.last_relinearised)
+        s.close()
+    for k in out[1][0]:
+        assert np.array_equal(out[1][0][k], out[0][0][k]), k
+    assert np.array_equal(out[1][1], out[0][1])
+    assert out[1][2] == out[0][2]
+    old = tmp_path / "old.txt"
+    old.write_text(f"{key} 128 256 4 2 0.0\n")
+    s = gbp.GBPSolver(prob, precision=gbp.GBP_FP32)
+    s.autotune(2, str(old))
+    lines = old.read_text().splitlines()
+    assert len(lines) == 2 and len(lines[1].split()) == 7
     s.close()
 
 
