@@ -760,9 +760,6 @@ std::string tune_key(gbp_problem *p) {
     return os.str();
 }
 
-// tiny cache: one line per key, "key kf_block lm_block lm_lanes ms"
-// cache line: key, keyframe-kernel size, landmark-kernel size, lanes per
-// landmark, relinearisation segments per workgroup, iteration ms
 // a whole token as a decimal integer (no trailing characters)
 static bool parse_int(const std::string &t, int &v) {
     if (t.empty()) return false;
@@ -773,6 +770,10 @@ static bool parse_int(const std::string &t, int &v) {
     return true;
 }
 
+// Tuning cache, a text file of one line per key: key, keyframe-kernel
+// size, landmark-kernel size, lanes per landmark, relinearisation segments
+// per workgroup, keyframe solves in the landmark launch (1) or apart (0),
+// iteration ms.
 bool cache_lookup(const char *path, const std::string &key, int &kb, int &lb, int &ll, int &rg, int &fu) {
     if (!path) return false;
     std::ifstream in(path);
