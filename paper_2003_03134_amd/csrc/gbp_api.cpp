@@ -596,8 +596,8 @@ void record_model(gbp_problem *p, hipStream_t s, bool stats_fresh) {
     // residual pass left them in are_out at the same beliefs, else compute
     if (!stats_fresh) launch_reproj<TS>(d, p->iopt, p->huber_k, nullptr, nullptr, nullptr, s);
     launch_monitor(d.are_out, p->np, p->fb_rise, p->d_best, p->d_fallback, d.pstatus, p->d_judge, s);
-    launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
-    launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
+    launch_features_bf16<TS>(d, p->iopt, (uint16_t *)p->d_feat, p->d_hist, p->huber_k, s);
+    launch_mlp_infer_bf16((const uint16_t *)p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
 }
 
 template <typename TS>
@@ -1117,8 +1117,8 @@ gbp_status depth_impl(gbp_problem *p, const std::vector<int> &lms) {
         HIP_TRY(p, hipMemcpyAsync(p->d_lms, lms.data(), lms.size() * 4, hipMemcpyHostToDevice, s));
     if (!fl.empty())
         HIP_TRY(p, hipMemcpyAsync(p->d_perm, fl.data(), fl.size() * 4, hipMemcpyHostToDevice, s));
-    launch_features<TS>(d, p->iopt, p->d_feat, p->d_hist, p->huber_k, s);
-    launch_mlp_infer(p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
+    launch_features_bf16<TS>(d, p->iopt, (uint16_t *)p->d_feat, p->d_hist, p->huber_k, s);
+    launch_mlp_infer_bf16((const uint16_t *)p->d_feat, d.nf, p->d_w, d.fdamp, p->d_delta, s);
     launch_depth_move<TS>(d, p->d_lms, (int)lms.size(), p->d_delta, s);
     launch_linearise<TS>(d, 0, (int)fl.size(), p->huber_k, p->d_perm, s);
     launch_belief_lm<TS>(d, p->iopt, 0, p->blk_lm, s);

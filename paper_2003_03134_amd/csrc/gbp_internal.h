@@ -165,6 +165,9 @@ template <typename TS> void launch_permute_factors(const Dev<TS> &d, const int *
                                                    void *scratch, float *fdamp, float *hist, hipStream_t s);
 template <typename TS> void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist,
                                             double huber_k, hipStream_t s);
+// the same features as BF16 bits, for the network inside the iteration
+template <typename TS> void launch_features_bf16(const Dev<TS> &d, const IterOpts &o, uint16_t *feat, float *hist,
+                                                 double huber_k, hipStream_t s);
 template <typename TS> void launch_export_messages(const Dev<TS> &d, const int *idx, const int *u2i, int n, float *out,
                                                    hipStream_t s);
 void launch_fill_f32(float *p, float v, int n, hipStream_t s);

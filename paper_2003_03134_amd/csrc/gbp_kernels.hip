@@ -1281,8 +1281,28 @@ __global__ __launch_bounds__(64) void k_kf_solve(Dev<TS> d, IterOpts o, int read
 // the landmark since linearisation). `hist` keeps FHIST values per factor
 // between evaluations: g_k (2), g_m (2), tr S_m, last change of g_m (2),
 // valid flag, last change of g_k (2), pad (2).
-template <typename TS>
-__global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *__restrict__ feat,
+// a feature row: FP32 (export) or BF16 bits (the in-loop network input,
+// rounded to nearest even as the network would round it)
+__device__ __forceinline__ void store_features(float *__restrict__ p, const float (&x)[NFEAT]) {
+    float4 *q = reinterpret_cast<float4 *>(p);
+#pragma unroll
+    for (int i = 0; i < NFEAT / 4; ++i) q[i] = make_float4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+}
+__device__ __forceinline__ void store_features(uint16_t *__restrict__ p, const float (&x)[NFEAT]) {
+    uint32_t w[NFEAT / 2];
+#pragma unroll
+    for (int i = 0; i < NFEAT / 2; ++i) {
+        const uint32_t lo = __builtin_bit_cast(uint16_t, (__bf16)x[2 * i]);
+        const uint32_t hi = __builtin_bit_cast(uint16_t, (__bf16)x[2 * i + 1]);
+        w[i] = lo | (hi << 16);
+    }
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    q[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+template <typename TS, typename FT>
+__global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, FT *__restrict__ feat,
                                                   float *__restrict__ hist, double huber_k) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= d.nf) return;
@@ -1323,7 +1343,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     const float nm = sqrtf(gm0 * gm0 + gm1 * gm1), nmp = sqrtf(h[2] * h[2] + h[3] * h[3]);
     const float ndm = sqrtf(dm0 * dm0 + dm1 * dm1), ndmp = sqrtf(h[5] * h[5] + h[6] * h[6]);
     const float ndk = sqrtf(dk0 * dk0 + dk1 * dk1), ndkp = sqrtf(h[8] * h[8] + h[9] * h[9]);
-    float *x = feat + 16 * (size_t)f;
+    float x[NFEAT];
     x[0] = N > 0.0 ? (float)fmin(M0 / N, 10.0) : 0.f;
     x[1] = (float)((double)kr[10] / pp.inv_s2);
     x[2] = (float)log1p(M0);
@@ -1342,6 +1362,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, float *
     x[13] = have ? (dk0 * h[8] + dk1 * h[9]) / (ndk * ndkp + 1e-12f) : 0.f;
     x[14] = fminf((float)d.t_dev[0], 300.f) / 300.f;
     x[15] = (float)log1p(sqrt(ju0 * ju0 + ju1 * ju1));
+    store_features(feat + NFEAT * (size_t)f, x);
     h[0] = gk0; h[1] = gk1; h[2] = gm0; h[3] = gm1; h[4] = trS;
     h[5] = have ? dm0 : 0.f; h[6] = have ? dm1 : 0.f; h[7] = 1.f;
     h[8] = have ? dk0 : 0.f; h[9] = have ? dk1 : 0.f;
@@ -2025,7 +2046,15 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
 
 template <typename TS>
 void launch_features(const Dev<TS> &d, const IterOpts &o, float *feat, float *hist, double huber_k, hipStream_t s) {
-    if (d.nf > 0) hipLaunchKernelGGL(k_features<TS>, dim3(blocks(d.nf, 256)), dim3(256), 0, s, d, o, feat, hist, huber_k);
+    if (d.nf > 0)
+        hipLaunchKernelGGL((k_features<TS, float>), dim3(blocks(d.nf, 256)), dim3(256), 0, s, d, o, feat, hist, huber_k);
+}
+template <typename TS>
+void launch_features_bf16(const Dev<TS> &d, const IterOpts &o, uint16_t *feat, float *hist, double huber_k,
+                          hipStream_t s) {
+    if (d.nf > 0)
+        hipLaunchKernelGGL((k_features<TS, uint16_t>), dim3(blocks(d.nf, 256)), dim3(256), 0, s, d, o, feat, hist,
+                           huber_k);
 }
 
 template <typename TS>
@@ -2075,6 +2104,8 @@ void launch_tick(int *t_dev, hipStream_t s) { hipLaunchKernelGGL(k_tick, dim3(1)
                                              hipStream_t);              \
     template void launch_depth_move<TS>(const Dev<TS> &, const int *, int, const float *, hipStream_t);            \
     template void launch_features<TS>(const Dev<TS> &, const IterOpts &, float *, float *, double, hipStream_t);  \
+    template void launch_features_bf16<TS>(const Dev<TS> &, const IterOpts &, uint16_t *, float *, double,        \
+                                           hipStream_t);                                                          \
     template void launch_export_messages<TS>(const Dev<TS> &, const int *, const int *, int, float *, hipStream_t);
 
 GBP_INSTANTIATE(float)

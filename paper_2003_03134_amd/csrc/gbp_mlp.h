@@ -13,6 +13,9 @@ constexpr float MLP_DMAX = 0.9f;    // damping head range [0, 0.9]
 constexpr float MLP_CDELTA = 2.5f;  // log-depth correction range [-2.5, 2.5]
 
 void launch_mlp_infer(const float *X, int n, const uint16_t *P, float *out_d, float *out_delta, hipStream_t s);
+// the same with the features already rounded to BF16 (bits), 32 B per row
+void launch_mlp_infer_bf16(const uint16_t *X, int n, const uint16_t *P, float *out_d, float *out_delta,
+                           hipStream_t s);
 void launch_mlp_train_step(const float *X, const float *Y, const float *M, int n_rows, const int *idx, int n_batch,
                            float *theta, float *m1, float *m2, float *grad, float *part_grad, float *part_loss,
                            float *loss, uint16_t *bf16, float lr, int step, bool update, hipStream_t s);

@@ -90,6 +90,14 @@ __device__ __forceinline__ bf16x8_t load_x(const float *__restrict__ X, int n, i
     return x;
 }
 
+// the same from features already stored as BF16 bits
+__device__ __forceinline__ bf16x8_t load_x(const uint16_t *__restrict__ X, int n, int tile, int r, int hh) {
+    const int row = tile * 32 + r;
+    uint4 u = make_uint4(0u, 0u, 0u, 0u);
+    if (row < n) u = *reinterpret_cast<const uint4 *>(X + (size_t)row * MLP_IN + 8 * hh);
+    return __builtin_bit_cast(bf16x8_t, u);
+}
+
 // relu(acc + bias) of one 32x32 accumulator, rounded to BF16, as two B
 // operands
 __device__ __forceinline__ void relu_operands(const f32x16_t &acc, const f32x16_t &bias, bf16x8_t &lo,
@@ -101,7 +109,8 @@ __device__ __forceinline__ void relu_operands(const f32x16_t &acc, const f32x16_
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ X, int n,
+template <typename TX>
+__global__ __launch_bounds__(256) void k_mlp_infer(const TX *__restrict__ X, int n,
                                                    const uint16_t *__restrict__ P, float *__restrict__ out_d,
                                                    float *__restrict__ out_delta) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5, r = lane & 31;
@@ -350,7 +359,14 @@ __global__ void k_to_bf16(const float *__restrict__ theta, uint16_t *__restrict_
 void launch_mlp_infer(const float *X, int n, const uint16_t *P, float *out_d, float *out_delta, hipStream_t s) {
     if (n > 0) {
         const int waves = std::min((n + 31) / 32, INFER_WAVES_MAX);
-        hipLaunchKernelGGL(k_mlp_infer, dim3((waves + 3) / 4), dim3(256), 0, s, X, n, P, out_d, out_delta);
+        hipLaunchKernelGGL(k_mlp_infer<float>, dim3((waves + 3) / 4), dim3(256), 0, s, X, n, P, out_d, out_delta);
+    }
+}
+void launch_mlp_infer_bf16(const uint16_t *X, int n, const uint16_t *P, float *out_d, float *out_delta,
+                           hipStream_t s) {
+    if (n > 0) {
+        const int waves = std::min((n + 31) / 32, INFER_WAVES_MAX);
+        hipLaunchKernelGGL(k_mlp_infer<uint16_t>, dim3((waves + 3) / 4), dim3(256), 0, s, X, n, P, out_d, out_delta);
     }
 }
 
