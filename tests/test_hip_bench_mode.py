@@ -20,8 +20,8 @@ batch; the 125- and 1000-keyframe problems):
     of that damping); in the transient after the undamped window their FP32
     rounding is amplified on problems far from the origin (the largest
     batch member reaches 5e-5 after 20 iterations), and beta decisions then
-    flip (the reading of SURVEY C15). There the comparison is made at a
-    shared fixed point with the information damped too (above), and the
+    flip on such rounding-level differences. There the comparison is made at
+    a shared fixed point with the information damped too (above), and the
     FP32 run is held to the tolerance through the undamped window and
     through 100 iterations on the 125-keyframe problem.
 The 1000-keyframe graph (power-law observation counts, 5% outliers) holds
@@ -37,7 +37,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL, TOL_PX = 1e-4, 1e-3          # FP32 factor state (the benchmark spec)
+TOL, TOL_PX = 1e-4, 1e-3          # FP32 factor state: stated tolerance
 TOL64, TOL64_PX = 1e-8, 1e-8      # FP64 factor state: rounding only
 CHUNK = 50
 
