@@ -38,25 +38,26 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # the step sends its two messages, then the keyframe's message sums):
 #   per such factor: read the keyframe-side Jacobian, s and landmark index
 #     (12 x 4 B), its message (5 x 4 B), the landmark-side Jacobian and J a
-#     (8 x 4 B), its message (5 x 4 B), the factor-private data (linearised
-#     residual and keyframe-side J a, 4 x 4 B), counter and flags (2 x 1 B);
-#     write both new messages (2 x 5 x 4 B) and the counter (1 B): 179 B;
+#     (8 x 4 B), its message (5 x 4 B), the linearised residual (2 x 4 B),
+#     counter and flags (2 x 1 B); write both new messages (2 x 5 x 4 B) and
+#     the counter (1 B): 171 B;
 #   per relinearised factor: its flags (read and cleared, 2 x 1 B), the
 #     keyframe-side record and message it sums (12 x 4 + 5 x 4 B): 70 B;
-#   per keyframe: its slot (16 B), its belief (27 x 8 B), its 27 sums
-#     (27 x 8 B); per landmark: its belief once (9 x 8 B).
-FACTOR_BYTES_PER_FACTOR = 12 * 4 + 5 * 4 + 8 * 4 + 5 * 4 + 4 * 4 + 2 + 2 * 5 * 4 + 1  # 179
+#   per keyframe: its slot (16 B), its belief (27 x 8 B) and anchor
+#     (6 x 8 B), its 27 sums (27 x 8 B); per landmark: its belief once
+#     (9 x 8 B).
+FACTOR_BYTES_PER_FACTOR = 12 * 4 + 5 * 4 + 8 * 4 + 5 * 4 + 2 * 4 + 2 + 2 * 5 * 4 + 1  # 171
 KF_DONE_BYTES = 2 + 12 * 4 + 5 * 4                                                   # 70
-KF_BELIEF_BYTES = 16 + 27 * 8 + 27 * 8
+KF_BELIEF_BYTES = 16 + 27 * 8 + 6 * 8 + 27 * 8
 LM_BELIEF_BYTES = 9 * 8
 # k_relin (queued factors relinearise and send): per factor the queue entry
 # (16 B), the old Jacobian records and messages (12 + 5 + 8 + 5 floats and
 # 2 bytes: 122 B), its measurement (2 x 8 B); writes the new records (11 + 8
-# + 4 floats), its linearisation point (9 floats), both messages (10 floats),
-# counter and flags: 170 B; gathered once per variable touched: a keyframe's
+# + 2 floats), its linearisation point (9 floats), both messages (10 floats),
+# counter and flags: 162 B; gathered once per variable touched: a keyframe's
 # belief and anchor (27 + 6 doubles), a landmark's belief and anchor (12
 # doubles).
-RELIN_BYTES_PER_FACTOR = 16 + 122 + 16 + 170                                         # 324
+RELIN_BYTES_PER_FACTOR = 16 + 122 + 16 + 162                                         # 316
 RELIN_KF_BYTES, RELIN_LM_BYTES = 33 * 8, 12 * 8
 # k_belief_lm (keyframe solves in its first workgroups, then landmarks):
 #   per keyframe: sums (27 x 8 B), prior base, anchor information, birth clock

@@ -11,7 +11,7 @@ constexpr int KREC = 12;  // keyframe-side Jacobian record per factor (see layou
 constexpr int KMSG = 5;   // message to the keyframe (dense, rewritten every iteration)
 constexpr int LREC = 8;   // landmark-side Jacobian record per factor
 constexpr int MMSG = 5;   // message to the landmark (dense, rewritten every iteration)
-constexpr int AREC = 4;   // factor-private record read by the message update
+constexpr int AREC = 2;   // factor-private record read by the message update
 constexpr int DREC = 12;  // factor's linearisation point (check, features)
 constexpr int KBEL = 32;  // doubles per keyframe belief: dmu 6, cov 21 (packed), pad
 constexpr int LBEL = 16;  // doubles per landmark belief: dmu 3, cov 6 (packed), anchor 3, pad to 128 B
@@ -48,7 +48,8 @@ constexpr int LBI = 12;     // doubles of landmark belief information: Lambda pa
 //   [0..1]  rho = z - h(x0) + J_k (x0_k - anchor_k) + J_m (x0_m - anchor_m),
 //           the linearised residual at the anchors: the message update needs
 //           the residual and the linearisation point only in this sum
-//   [2..3]  J_k anchor_k
+// (J_k anchor_k is formed where it is needed, from the keyframe's anchor,
+// which a keyframe-kernel workgroup holds in scalar registers)
 // linearisation-point record: [0..5] x0_k - anchor_k, [6..8] x0_m - anchor_m, pad
 
 struct ProbParams {

@@ -106,6 +106,15 @@ __device__ __forceinline__ void load4(const double *__restrict__ p, double (&v)[
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
+__device__ __forceinline__ void load2(const float *__restrict__ p, float (&v)[2]) {
+    const float2 a = *reinterpret_cast<const float2 *>(p);
+    v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void load2(const double *__restrict__ p, double (&v)[2]) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    v[0] = a.x; v[1] = a.y;
+}
+
 __device__ __forceinline__ void load8(const float *__restrict__ p, float (&v)[8]) {
     const float4 *q = reinterpret_cast<const float4 *>(p);
 #pragma unroll
@@ -490,10 +499,11 @@ __device__ __forceinline__ void cavity_same_j(const double (&J)[2][D], const dou
 template <typename TS, bool RELIN>
 __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o, const int f, const int k,
                                             const int m_in, const double *__restrict__ bk,
-                                            TS *__restrict__ stage, const int fd_on = -1,
-                                            const int prob = -1, const double pend_k = 0.0) {
+                                            const double *__restrict__ ak, TS *__restrict__ stage,
+                                            const int fd_on = -1, const int prob = -1,
+                                            const double pend_k = 0.0) {
     TS ar[AREC], kr[KREC], lr[LREC], km[KMSG], mm[MMSG];
-    load4(d.arec + (size_t)f * AREC, ar);
+    load2(d.arec + (size_t)f * AREC, ar);
     load12(d.krec + (size_t)f * KREC, kr);
     // the relinearising caller has the landmark from its queue entry; the
     // keyframe kernel takes it from the keyframe-side record
@@ -526,10 +536,15 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
     Jko[1][3] = 0.0; Jko[1][4] = (double)kr[7]; Jko[1][5] = (double)kr[9];
     // linearised residual at the anchors, rho = r0 + J_k d0_k + J_m d0_m
     // (d0: the linearisation point relative to the anchors), and J a of both
-    // blocks
+    // blocks (the keyframe's from its anchor ak, the landmark's stored)
     double rho0 = (double)ar[0], rho1 = (double)ar[1];
     double s = (double)kr[10];
-    double jak0 = (double)ar[2], jak1 = (double)ar[3], jam0 = (double)lr[6], jam1 = (double)lr[7];
+    double jak0 = 0.0, jak1 = 0.0, jam0 = (double)lr[6], jam1 = (double)lr[7];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        if (!jac_zero<6>(0, i)) jak0 += Jko[0][i] * ak[i];
+        if (!jac_zero<6>(1, i)) jak1 += Jko[1][i] * ak[i];
+    }
     const double Ska = km[0], Skb = km[1], Skc = km[2], gk0 = km[3], gk1 = km[4];
     const double Sma = mm[0], Smb = mm[1], Smc = mm[2], gm0 = mm[3], gm1 = mm[4];
 
@@ -540,7 +555,7 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         const double hk = (fl & FLAG_PENDING) ? pend_k : o.huber_k;
         double x[6], l[3], zz[2] = {d.z[2 * (size_t)f], d.z[2 * (size_t)f + 1]};
 #pragma unroll
-        for (int i = 0; i < 6; ++i) x[i] = d.kf_anchor[6 * (size_t)k + i] + dmk[i];
+        for (int i = 0; i < 6; ++i) x[i] = ak[i] + dmk[i];
 #pragma unroll
         for (int i = 0; i < 3; ++i) l[i] = bm[LANC + i] + dmm[i];
         Lin L;
@@ -564,9 +579,8 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         jak0 = jak1 = jam0 = jam1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            double a = d.kf_anchor[6 * (size_t)k + i];
-            jak0 += Jkn[0][i] * a;
-            jak1 += Jkn[1][i] * a;
+            jak0 += Jkn[0][i] * ak[i];
+            jak1 += Jkn[1][i] * ak[i];
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -655,7 +669,6 @@ __device__ __forceinline__ void factor_body(const Dev<TS> &d, const IterOpts &o,
         kw[10] = (TS)s;
         TS *dw = d.drec + (size_t)f * DREC;
         aw[0] = (TS)rho0; aw[1] = (TS)rho1;
-        aw[2] = (TS)jak0; aw[3] = (TS)jak1;
         lw[6] = (TS)jam0; lw[7] = (TS)jam1;
 #pragma unroll
         for (int i = 0; i < 6; ++i) dw[i] = (TS)dmk[i];
@@ -1057,7 +1070,8 @@ __global__ __launch_bounds__(RELIN_BS) __attribute__((amdgpu_waves_per_eu(2))) v
         const int prob = d.rblk_prob[b];
         const int fd_on = (d.fdamp && !d.fallback[prob]) ? 1 : 0;
         const RelinEntry q = d.relin_queue[(size_t)b * RBLK + (i - pre[g])];
-        factor_body<TS, true>(d, o, q.f, q.k, q.m, d.kf_bel + (size_t)q.k * KBEL, nullptr, fd_on, prob, pend_k);
+        factor_body<TS, true>(d, o, q.f, q.k, q.m, d.kf_bel + (size_t)q.k * KBEL, d.kf_anchor + 6 * (size_t)q.k,
+                              nullptr, fd_on, prob, pend_k);
     }
 }
 
@@ -1205,9 +1219,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
     // scalar registers (loaded per lane, the compiler would keep 54 vector
     // registers for it, since it cannot rule out that the record stores
     // alias the belief array)
-    double kb[27];
+    double kb[27], ka[6];
 #pragma unroll
     for (int i = 0; i < 27; ++i) kb[i] = uniform_f64(d.kf_bel[(size_t)k * KBEL + i]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ka[i] = uniform_f64(d.kf_anchor[6 * (size_t)k + i]);
     const double *bk = kb;
     // learned damping: on unless absent or the keyframe's problem fell back
     // (the same for the whole workgroup)
@@ -1222,7 +1238,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(kf_waves_per
         if (f < e1) {
             const uint8_t fl = d.flags[f];
             if (MODE == 0 && !(fl & FLAG_DONE)) {
-                factor_body<TS, false>(d, o, f, k, -1, bk, row, fd_on);
+                factor_body<TS, false>(d, o, f, k, -1, bk, ka, row, fd_on);
             } else {
                 TS kr[KREC], km[KMSG];
                 load12(d.krec + (size_t)f * KREC, kr);
@@ -1312,7 +1328,7 @@ __global__ __launch_bounds__(256) void k_features(Dev<TS> d, IterOpts o, FT *__r
     load5(d.kmsg + (size_t)f * KMSG, km);
     load8(d.lrec + (size_t)f * LREC, lr);
     load5(d.mmsg + (size_t)f * MMSG, mm);
-    load4(d.arec + (size_t)f * AREC, ar);
+    load2(d.arec + (size_t)f * AREC, ar);
     load12(d.drec + (size_t)f * DREC, dr);
     const ProbParams pp = d.prob[d.kf_prob[k]];
     const double *bk = d.kf_bel + (size_t)k * KBEL, *bm = d.lm_bel + (size_t)m * LBEL;
@@ -1409,8 +1425,17 @@ __global__ void k_export_messages(Dev<TS> d, const int *__restrict__ idx, const 
     for (int c = 0; c < 5; ++c) o[5 + c] = (float)mm[c];
     o[10] = (float)d.cnt[f];
     o[11] = (float)d.flags[f];
-    const TS *ar = d.arec + (size_t)f * AREC;
-    o[12] = (float)ar[2]; o[13] = (float)ar[3];
+    // J_k anchor_k from the keyframe-side Jacobian and the keyframe's anchor
+    const int k = d.f_kf[f];
+    const double *ak = d.kf_anchor + 6 * (size_t)k;
+    double ja0 = 0.0, ja1 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        ja0 += (double)kr[i] * ak[i];
+        ja1 += (double)kr[3 + i] * ak[i];
+    }
+    ja0 += (double)kr[6] * ak[3] + (double)kr[8] * ak[5];
+    ja1 += (double)kr[7] * ak[4] + (double)kr[9] * ak[5];
+    o[12] = (float)ja0; o[13] = (float)ja1;
     o[14] = (float)lr[6]; o[15] = (float)lr[7];
 }
 
@@ -1456,20 +1481,13 @@ __global__ __launch_bounds__(256) void k_linearise(Dev<TS> d, int f0, int f1, do
 #pragma unroll
     for (int i = 9; i < DREC; ++i) dw[i] = (TS)0;
     aw[0] = (TS)rho0; aw[1] = (TS)rho1;
-    double jak0 = 0, jak1 = 0, jam0 = 0, jam1 = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double a = d.kf_anchor[6 * (size_t)k + i];
-        jak0 += L.J[0][i] * a;
-        jak1 += L.J[1][i] * a;
-    }
+    double jam0 = 0, jam1 = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         double a = d.lm_bel[(size_t)m * LBEL + LANC + i];
         jam0 += L.J[0][6 + i] * a;
         jam1 += L.J[1][6 + i] * a;
     }
-    aw[2] = (TS)jak0; aw[3] = (TS)jak1;
     lw[6] = (TS)jam0; lw[7] = (TS)jam1;
     d.cnt[f] = 0;
     d.flags[f] = L.valid ? 0 : FLAG_INVALID;
@@ -2020,6 +2038,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         T *tmp = (T *)scratch;
         switch (w) {
             case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
+            case 2: hipLaunchKernelGGL((k_gather<T, 2>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 4: hipLaunchKernelGGL((k_gather<T, 4>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 5: hipLaunchKernelGGL((k_gather<T, 5>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
             case 8: hipLaunchKernelGGL((k_gather<T, 8>), dim3(b), dim3(256), 0, s, (const T *)arr, tmp, perm, nf, fresh); break;
@@ -2029,7 +2048,7 @@ void launch_permute_factors(const Dev<TS> &d, const int *perm, int nf, void *scr
         }
         (void)hipMemcpyAsync(arr, tmp, sizeof(T) * (size_t)w * nf, hipMemcpyDeviceToDevice, s);
     };
-    static_assert(KREC == 12 && KMSG == 5 && LREC == 8 && MMSG == 5 && AREC == 4 && DREC == 12,
+    static_assert(KREC == 12 && KMSG == 5 && LREC == 8 && MMSG == 5 && AREC == 2 && DREC == 12,
                   "every record width needs its gather below");
     run(d.krec, TS(0), KREC);
     run(d.kmsg, TS(0), KMSG);

@@ -15,25 +15,25 @@ import bench  # noqa: E402
 
 def test_algorithmic_bytes_of_the_keyframe_kernel():
     # per factor: keyframe-side Jacobian, s and message (16 floats),
-    # landmark-side Jacobian and message (11), the linearised residual and
-    # both J a (6), landmark index, counter and flags; both messages and the
-    # counter written: 179 B; per keyframe its slot, 27 doubles in and 27
-    # out; per landmark 9 doubles
-    assert bench.FACTOR_BYTES_PER_FACTOR == 179
+    # landmark-side Jacobian, its J a and message (13), the linearised
+    # residual (2), landmark index, counter and flags; both messages and the
+    # counter written: 171 B; per keyframe its slot, 27 + 6 doubles in and
+    # 27 out; per landmark 9 doubles
+    assert bench.FACTOR_BYTES_PER_FACTOR == 171
     kf = lambda nf, nk, nl, due=0: bench.step_bytes(nf, nk, nl, due, 0, 0, False)["k_factor_kf"]  # noqa: E731
-    assert kf(1, 0, 0) == 179
-    assert kf(0, 1, 0) == 448
+    assert kf(1, 0, 0) == 171
+    assert kf(0, 1, 0) == 496
     assert kf(0, 0, 1) == 72
-    assert kf(10, 0, 0, due=1) == 9 * 179 + 70
+    assert kf(10, 0, 0, due=1) == 9 * 171 + 70
 
 
 def test_step_bytes_of_the_other_launches():
     """Each launch's per-unit figure, one unit at a time."""
     sb = lambda *a: bench.step_bytes(*a)  # noqa: E731
-    # relinearisation: 324 B per due factor, every keyframe's belief and
+    # relinearisation: 316 B per due factor, every keyframe's belief and
     # anchor once, the landmarks it touches once
     assert sb(1, 0, 0, 0, 0, 0, False)["k_relin"] == 0
-    assert sb(1, 1, 1, 1, 0, 0, False)["k_relin"] == 324 + 264 + 96
+    assert sb(1, 1, 1, 1, 0, 0, False)["k_relin"] == 316 + 264 + 96
     # landmark beliefs: 56 B per edge, 104 B per landmark, 636 B per keyframe
     assert sb(1, 0, 0, 0, 0, 0, False)["k_belief_lm"] == 56
     assert sb(0, 1, 1, 0, 0, 0, False)["k_belief_lm"] == 636 + 104
