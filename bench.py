@@ -502,16 +502,25 @@ def main():
         ", ".join(f"{k} {v:.4f}" for k, v in ph.items()))
 
     # factors relinearised in each timed iteration: the run is bitwise
-    # reproducible, so it is replayed from its start one iteration at a time,
-    # reading the relinearisation count after each (untimed)
+    # reproducible, so it is replayed from its start one iteration at a time
+    # (separate launches, each phase between events), reading the
+    # relinearisation count after each
     solver.reset()
     while solver.t < start - 9:
         solver.iterate_logged(min(c, start - 9 - solver.t), 0.4, 2.0, log_every=1)
     due = []  # due[j]: factors relinearised in iteration start - 8 + j
+    relin_ms = []  # the relinearisation launch of the same iteration, ms
     while solver.t < t_end:
-        solver.iterate(1, 0.4, 2.0)
+        relin_ms.append(solver.phase_times(1, 0.4, 2.0)["relin"])
         due.append(solver.last_relinearised)
     due_win = due[9:]
+    # the relinearisation launch against its due count over the window:
+    # a fixed part (every queue segment's workgroup runs its chain of
+    # dependent loads whatever its count) and a part per due factor
+    slope, icpt = np.polyfit(np.asarray(due_win, float), np.asarray(relin_ms[9:]) * 1e3, 1)
+    relin_model = dict(fixed_us=round(float(icpt), 2), ns_per_relinearised_factor=round(float(slope) * 1e3, 4),
+                       iterations=len(due_win), timing="one iteration per call, separate launches")
+    log(f"relinearisation launch: {icpt:.1f} us + {slope * 1e3:.3f} ns per relinearised factor")
     n_due = float(np.mean(due_win))
     # factors old enough to be checked in timed iteration start + 1 + j:
     # those not relinearised in the 9 iterations before it
@@ -539,6 +548,7 @@ def main():
                                ms_per_step=round(ms_per_step, 5)),
                     phases_ms={k: round(v, 5) for k, v in ph.items()},
                     relinearised_fraction=round(relin_frac, 5),
+                    relin_time_model=relin_model,
                     checked_fraction=round(n_old / nf, 4),
                     timed_iterations=[start + 1, t_end])
     solver.close()
