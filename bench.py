@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -100,11 +101,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def code_only(text):
+    """Source text without its comments and blank lines (the kernel sources
+    hold no comment markers inside string literals)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_sha():
+    """Hash of the kernel sources' code: a measurement recorded with it stays
+    valid through changes to comments only."""
     h = hashlib.sha256()
     for f in ("gbp_kernels.hip", "gbp_internal.h"):
-        with open(os.path.join(ROOT, "paper_2003_03134_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2003_03134_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

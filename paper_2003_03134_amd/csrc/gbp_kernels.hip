@@ -1033,8 +1033,8 @@ __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
 constexpr int RELIN_BS = 128;
 constexpr int RELIN_GROUP_MAX = 16;  // queue segments per relinearisation workgroup, at most
 
-// (two waves per SIMD: 256 registers, of which about 150 accumulation
-// registers the compiler uses as spill space)
+// (two waves per SIMD at 252 registers; held to three waves it spills, and
+// was slower)
 template <typename TS>
 __global__ __launch_bounds__(RELIN_BS) __attribute__((amdgpu_waves_per_eu(2))) void k_relin(Dev<TS> d, IterOpts o,
                                                                                             int nseg, int nred,
@@ -1195,9 +1195,10 @@ __device__ __forceinline__ void kf_contrib(const TS *row, TS *c) {
 // the factor-state precision, to a padded LDS row; 27 x G lanes then add
 // interleaved rows column by column in FP64 and the G partials are added in
 // group order (fixed order, no cross-lane shuffles).
-// FP32 factor state: four waves per SIMD. At 137 registers the kernel ran
-// three; the compiler fits it in 128 with a 12-byte spill, which measured 4%
-// faster. (No target for FP64 factor state, which cannot reach it.)
+// FP32 factor state: four waves per SIMD (126 registers, no spill). The
+// target once held the kernel, then at 137 registers, to 128 with a 12-byte
+// spill, 4% faster than three waves; it now keeps a change from silently
+// costing a wave. (No target for FP64 factor state, which cannot reach it.)
 template <typename TS, int BS>
 constexpr int kf_waves_per_eu() { return sizeof(TS) == 4 ? 4 : 1; }
 

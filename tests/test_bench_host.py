@@ -70,6 +70,14 @@ def test_kernel_sha_covers_the_kernel_sources():
     assert len(sha) == 16 and int(sha, 16) >= 0
 
 
+def test_code_only_drops_comments_and_keeps_code():
+    src = "int a = 1;  // one\n/* block\n   comment */\n\nint b = a / 2; /* inline */ int c;\n"
+    assert bench.code_only(src) == "int a = 1;\nint b = a / 2;  int c;"
+    # a change of comments only leaves the code, a change of code does not
+    assert bench.code_only(src.replace("one", "the first")) == bench.code_only(src)
+    assert bench.code_only(src.replace("a / 2", "a / 3")) != bench.code_only(src)
+
+
 @pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})])
 def test_more_than_one_gpu_is_refused(argv, env):
     e = dict(os.environ, **env)
