@@ -2,6 +2,7 @@
 differences on every parameter, head ranges, BF16 rounding vs the format's
 definition."""
 import numpy as np
+import pytest
 
 from oracle import mlp
 
@@ -76,6 +77,40 @@ def test_bf16_forward_reduces_to_fp64_forward_on_representable_values():
     x = rng.normal(size=(50, mlp.N_IN))
     diff = np.abs(mlp.forward_bf16(theta, x) - mlp.forward(theta, x)[0])
     assert 0 < diff.max() < 0.05
+
+
+@pytest.mark.parametrize("where", ["input", "weight", "hidden1", "hidden2"])
+def test_bf16_forward_rounds_at_each_storage_point(where):
+    """Inputs, weights and both hidden activations are stored in bfloat16
+    (nearest even) before they are read: a value v = 1 + 2^-9 + 2^-12, which
+    bfloat16 cannot hold, placed at one storage point of a one-unit path
+    reads as 1 there. Where a later rounding would hide it, the path doubles
+    and shifts the value (2 v - 1 rounds up to 1 + 2^-7, 2 round(v) - 1 is 1)."""
+    v = 1.0 + 2.0 ** -9 + 2.0 ** -12
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    x = np.zeros((1, mlp.N_IN))
+    x[0, 0] = 1.0
+    p["W1"][0, 0] = p["W2"][0, 0] = p["W3"][0, 0] = 1.0
+    if where == "input":            # h1 = 2 x - 1
+        x[0, 0] = v
+        p["W1"][0, 0], p["b1"][0] = 2.0, -1.0
+        o_fp64 = 2.0 * v - 1.0
+    elif where == "weight":         # o = W3 h2
+        p["W3"][0, 0] = v
+        o_fp64 = v
+    elif where == "hidden1":        # h1 = v, h2 = 2 h1 - 1
+        p["b1"][0] = v - 1.0
+        p["W2"][0, 0], p["b2"][0] = 2.0, -1.0
+        o_fp64 = 2.0 * v - 1.0
+    else:                           # h2 = v, o = h2
+        p["b2"][0] = v - 1.0
+        o_fp64 = v
+    theta = mlp.pack(p)
+    d_bf16 = mlp.forward_bf16(theta, x)[0, 0]
+    d_fp64 = mlp.forward(theta, x)[0][0, 0]
+    assert d_bf16 == mlp.D_MAX / (1.0 + np.exp(-1.0))
+    assert abs(d_fp64 - mlp.D_MAX / (1.0 + np.exp(-o_fp64))) < 1e-15
+    assert d_bf16 != d_fp64
 
 
 def test_adam_first_step_is_signed_learning_rate():

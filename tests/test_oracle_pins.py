@@ -123,10 +123,12 @@ def test_huber_weight_closed_form(oracle_mod):
 # linearised factor in information form (Section 4, eq. (infform))
 # --------------------------------------------------------------------------
 
-def test_factor_information_form(oracle_mod):
+@pytest.mark.parametrize("sigma", [1.0, 2.5])
+def test_factor_information_form(oracle_mod, sigma):
     """1/2 x^T Lambda x - eta^T x equals 1/2 (w/sigma^2) |J x - (J x0 + r0)|^2
-    up to a constant, for the oracle's stored eta_f and Lambda_f."""
-    p = synth.make_config0(seed=3)
+    up to a constant, for the oracle's stored eta_f and Lambda_f (a pixel
+    noise other than 1 keeps sigma from cancelling out)."""
+    p = synth.make_config0(seed=3, sigma=sigma)
     o = oracle_mod.Oracle(p, huber_k=2.0)
     rng = np.random.default_rng(5)
     for f in rng.choice(p.n_factors, 12, replace=False):
@@ -352,9 +354,12 @@ def test_eta_only_damping_transient_returns_to_truth(oracle_mod):
     assert np.abs(b["lm_mu"] - p.lm_true).max() < 1e-9
 
 
-def test_reprojection_error_brute_force(oracle_mod):
-    """Average reprojection error (Section 9.1) recomputed with scipy."""
-    p = synth.make_random_walk("t", 3, 12, 150, "poisson", 0.05)
+@pytest.mark.parametrize("sigma", [1.0, 2.5])
+def test_reprojection_error_brute_force(oracle_mod, sigma):
+    """Average reprojection error (Section 9.1) recomputed with scipy; the
+    robust kernel's linear regime is |r| above the threshold in pixels,
+    whatever the pixel noise."""
+    p = synth.make_random_walk("t", 3, 12, 150, "poisson", 0.05, sigma=sigma)
     o = oracle_mod.Oracle(p)
     o.iterate(15, 0.4, 2.0)
     b = o.beliefs()
@@ -377,6 +382,35 @@ def test_reprojection_error_brute_force(oracle_mod):
     assert r["n_ref"] == (valid & p.inlier).sum()
     assert r["n_linear_ref"] == (lin & p.inlier).sum()
     assert 0 < r["n_linear_ref"] < r["n_linear"]
+
+
+def test_reprojection_statistics_leave_out_points_behind_the_camera(oracle_mod):
+    """The averages run over the points in front of their camera only, and
+    the others are counted apart (brute force at the oracle's means)."""
+    p = synth.make_config0(seed=7)
+    for m in (0, 5):
+        k = int(p.factor_kf[np.flatnonzero(p.factor_lm == m)[0]])
+        R = Rotation.from_rotvec(p.kf_init[k, :3]).as_matrix()
+        p.lm_init[m] = R.T @ (np.array([0.1, 0.1, -1.0]) - p.kf_init[k, 3:])
+    o = oracle_mod.Oracle(p)
+    b = o.beliefs()
+    pc = (Rotation.from_rotvec(b["kf_mu"][p.factor_kf, :3]).apply(b["lm_mu"][p.factor_lm])
+          + b["kf_mu"][p.factor_kf, 3:])
+    valid = pc[:, 2] > 1e-3
+    assert 0 < (~valid).sum() < len(valid)
+    hz = np.stack([500 * pc[:, 0] / pc[:, 2] + 320, 500 * pc[:, 1] / pc[:, 2] + 240], 1)
+    e = np.linalg.norm(p.z - hz, axis=1)
+    # a threshold between the errors, so that both regimes occur (the
+    # means at creation do not depend on it)
+    thr = float(np.median(e[valid]))
+    o = oracle_mod.Oracle(p, huber_k=thr)
+    assert np.array_equal(o.beliefs()["lm_mu"], b["lm_mu"])
+    r = o.reproj()
+    assert r["n_invalid"] == (~valid).sum() and r["n_valid"] == valid.sum()
+    assert abs(r["are_all"] - e[valid].mean()) < 1e-10
+    lin = valid & (e > thr)
+    assert 0 < lin.sum() < valid.sum() and r["n_linear"] == lin.sum()
+    assert abs(r["are_quadratic"] - e[valid & ~lin].mean()) < 1e-10
 
 
 def test_point_behind_camera_carries_no_information(oracle_mod):
