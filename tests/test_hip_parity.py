@@ -181,6 +181,39 @@ def test_batch_equals_single_and_oracle(gbp):
     b.close()
 
 
+def test_fp64_pixel_noise_per_problem_in_one_batch(gbp):
+    """Problems of one batch with pixel noise 0.5, 1 and 2.5 px: each
+    follows its own oracle under the beta rule (the factor precision
+    w / sigma^2 and the robust threshold in units of sigma are the
+    problem's own), and so do its residual statistics, linear-regime
+    counts included, with a reference set."""
+    import oracle
+    probs = [synth.make_random_walk("px", 31 + i, 12, 160, "poisson", 0.05, sigma=sg)
+             for i, sg in enumerate((0.5, 1.0, 2.5))]
+    s = gbp.GBPSolver(probs, precision=gbp.GBP_FP64)
+    s.set_reference(np.concatenate([p.z_true for p in probs]), np.concatenate([p.inlier for p in probs]))
+    os_ = [oracle.Oracle(p, anneal=False) for p in probs]
+    ko = np.cumsum([0] + [p.n_keyframes for p in probs])
+    lo = np.cumsum([0] + [p.n_landmarks for p in probs])
+    for it in range(4):
+        s.iterate(15, 0.4, 2.0)
+        g = s.beliefs()
+        for i, (p, o) in enumerate(zip(probs, os_)):
+            o.iterate(15, 0.4, 2.0)
+            gi = dict(kf_mu=g["kf_mu"][ko[i]:ko[i + 1]], lm_mu=g["lm_mu"][lo[i]:lo[i + 1]])
+            assert mean_errs(gi, o.beliefs()) < 1e-7, (it, i)
+            rg, ro = s.reproj(i), o.reproj(p.z_true, p.inlier)
+            for key in ("n_valid", "n_quadratic", "n_linear", "n_invalid", "n_ref", "n_linear_ref"):
+                assert rg[key] == ro[key], (it, i, key)
+            for key in ("are_all", "are_quadratic", "are_ref"):
+                assert abs(rg[key] - ro[key]) < 1e-7, (it, i, key)
+    # the three noise levels put different shares of the factors in the
+    # linear regime of the 2-px threshold
+    lin = [s.reproj(i)["n_linear"] / p.n_factors for i, p in enumerate(probs)]
+    assert lin[0] < lin[1] < lin[2]
+    s.close()
+
+
 def test_caller_factor_order_does_not_matter(gbp):
     prob = synth.make_config0(seed=4)
     rng = np.random.default_rng(0)
