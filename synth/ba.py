@@ -169,12 +169,14 @@ def _assemble(name, cam, kf_true, lm_true, obs, rng, outlier_frac,
 # ----------------------------------------------------------------------------
 
 def make_config0(seed: int = 0, n_kf: int = 5, n_lm: int = 50,
-                 radius: float = 2.0, sigma: float = 1.0) -> BAProblem:
+                 radius: float = 2.0, sigma: float = 1.0,
+                 camera: Camera | None = None) -> BAProblem:
     """Tiny loopy problem: keyframes evenly spaced on a horizontal circle,
     each facing the origin; landmarks uniform in a 1 m cube; each landmark
-    observed by 3-5 distinct keyframes chosen among those that see it."""
+    observed by 3-5 distinct keyframes chosen among those that see it.
+    `camera` replaces the default intrinsics (and its sigma the noise)."""
     rng = np.random.default_rng(seed)
-    cam = Camera(sigma=sigma)
+    cam = camera if camera is not None else Camera(sigma=sigma)
     kf = []
     for i in range(n_kf):
         a = 2.0 * np.pi * i / n_kf
@@ -227,7 +229,7 @@ def make_random_walk(name: str, seed: int, n_kf: int, n_lm: int,
                      max_tries: int = 30, min_obs: int = 2,
                      look_yaw_deg: float = 0.0,
                      rot_sigma: float = 0.0, centre_sigma: float = 0.07,
-                     lm_sigma: float = 0.1) -> BAProblem:
+                     lm_sigma: float = 0.1, camera: Camera | None = None) -> BAProblem:
     """Random-walk trajectory (0.2 m steps, heading changes U(+-5 deg) per
     step), camera looking along the heading (rotated by look_yaw_deg). Each
     landmark is spawned from a random keyframe at a random pixel and depth
@@ -238,9 +240,10 @@ def make_random_walk(name: str, seed: int, n_kf: int, n_lm: int,
 
     Initial estimate (Section 9.1 protocol): keyframe camera centres perturbed
     by N(0, 7 cm) per axis, orientations left at the truth, landmarks
-    perturbed by N(0, 0.1 m) per axis; keyframe 0 exact and anchored."""
+    perturbed by N(0, 0.1 m) per axis; keyframe 0 exact and anchored.
+    `camera` replaces the default intrinsics (and its sigma the noise)."""
     rng = np.random.default_rng(seed)
-    cam = Camera(sigma=sigma)
+    cam = camera if camera is not None else Camera(sigma=sigma)
     centres, heading = _walk(n_kf, rng)
     yaw = heading + np.deg2rad(look_yaw_deg)
     kf_true = np.array([_pose_looking(c, np.array([np.cos(h), np.sin(h), 0.0]))

@@ -181,15 +181,18 @@ def test_batch_equals_single_and_oracle(gbp):
     b.close()
 
 
-def test_fp64_pixel_noise_per_problem_in_one_batch(gbp):
-    """Problems of one batch with pixel noise 0.5, 1 and 2.5 px: each
+def test_fp64_pixel_noise_and_intrinsics_per_problem_in_one_batch(gbp):
+    """Problems of one batch with pixel noise 0.5, 1 and 2.5 px, and one
+    whose focal lengths and principal point coordinates all differ: each
     follows its own oracle under the beta rule (the factor precision
-    w / sigma^2 and the robust threshold in units of sigma are the
-    problem's own), and so do its residual statistics, linear-regime
+    w / sigma^2, the robust threshold in units of sigma and the intrinsics
+    are the problem's own), and so do its residual statistics, linear-regime
     counts included, with a reference set."""
     import oracle
-    probs = [synth.make_random_walk("px", 31 + i, 12, 160, "poisson", 0.05, sigma=sg)
-             for i, sg in enumerate((0.5, 1.0, 2.5))]
+    cams = [synth.Camera(sigma=0.5), synth.Camera(), synth.Camera(sigma=2.5),
+            synth.Camera(450.0, 520.0, 300.0, 250.0, sigma=1.5)]
+    probs = [synth.make_random_walk("px", 31 + i, 12, 160, "poisson", 0.05, camera=c)
+             for i, c in enumerate(cams)]
     s = gbp.GBPSolver(probs, precision=gbp.GBP_FP64)
     s.set_reference(np.concatenate([p.z_true for p in probs]), np.concatenate([p.inlier for p in probs]))
     os_ = [oracle.Oracle(p, anneal=False) for p in probs]
@@ -209,7 +212,7 @@ def test_fp64_pixel_noise_per_problem_in_one_batch(gbp):
                 assert abs(rg[key] - ro[key]) < 1e-7, (it, i, key)
     # the three noise levels put different shares of the factors in the
     # linear regime of the 2-px threshold
-    lin = [s.reproj(i)["n_linear"] / p.n_factors for i, p in enumerate(probs)]
+    lin = [s.reproj(i)["n_linear"] / p.n_factors for i, p in enumerate(probs[:3])]
     assert lin[0] < lin[1] < lin[2]
     s.close()
 

@@ -16,6 +16,9 @@ from tests import dense_ref
 pytestmark = []
 
 CAM = [500.0, 500.0, 320.0, 240.0]
+# a camera whose focal lengths and principal point coordinates all differ,
+# so that no pin passes with one of them read for another
+CAM_SKEWED = [450.0, 520.0, 300.0, 250.0]
 
 
 def rand_pose_point(rng):
@@ -62,34 +65,42 @@ def test_so3_right_jacobian_fd(oracle_mod, scale):
         assert np.abs(col - Jr[:, i]).max() < 2e-8
 
 
-def test_projection_matches_library_rotation(oracle_mod):
+@pytest.mark.parametrize("cam", [CAM, CAM_SKEWED])
+def test_projection_matches_library_rotation(oracle_mod, cam):
     rng = np.random.default_rng(3)
     for _ in range(20):
         x, l = rand_pose_point(rng)
-        h, _, pz = oracle_mod.project(x, l, CAM)
+        h, _, pz = oracle_mod.project(x, l, cam)
         pc = Rotation.from_rotvec(x[:3]).apply(l) + x[3:]
         assert abs(pz - pc[2]) < 1e-12
-        assert np.allclose(h, [CAM[0] * pc[0] / pc[2] + CAM[2],
-                               CAM[1] * pc[1] / pc[2] + CAM[3]], atol=1e-10)
+        assert np.allclose(h, [cam[0] * pc[0] / pc[2] + cam[2],
+                               cam[1] * pc[1] / pc[2] + cam[3]], atol=1e-10)
 
 
-def test_projection_principal_point(oracle_mod):
+@pytest.mark.parametrize("cam", [CAM, CAM_SKEWED])
+def test_projection_principal_point(oracle_mod, cam):
     # identity pose: a point on the optical axis projects to (cx, cy)
-    h, _, pz = oracle_mod.project(np.zeros(6), np.array([0.0, 0.0, 3.0]), CAM)
-    assert np.allclose(h, [320.0, 240.0]) and pz == 3.0
+    h, _, pz = oracle_mod.project(np.zeros(6), np.array([0.0, 0.0, 3.0]), cam)
+    assert np.allclose(h, cam[2:4]) and pz == 3.0
     # a quarter turn about camera y sends world +x onto the optical axis
     x = np.array([0.0, -np.pi / 2, 0.0, 0.0, 0.0, 0.0])
-    h, _, pz = oracle_mod.project(x, np.array([2.0, 0.0, 0.0]), CAM)
-    assert np.allclose(h, [320.0, 240.0], atol=1e-9) and abs(pz - 2.0) < 1e-12
+    h, _, pz = oracle_mod.project(x, np.array([2.0, 0.0, 0.0]), cam)
+    assert np.allclose(h, cam[2:4], atol=1e-9) and abs(pz - 2.0) < 1e-12
+    # one unit off the axis in x (y) at depth 2 moves u (v) by fx / 2 (fy / 2)
+    h, _, _ = oracle_mod.project(np.zeros(6), np.array([1.0, 0.0, 2.0]), cam)
+    assert np.allclose(h, [cam[2] + cam[0] / 2, cam[3]], atol=1e-12)
+    h, _, _ = oracle_mod.project(np.zeros(6), np.array([0.0, 1.0, 2.0]), cam)
+    assert np.allclose(h, [cam[2], cam[3] + cam[1] / 2], atol=1e-12)
 
 
-def test_jacobian_central_differences(oracle_mod):
+@pytest.mark.parametrize("cam", [CAM, CAM_SKEWED])
+def test_jacobian_central_differences(oracle_mod, cam):
     """The 2x9 Jacobian of the measurement function (Section 4) against
     central finite differences in every coordinate, relative error < 1e-6."""
     rng = np.random.default_rng(4)
     for _ in range(25):
         x, l = rand_pose_point(rng)
-        _, J, _ = oracle_mod.project(x, l, CAM)
+        _, J, _ = oracle_mod.project(x, l, cam)
         v = np.concatenate([x, l])
         Jfd = np.zeros((2, 9))
         for i in range(9):
@@ -97,8 +108,8 @@ def test_jacobian_central_differences(oracle_mod):
             vp, vm = v.copy(), v.copy()
             vp[i] += e
             vm[i] -= e
-            hp = oracle_mod.project(vp[:6], vp[6:], CAM)[0]
-            hm = oracle_mod.project(vm[:6], vm[6:], CAM)[0]
+            hp = oracle_mod.project(vp[:6], vp[6:], cam)[0]
+            hm = oracle_mod.project(vm[:6], vm[6:], cam)[0]
             Jfd[:, i] = (hp - hm) / (2 * e)
         assert np.abs(J - Jfd).max() <= 1e-6 * np.abs(Jfd).max()
 
@@ -123,17 +134,20 @@ def test_huber_weight_closed_form(oracle_mod):
 # linearised factor in information form (Section 4, eq. (infform))
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("sigma", [1.0, 2.5])
-def test_factor_information_form(oracle_mod, sigma):
+@pytest.mark.parametrize("camera", [synth.Camera(), synth.Camera(sigma=2.5),
+                                    synth.Camera(*CAM_SKEWED, sigma=1.5)], ids=["unit", "sigma2.5", "skewed"])
+def test_factor_information_form(oracle_mod, camera):
     """1/2 x^T Lambda x - eta^T x equals 1/2 (w/sigma^2) |J x - (J x0 + r0)|^2
     up to a constant, for the oracle's stored eta_f and Lambda_f (a pixel
-    noise other than 1 keeps sigma from cancelling out)."""
-    p = synth.make_config0(seed=3, sigma=sigma)
+    noise other than 1 keeps sigma from cancelling out; a camera whose
+    intrinsics all differ checks that the oracle reads the problem's own)."""
+    p = synth.make_config0(seed=3, camera=camera)
     o = oracle_mod.Oracle(p, huber_k=2.0)
     rng = np.random.default_rng(5)
+    cam = [camera.fx, camera.fy, camera.cx, camera.cy]
     for f in rng.choice(p.n_factors, 12, replace=False):
         eta, lam, lin, w = o.factor(int(f))
-        h, J, _ = oracle_mod.project(lin[:6], lin[6:], CAM)
+        h, J, _ = oracle_mod.project(lin[:6], lin[6:], cam)
         r0 = p.z[f] - h
         M = np.linalg.norm(r0) / p.cam.sigma
         assert abs(w - oracle_mod.huber_weight(M, 2.0 / p.cam.sigma)) < 1e-14
@@ -354,18 +368,20 @@ def test_eta_only_damping_transient_returns_to_truth(oracle_mod):
     assert np.abs(b["lm_mu"] - p.lm_true).max() < 1e-9
 
 
-@pytest.mark.parametrize("sigma", [1.0, 2.5])
-def test_reprojection_error_brute_force(oracle_mod, sigma):
+@pytest.mark.parametrize("camera", [synth.Camera(), synth.Camera(sigma=2.5),
+                                    synth.Camera(*CAM_SKEWED, sigma=1.5)], ids=["unit", "sigma2.5", "skewed"])
+def test_reprojection_error_brute_force(oracle_mod, camera):
     """Average reprojection error (Section 9.1) recomputed with scipy; the
     robust kernel's linear regime is |r| above the threshold in pixels,
     whatever the pixel noise."""
-    p = synth.make_random_walk("t", 3, 12, 150, "poisson", 0.05, sigma=sigma)
+    p = synth.make_random_walk("t", 3, 12, 150, "poisson", 0.05, camera=camera)
     o = oracle_mod.Oracle(p)
     o.iterate(15, 0.4, 2.0)
     b = o.beliefs()
     pc = (Rotation.from_rotvec(b["kf_mu"][p.factor_kf, :3]).apply(b["lm_mu"][p.factor_lm])
           + b["kf_mu"][p.factor_kf, 3:])
-    hz = np.stack([500 * pc[:, 0] / pc[:, 2] + 320, 500 * pc[:, 1] / pc[:, 2] + 240], 1)
+    hz = np.stack([camera.fx * pc[:, 0] / pc[:, 2] + camera.cx,
+                   camera.fy * pc[:, 1] / pc[:, 2] + camera.cy], 1)
     valid = pc[:, 2] > 1e-3
     e = np.linalg.norm(p.z - hz, axis=1)
     r = o.reproj(p.z_true, p.inlier)
