@@ -275,21 +275,28 @@ def learned_kernels_leg(n_rows):
     x = torch.randn(n_rows, gbp.MLP_FEATURES, device="cuda", generator=gen)
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for _ in range(3):
-        gbp.mlp_infer(wt, x)
     reps = 20
-    torch.cuda.synchronize()
-    ev[0].record(s)
-    for _ in range(reps):
-        gbp.mlp_infer(wt, x)
-    ev[1].record(s)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / reps
-    flop, nbytes = 2 * (16 * 64 + 64 * 64 + 64 * 2), 16 * 4 + 2 * 4
-    infer = dict(rows=n_rows, ms=round(ms, 4), tflops=round(n_rows * flop / ms / 1e9, 2),
-                 gbps=round(n_rows * nbytes / ms / 1e6, 1),
-                 frac_hbm=round(n_rows * nbytes / ms / 1e6 / HBM_PEAK_GBS, 3),
-                 frac_mfma_bf16=round(n_rows * flop / ms / 1e9 / 2500.0, 4))
+    flop = 2 * (16 * 64 + 64 * 64 + 64 * 2)
+
+    def time_infer(xin, nbytes):
+        for _ in range(3):
+            gbp.mlp_infer(wt, xin)
+        torch.cuda.synchronize()
+        ev[0].record(s)
+        for _ in range(reps):
+            gbp.mlp_infer(wt, xin)
+        ev[1].record(s)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps
+        return t, dict(rows=n_rows, ms=round(t, 4), tflops=round(n_rows * flop / t / 1e9, 2),
+                       gbps=round(n_rows * nbytes / t / 1e6, 1),
+                       frac_hbm=round(n_rows * nbytes / t / 1e6 / HBM_PEAK_GBS, 3),
+                       frac_mfma_bf16=round(n_rows * flop / t / 1e9 / 2500.0, 4))
+
+    # FP32 feature rows (64 B) and, as the iteration's own evaluation reads
+    # them, BF16 rows (32 B); both write two 4-B heads
+    ms, infer = time_infer(x, 16 * 4 + 2 * 4)
+    _, infer["bf16_rows"] = time_infer(x.to(torch.bfloat16), 16 * 2 + 2 * 4)
     nb, nd = 8192, 1 << 16
     tr = gbp.MLPTrainer(theta, max_batch=nb)
     y = torch.rand(nd, 2, device="cuda", generator=gen)

@@ -347,6 +347,14 @@ gbp_status gbp_factor_messages(gbp_problem *p, const int32_t *idx, int32_t n,
 gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n,
                          float *d_out, float *delta_out, void *stream);
 
+/* The same with the features already stored as BF16 bit patterns, x_bf16
+ * [n][16] (device): half the bytes per row; the network rounds its FP32
+ * inputs to BF16 (nearest even) anyway, so features rounded that way give
+ * bit for bit the outputs of gbp_mlp_infer. Errors as gbp_mlp_infer. */
+gbp_status gbp_mlp_infer_bf16(const uint16_t *weights, const uint16_t *x_bf16,
+                              int32_t n, float *d_out, float *delta_out,
+                              void *stream);
+
 /* Device workspace bytes of gbp_mlp_train_step for batches up to max_batch. */
 gbp_status gbp_mlp_train_workspace_bytes(int32_t max_batch, size_t *bytes);
 

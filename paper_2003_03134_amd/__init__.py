@@ -357,12 +357,13 @@ def _check_plain(st):
 
 def mlp_infer(weights_bf16, x, stream=None):
     """Damping and log-depth heads of the network for feature rows x
-    (n x 16 float32 CUDA tensor); weights_bf16 is a CUDA tensor holding the
-    BF16 bit patterns (int16 or uint16, MLP_PARAMS entries)."""
+    (n x 16 CUDA tensor, float32, or bfloat16 for gbp_mlp_infer_bf16);
+    weights_bf16 is a CUDA tensor holding the BF16 bit patterns (int16 or
+    uint16, MLP_PARAMS entries)."""
     import torch
     lib = _capi.load()
-    if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 2 or x.shape[1] != MLP_FEATURES:
-        raise ValueError("x must be a CUDA float32 tensor of shape (n, 16)")
+    if x.dtype not in (torch.float32, torch.bfloat16) or not x.is_cuda or x.dim() != 2 or x.shape[1] != MLP_FEATURES:
+        raise ValueError("x must be a CUDA float32 or bfloat16 tensor of shape (n, 16)")
     if weights_bf16.numel() != MLP_PARAMS or weights_bf16.element_size() != 2 or not weights_bf16.is_cuda:
         raise ValueError("weights must be a CUDA tensor of MLP_PARAMS 16-bit values")
     x = x.contiguous()
@@ -371,9 +372,9 @@ def mlp_infer(weights_bf16, x, stream=None):
     d = torch.empty(n, dtype=torch.float32, device=x.device)
     delta = torch.empty(n, dtype=torch.float32, device=x.device)
     s = stream if stream is not None else torch.cuda.current_stream(x.device)
-    _check_plain(lib.gbp_mlp_infer(C.c_void_p(weights_bf16.data_ptr()), C.c_void_p(x.data_ptr()), n,
-                                   C.c_void_p(d.data_ptr()), C.c_void_p(delta.data_ptr()),
-                                   C.c_void_p(s.cuda_stream)))
+    fn = lib.gbp_mlp_infer if x.dtype == torch.float32 else lib.gbp_mlp_infer_bf16
+    _check_plain(fn(C.c_void_p(weights_bf16.data_ptr()), C.c_void_p(x.data_ptr()), n,
+                    C.c_void_p(d.data_ptr()), C.c_void_p(delta.data_ptr()), C.c_void_p(s.cuda_stream)))
     return d, delta
 
 

@@ -60,7 +60,7 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
            "gbp_create_batch", "gbp_relinearise", "gbp_iterate", "gbp_beliefs",
            "gbp_reproj_error", "gbp_reproj_stats", "gbp_set_reference", "gbp_add_pair_factors",
            "gbp_iterate_logged", "gbp_add_keyframe", "gbp_set_damping_model",
-           "gbp_reset", "gbp_apply_depth_model", "gbp_set_damping_judges", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer",
+           "gbp_reset", "gbp_apply_depth_model", "gbp_set_damping_judges", "gbp_fallback_flags", "gbp_factor_features", "gbp_factor_messages", "gbp_mlp_infer", "gbp_mlp_infer_bf16",
            "gbp_mlp_train_workspace_bytes", "gbp_mlp_train_step", "gbp_mlp_train_step_static",
            "gbp_phase_times", "gbp_counters", "gbp_autotune", "gbp_sizes", "gbp_last_error", "gbp_destroy"]
 
@@ -115,6 +115,7 @@ def load():
     lib.gbp_factor_features.argtypes = [P, P, C.c_int32, P]
     lib.gbp_factor_messages.argtypes = [P, P, C.c_int32, P]
     lib.gbp_mlp_infer.argtypes = [P, P, C.c_int32, P, P, P]
+    lib.gbp_mlp_infer_bf16.argtypes = [P, P, C.c_int32, P, P, P]
     lib.gbp_mlp_train_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
     lib.gbp_mlp_train_step.argtypes = [P, P, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_float, C.c_int32,
                                        P, P, P, C.c_size_t, P]

@@ -1683,6 +1683,18 @@ gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n, flo
     return GBP_OK;
 }
 
+gbp_status gbp_mlp_infer_bf16(const uint16_t *weights, const uint16_t *x_bf16, int32_t n, float *d_out,
+                              float *delta_out, void *stream) {
+    if (n < 0 || (n > 0 && (!weights || !x_bf16 || !d_out))) {
+        g_err = "gbp_mlp_infer_bf16: need n >= 0 and device weights, x and d_out";
+        return GBP_EINVAL;
+    }
+    launch_mlp_infer_bf16(x_bf16, n, weights, d_out, delta_out, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { g_err = std::string("gbp_mlp_infer_bf16: ") + hipGetErrorString(e); return GBP_EDEVICE; }
+    return GBP_OK;
+}
+
 gbp_status gbp_mlp_train_workspace_bytes(int32_t max_batch, size_t *bytes) {
     if (max_batch < 1 || !bytes) { g_err = "gbp_mlp_train_workspace_bytes: need max_batch >= 1"; return GBP_EINVAL; }
     *bytes = (size_t)mlp_partial_blocks(max_batch) * (MLP_NPARAMS + 1) * 4 + 256;

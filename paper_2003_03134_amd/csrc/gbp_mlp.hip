@@ -73,30 +73,41 @@ __device__ __forceinline__ int hid(int kk, int hh, int j) {
 }
 
 constexpr int INFER_WAVES_MAX = 2048;  // 256 CUs x 8 waves
+constexpr int INFER_AHEAD = 4;         // tiles whose features a wave has in flight
 
-// one tile's features, converted to BF16 (round to nearest even) in the
-// layer-1 B operand layout: row tile * 32 + r, features 8 hh .. 8 hh + 7
-__device__ __forceinline__ bf16x8_t load_x(const float *__restrict__ X, int n, int tile, int r, int hh) {
+// One tile's features in the layer-1 B operand layout (row tile * 32 + r,
+// features 8 hh .. 8 hh + 7), loaded raw so that the load stays in flight
+// until the tile is computed, then converted to BF16 (round to nearest even)
+// at use. Rows past n read as zeros without a load.
+struct RawF32 { float4 u, v; };
+struct RawBF16 { uint4 u; };
+
+__device__ __forceinline__ RawF32 load_raw(const float *__restrict__ X, int n, int tile, int r, int hh) {
     const int row = tile * 32 + r;
-    float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
+    RawF32 x{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
     if (row < n) {
         const float4 *xp = reinterpret_cast<const float4 *>(X + (size_t)row * MLP_IN + 8 * hh);
-        u = xp[0];
-        v = xp[1];
+        x.u = xp[0];
+        x.v = xp[1];
     }
-    bf16x8_t x;
-    x[0] = (__bf16)u.x; x[1] = (__bf16)u.y; x[2] = (__bf16)u.z; x[3] = (__bf16)u.w;
-    x[4] = (__bf16)v.x; x[5] = (__bf16)v.y; x[6] = (__bf16)v.z; x[7] = (__bf16)v.w;
     return x;
 }
 
 // the same from features already stored as BF16 bits
-__device__ __forceinline__ bf16x8_t load_x(const uint16_t *__restrict__ X, int n, int tile, int r, int hh) {
+__device__ __forceinline__ RawBF16 load_raw(const uint16_t *__restrict__ X, int n, int tile, int r, int hh) {
     const int row = tile * 32 + r;
-    uint4 u = make_uint4(0u, 0u, 0u, 0u);
-    if (row < n) u = *reinterpret_cast<const uint4 *>(X + (size_t)row * MLP_IN + 8 * hh);
-    return __builtin_bit_cast(bf16x8_t, u);
+    RawBF16 x{make_uint4(0u, 0u, 0u, 0u)};
+    if (row < n) x.u = *reinterpret_cast<const uint4 *>(X + (size_t)row * MLP_IN + 8 * hh);
+    return x;
 }
+
+__device__ __forceinline__ bf16x8_t to_operand(const RawF32 &r) {
+    bf16x8_t x;
+    x[0] = (__bf16)r.u.x; x[1] = (__bf16)r.u.y; x[2] = (__bf16)r.u.z; x[3] = (__bf16)r.u.w;
+    x[4] = (__bf16)r.v.x; x[5] = (__bf16)r.v.y; x[6] = (__bf16)r.v.z; x[7] = (__bf16)r.v.w;
+    return x;
+}
+__device__ __forceinline__ bf16x8_t to_operand(const RawBF16 &r) { return __builtin_bit_cast(bf16x8_t, r.u); }
 
 // relu(acc + bias) of one 32x32 accumulator, rounded to BF16, as two B
 // operands
@@ -151,12 +162,20 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const TX *__restrict__ X, int
 
     const int ntiles = (n + 31) / 32;
     const int stride = gridDim.x * (blockDim.x / 64);
-    int tile = blockIdx.x * (blockDim.x / 64) + wave;
-    bf16x8_t x = load_x(X, n, tile < ntiles ? tile : 0, r, hh);
-    for (; tile < ntiles; tile += stride) {
-        // the next tile's features are in flight while this one computes
-        const int next = tile + stride;
-        const bf16x8_t xn = load_x(X, n, next < ntiles ? next : tile, r, hh);
+    const int first = blockIdx.x * (blockDim.x / 64) + wave;
+    // the features of the wave's next INFER_AHEAD tiles are in flight while
+    // one computes (a ring of registers, rotated by unrolling; rows past n
+    // read as zeros without a load)
+    decltype(load_raw(X, n, 0, r, hh)) ring[INFER_AHEAD];
+#pragma unroll
+    for (int u = 0; u < INFER_AHEAD; ++u) ring[u] = load_raw(X, n, first + u * stride, r, hh);
+    for (int t0 = first; t0 < ntiles; t0 += INFER_AHEAD * stride)
+#pragma unroll
+    for (int u = 0; u < INFER_AHEAD; ++u) {
+        const int tile = t0 + u * stride;
+        if (tile >= ntiles) break;
+        const bf16x8_t x = to_operand(ring[u]);
+        ring[u] = load_raw(X, n, tile + INFER_AHEAD * stride, r, hh);
         // layer 1: H1^T = relu(W1 X^T + b1)
         bf16x8_t h1[4];
 #pragma unroll
@@ -185,7 +204,6 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const TX *__restrict__ X, int
             out_d[row] = d;
             if (out_delta) out_delta[row] = delta;
         }
-        x = xn;
     }
 }
 

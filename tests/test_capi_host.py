@@ -19,7 +19,7 @@ def capi():
 
 def test_header_declarations_are_exported(capi):
     text = open(os.path.join(ROOT, "include", "gbp.h")).read()
-    declared = set(re.findall(r"\b(gbp_[a-z_]+)\s*\(", text))
+    declared = set(re.findall(r"\b(gbp_[a-z0-9_]+)\s*\(", text))
     lib = capi.load()
     for name in sorted(declared):
         assert hasattr(lib, name), name

@@ -65,6 +65,25 @@ def test_mlp_infer_matches_bf16_oracle(gbp, n):
     assert np.all((d.cpu().numpy() >= 0) & (d.cpu().numpy() <= 0.9))
 
 
+def test_mlp_infer_large_launch_equals_small_launches(gbp):
+    """A launch in which every wave of the persistent grid (2048 waves of
+    32-row tiles) works through five tiles and a ragged sixth, its features
+    in flight several tiles ahead, gives each row bit for bit what launches
+    of at most 4133 rows (one tile per wave, checked against the oracle
+    above) give; and features stored as BF16 bits (rounded to nearest even,
+    as the network rounds its FP32 inputs) give the FP32 rows' outputs."""
+    import torch
+    n, piece = 2048 * 32 * 5 + 13, 4133
+    x = _dev(np.random.default_rng(5).normal(0, 1.5, (n, 16)).astype(np.float32))
+    w = _dev(omlp.to_bf16_bits(_theta(11)).view(np.int16))
+    d, e = gbp.mlp_infer(w, x)
+    parts = [gbp.mlp_infer(w, x[i:i + piece]) for i in range(0, n, piece)]
+    d16, e16 = gbp.mlp_infer(w, x.to(torch.bfloat16))
+    torch.cuda.synchronize()
+    assert torch.equal(d, torch.cat([p[0] for p in parts])) and torch.equal(e, torch.cat([p[1] for p in parts]))
+    assert torch.equal(d, d16) and torch.equal(e, e16)
+
+
 @pytest.mark.parametrize("weights", ["random", "packaged"])
 def test_mlp_infer_within_bf16_bound_of_fp64_network(gbp, weights):
     """The MFMA network against the plain FP64 network (no emulation of the
