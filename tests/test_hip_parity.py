@@ -217,6 +217,33 @@ def test_fp64_pixel_noise_and_intrinsics_per_problem_in_one_batch(gbp):
     s.close()
 
 
+def test_fp32_pixel_noise_and_intrinsics_per_problem_forced_schedule(gbp):
+    """The same four problems with FP32 factor state and annealed priors,
+    the linearisation forced every 10 iterations on both sides: every
+    problem's means within 1e-4 relative of its oracle and its reprojection
+    error within 1e-3 px."""
+    import oracle
+    cams = [synth.Camera(sigma=0.5), synth.Camera(), synth.Camera(sigma=2.5),
+            synth.Camera(450.0, 520.0, 300.0, 250.0, sigma=1.5)]
+    probs = [synth.make_random_walk("px", 31 + i, 12, 160, "poisson", 0.05, camera=c)
+             for i, c in enumerate(cams)]
+    s = gbp.GBPSolver(probs, precision=gbp.GBP_FP32, anneal=True)
+    os_ = [oracle.Oracle(p, anneal=True) for p in probs]
+    ko = np.cumsum([0] + [p.n_keyframes for p in probs])
+    lo = np.cumsum([0] + [p.n_landmarks for p in probs])
+    for it in range(6):
+        s.iterate(10, 0.4, 2.0)
+        g = s.beliefs()
+        for i, o in enumerate(os_):
+            o.iterate(10, 0.4, 2.0)
+            gi = dict(kf_mu=g["kf_mu"][ko[i]:ko[i + 1]], lm_mu=g["lm_mu"][lo[i]:lo[i + 1]])
+            assert mean_errs(gi, o.beliefs()) < 1e-4, (it, i)
+            assert abs(s.reproj(i)["are_all"] - o.reproj()["are_all"]) < 1e-3, (it, i)
+            o.relinearise(-1)
+        s.relinearise(-1)
+    s.close()
+
+
 def test_caller_factor_order_does_not_matter(gbp):
     prob = synth.make_config0(seed=4)
     rng = np.random.default_rng(0)
