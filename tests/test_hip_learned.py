@@ -253,12 +253,15 @@ def _proj(prob, lin):
     return oracle.project(lin[:6], lin[6:], _cam(prob))
 
 
-def test_factor_messages_match_oracle_messages(gbp):
+@pytest.mark.parametrize("camera", [synth.Camera(), synth.Camera(450.0, 520.0, 300.0, 250.0, sigma=1.5)],
+                         ids=["unit", "skewed"])
+def test_factor_messages_match_oracle_messages(gbp, camera):
     """FP64 run under a forced schedule: the exported measurement-space
     messages, mapped to variable space (J^T S J, J^T (g + S J a)), equal the
-    oracle's messages; the counters equal the oracle's."""
+    oracle's messages; the counters equal the oracle's (also with a camera
+    whose intrinsics all differ and a pixel noise other than 1)."""
     import oracle
-    prob = synth.make_config0(seed=0)
+    prob = synth.make_config0(seed=0, camera=camera)
     s = gbp.GBPSolver(prob, precision=gbp.GBP_FP64, anneal=False)
     o = oracle.Oracle(prob, anneal=False)
     s.iterate(13, 0.4, 2.0)
@@ -289,12 +292,15 @@ def test_factor_messages_match_oracle_messages(gbp):
     s.close()
 
 
-def test_features_follow_their_definitions(gbp):
+@pytest.mark.parametrize("camera", [synth.Camera(), synth.Camera(450.0, 520.0, 300.0, 250.0, sigma=1.5)],
+                         ids=["unit", "skewed"])
+def test_features_follow_their_definitions(gbp, camera):
     """Features of every factor against their definitions, evaluated from
     the oracle's state (FP64 run, forced schedule) and the exported
-    messages of two consecutive evaluations."""
+    messages of two consecutive evaluations; also with a camera whose
+    intrinsics all differ and a pixel noise other than 1."""
     import oracle
-    prob = synth.make_config0(seed=1)
+    prob = synth.make_config0(seed=1, camera=camera)
     nf = prob.n_factors
     s = gbp.GBPSolver(prob, precision=gbp.GBP_FP64, anneal=False)
     o = oracle.Oracle(prob, anneal=False)
