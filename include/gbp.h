@@ -340,17 +340,19 @@ gbp_status gbp_factor_messages(gbp_problem *p, const int32_t *idx, int32_t n,
                                float *out);
 
 /* Network inference on caller buffers (all device pointers): x [n][16]
- * float, weights GBP_MLP_PARAMS BF16, d_out [n] damping head, delta_out [n]
- * log-depth head (may be NULL). Asynchronous on `stream` (hipStream_t, NULL
- * = default stream). Errors (GBP_EINVAL, GBP_EDEVICE) leave their text in
- * gbp_last_error(NULL). */
+ * float, 16-byte aligned (each row is read as 16-byte vectors; a misaligned
+ * x is GBP_EINVAL), weights GBP_MLP_PARAMS BF16, d_out [n] damping head,
+ * delta_out [n] log-depth head (may be NULL). Asynchronous on `stream`
+ * (hipStream_t, NULL = default stream). Errors (GBP_EINVAL, GBP_EDEVICE)
+ * leave their text in gbp_last_error(NULL). */
 gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n,
                          float *d_out, float *delta_out, void *stream);
 
 /* The same with the features already stored as BF16 bit patterns, x_bf16
- * [n][16] (device): half the bytes per row; the network rounds its FP32
- * inputs to BF16 (nearest even) anyway, so features rounded that way give
- * bit for bit the outputs of gbp_mlp_infer. Errors as gbp_mlp_infer. */
+ * [n][16] (device, 16-byte aligned): half the bytes per row; the network
+ * rounds its FP32 inputs to BF16 (nearest even) anyway, so features rounded
+ * that way give bit for bit the outputs of gbp_mlp_infer. Errors as
+ * gbp_mlp_infer. */
 gbp_status gbp_mlp_infer_bf16(const uint16_t *weights, const uint16_t *x_bf16,
                               int32_t n, float *d_out, float *delta_out,
                               void *stream);

@@ -1677,6 +1677,11 @@ gbp_status gbp_mlp_infer(const uint16_t *weights, const float *x, int32_t n, flo
         g_err = "gbp_mlp_infer: need n >= 0 and device weights, x and d_out";
         return GBP_EINVAL;
     }
+    if ((uintptr_t)x % 16 != 0) {
+        g_err = "gbp_mlp_infer: x must be 16-byte aligned (rows are read as 16-byte vectors)";
+        return GBP_EINVAL;
+    }
+    if (n == 0) return GBP_OK;
     launch_mlp_infer(x, n, weights, d_out, delta_out, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { g_err = std::string("gbp_mlp_infer: ") + hipGetErrorString(e); return GBP_EDEVICE; }
@@ -1689,6 +1694,11 @@ gbp_status gbp_mlp_infer_bf16(const uint16_t *weights, const uint16_t *x_bf16, i
         g_err = "gbp_mlp_infer_bf16: need n >= 0 and device weights, x and d_out";
         return GBP_EINVAL;
     }
+    if ((uintptr_t)x_bf16 % 16 != 0) {
+        g_err = "gbp_mlp_infer_bf16: x_bf16 must be 16-byte aligned (rows are read as 16-byte vectors)";
+        return GBP_EINVAL;
+    }
+    if (n == 0) return GBP_OK;
     launch_mlp_infer_bf16(x_bf16, n, weights, d_out, delta_out, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { g_err = std::string("gbp_mlp_infer_bf16: ") + hipGetErrorString(e); return GBP_EDEVICE; }

@@ -127,3 +127,17 @@ def test_static_training_step_rejects_oversized_batches(capi):
     st = lib.gbp_mlp_train_step_static(fake, fake, fake, 10, fake, 0, fake, fake, fake, fake,
                                        C.c_float(1e-3), 1, fake, fake, None)
     assert st == capi.GBP_EINVAL
+
+
+@pytest.mark.parametrize("entry", ["gbp_mlp_infer", "gbp_mlp_infer_bf16"])
+def test_inference_rejects_misaligned_rows(capi, entry):
+    """Feature rows are read as 16-byte vectors: a misaligned row pointer is
+    refused before any device work (the pointers are never dereferenced);
+    n = 0 with no buffers is a no-op."""
+    lib = capi.load()
+    fake = C.c_void_p(0x1000)
+    st = getattr(lib, entry)(fake, C.c_void_p(0x1008), 4, fake, None, None)
+    assert st == capi.GBP_EINVAL and b"aligned" in lib.gbp_last_error(None)
+    st = getattr(lib, entry)(fake, fake, -1, fake, None, None)
+    assert st == capi.GBP_EINVAL
+    assert getattr(lib, entry)(None, None, 0, None, None, None) == capi.GBP_OK

@@ -121,6 +121,13 @@ def test_mlp_infer_empty_and_bad_arguments(gbp):
     lib = gbp.load_library()
     assert lib.gbp_mlp_infer(None, None, 5, None, None, None) == -1
     assert b"gbp_mlp_infer" in lib.gbp_last_error(None)
+    # rows are read as 16-byte vectors: a view starting 4 bytes into its
+    # storage is refused, not read misaligned
+    for dt in (torch.float32, torch.bfloat16):
+        base = torch.zeros(5 * 16 + 8, dtype=dt, device="cuda")
+        shift = 4 // base.element_size()
+        with pytest.raises(RuntimeError, match="aligned"):
+            gbp.mlp_infer(w, base[shift:shift + 5 * 16].view(5, 16))
 
 
 def _bf16(a):
