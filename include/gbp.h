@@ -133,6 +133,14 @@ gbp_status gbp_create(const gbp_graph *graph, const gbp_camera *camera,
 
 /* Build n independent problems that run as one block-diagonal graph and
  * one launch sequence (arrays of n graphs / cameras / measurements). */
+
+/* Largest batch: the keyframes, the landmarks and the factors of all of a
+ * batch's problems (growth capacities included) may each number at most
+ * this; gbp_create, gbp_create_batch and gbp_workspace_bytes return
+ * GBP_EINVAL beyond it, before reading any array. Indices are 32-bit; at
+ * about 375 B of device memory per factor (FP32 state), the factor limit
+ * lies above what one 288 GB GPU holds. */
+#define GBP_MAX_BATCH_ITEMS 1073741824
 gbp_status gbp_create_batch(int32_t n, const gbp_graph *graphs,
                             const gbp_camera *cameras,
                             const gbp_measurements *meas,
@@ -204,7 +212,9 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping,
  * they enter every later belief update. May be called at any clock and
  * repeatedly; synchronises. Their state lives in one extra device
  * allocation made here (outside a caller workspace). GBP_EINVAL for a bad
- * kind, index, a == b, non-finite z or non-positive precision; GBP_ESTATE on
+ * kind, index, a == b, non-finite z or non-positive precision, or more than
+ * GBP_MAX_BATCH_ITEMS pairs between keyframes (odometry included) or between
+ * landmarks in total (checked before the arrays are read); GBP_ESTATE on
  * a problem that has grown (gbp_add_keyframe), and afterwards
  * gbp_add_keyframe (and gbp_apply_depth_model, for landmark pairs) return
  * GBP_ESTATE. gbp_reset zeroes their messages and keeps them. */

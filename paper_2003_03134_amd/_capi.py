@@ -66,6 +66,7 @@ EXPORTS = ["gbp_default_options", "gbp_workspace_bytes", "gbp_create",
 
 MLP_PARAMS = 5378
 GBP_MLP_STATIC_MAX_BATCH = 8192   # batch limit of gbp_mlp_train_step_static
+GBP_MAX_BATCH_ITEMS = 1 << 30     # keyframes, landmarks, factors per batch, at most
 LOG_COLS = 5           # GBP_LOG_COLS: columns of a gbp_iterate_logged row
 MLP_FEATURES = 16
 

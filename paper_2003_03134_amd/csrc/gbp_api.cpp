@@ -231,6 +231,31 @@ gbp_status check_opts(const gbp_options *o, std::string &msg) {
     return GBP_OK;
 }
 
+// Sizes of a batch before any of its arrays is read: each graph's sizes,
+// then the totals (capacities included) against GBP_MAX_BATCH_ITEMS, so
+// that every index and every 2 x index fits 32 bits.
+gbp_status check_totals(int n, const gbp_graph *gs, const gbp_options &o, std::string &msg) {
+    long long nk = 0, nl = 0, nf = 0;
+    for (int i = 0; i < n; ++i) {
+        if (gs[i].n_keyframes < 1 || gs[i].n_landmarks < 0 || gs[i].n_factors < 0) {
+            msg = "problem " + std::to_string(i) + ": bad sizes";
+            return GBP_EINVAL;
+        }
+        nk += gs[i].n_keyframes;
+        nl += gs[i].n_landmarks;
+        nf += gs[i].n_factors;
+    }
+    nk = std::max(nk, (long long)o.max_keyframes);
+    nl = std::max(nl, (long long)o.max_landmarks);
+    nf = std::max(nf, (long long)o.max_factors);
+    if (nk > GBP_MAX_BATCH_ITEMS || nl > GBP_MAX_BATCH_ITEMS || nf > GBP_MAX_BATCH_ITEMS) {
+        msg = "batch too large: " + std::to_string(nk) + " keyframes, " + std::to_string(nl) + " landmarks, " +
+              std::to_string(nf) + " factors (at most " + std::to_string(GBP_MAX_BATCH_ITEMS) + " each)";
+        return GBP_EINVAL;
+    }
+    return GBP_OK;
+}
+
 gbp_status check_graph(const gbp_graph *g, const gbp_measurements *m, const gbp_camera *c, std::string &msg) {
     if (!g || !m || !c) { msg = "null argument"; return GBP_EINVAL; }
     if (g->n_keyframes < 1 || g->n_landmarks < 0 || g->n_factors < 0) { msg = "bad sizes"; return GBP_EINVAL; }
@@ -538,6 +563,8 @@ gbp_status create_impl(int n, const gbp_graph *gs, const gbp_camera *cams, const
     gbp_status st = check_opts(&opt, msg);
     if (st != GBP_OK) { p->broken = true; return fail(p, st, msg); }
     if (n < 1 || !gs || !cams || !ms) { p->broken = true; return fail(p, GBP_EINVAL, "need n >= 1 problems"); }
+    st = check_totals(n, gs, opt, msg);
+    if (st != GBP_OK) { p->broken = true; return fail(p, st, msg); }
     for (int i = 0; i < n; ++i) {
         st = check_graph(&gs[i], &ms[i], &cams[i], msg);
         if (st != GBP_OK) { p->broken = true; return fail(p, st, "problem " + std::to_string(i) + ": " + msg); }
@@ -1415,6 +1442,11 @@ gbp_status gbp_workspace_bytes(int32_t n, const gbp_graph *gs, const gbp_options
     if (!bytes || n < 1 || !gs) return GBP_EINVAL;
     gbp_options opt;
     if (opt_in) opt = *opt_in; else default_opts(&opt);
+    std::string msg;
+    if (check_totals(n, gs, opt, msg) != GBP_OK) {
+        g_err = "gbp_workspace_bytes: " + msg;
+        return GBP_EINVAL;
+    }
     gbp_problem tmp;
     tmp.np = n;
     long nk = 0, nl = 0, nf = 0;
@@ -1551,6 +1583,9 @@ gbp_status gbp_add_pair_factors(gbp_problem *p, int32_t kind, int32_t n, const i
         return fail(p, GBP_EINVAL, "gbp_add_pair_factors: need n >= 0 and the four arrays");
     if (p->grown) return fail(p, GBP_ESTATE, "gbp_add_pair_factors: the problem has grown since creation");
     if (n == 0) return GBP_OK;
+    if ((long long)p->h_pair_ab[kind == GBP_PAIR_LANDMARKS ? 1 : 0].size() / 2 + n > GBP_MAX_BATCH_ITEMS)
+        return fail(p, GBP_EINVAL, "gbp_add_pair_factors: more than GBP_MAX_BATCH_ITEMS pair factors of one kind of "
+                                   "variable");
     // odometry factors live with the keyframe pairs (D = 6 storage, 3 values
     // measured, the rest zero)
     const bool kfk = kind != GBP_PAIR_LANDMARKS;

@@ -31,6 +31,7 @@ def test_header_constants_match_the_binding(capi):
     assert int(re.search(r"#define GBP_MLP_STATIC_MAX_BATCH (\d+)", text).group(1)) == \
         capi.GBP_MLP_STATIC_MAX_BATCH
     assert int(re.search(r"#define GBP_LOG_COLS (\d+)", text).group(1)) == capi.LOG_COLS
+    assert int(re.search(r"#define GBP_MAX_BATCH_ITEMS (\d+)", text).group(1)) == capi.GBP_MAX_BATCH_ITEMS
     fields = re.search(r"typedef struct \{([^}]*)\} gbp_reproj;", text).group(1)
     names = re.findall(r"\b(?:double|int64_t)\s+(\w+);", fields)
     assert names == [n for n, _ in capi.gbp_reproj._fields_]
@@ -141,3 +142,45 @@ def test_inference_rejects_misaligned_rows(capi, entry):
     st = getattr(lib, entry)(fake, fake, -1, fake, None, None)
     assert st == capi.GBP_EINVAL
     assert getattr(lib, entry)(None, None, 0, None, None, None) == capi.GBP_OK
+
+
+def test_batches_beyond_the_index_limit_are_rejected(capi):
+    """Totals over a batch (capacities included) above GBP_MAX_BATCH_ITEMS
+    are refused before any array is read: the graphs below claim sizes their
+    arrays do not have, and their pointers are never dereferenced."""
+    lib = capi.load()
+    lim = capi.GBP_MAX_BATCH_ITEMS
+    fake_i = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_int32))
+    fake_d = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_double))
+
+    def graph(nk, nl, nf):
+        return capi.gbp_graph(nk, nl, nf, fake_i, fake_i, fake_d, fake_d, None)
+
+    n = C.c_size_t()
+    # exactly at the limit: sized (about 400 GB in FP32), not refused
+    g = graph(2, 2, lim)
+    assert lib.gbp_workspace_bytes(1, C.byref(g), None, C.byref(n)) == 0
+    assert n.value > 300 * lim
+    # one factor more, split over two problems
+    gs = (capi.gbp_graph * 2)(graph(2, 2, lim // 2), graph(2, 2, lim // 2 + 1))
+    assert lib.gbp_workspace_bytes(2, gs, None, C.byref(n)) == capi.GBP_EINVAL
+    assert b"batch too large" in lib.gbp_last_error(None)
+    cams = (capi.gbp_camera * 2)(capi.gbp_camera(500, 500, 320, 240, 1.0), capi.gbp_camera(500, 500, 320, 240, 1.0))
+    ms = (capi.gbp_measurements * 2)(capi.gbp_measurements(fake_d), capi.gbp_measurements(fake_d))
+    h = C.c_void_p()
+    assert lib.gbp_create_batch(2, gs, cams, ms, None, C.byref(h)) == capi.GBP_EINVAL
+    assert b"batch too large" in lib.gbp_last_error(h)
+    lib.gbp_destroy(h)
+    # keyframes and landmarks, and a growth capacity beyond the limit
+    for g in (graph(lim + 1, 2, 4), graph(2, lim + 1, 4)):
+        assert lib.gbp_workspace_bytes(1, C.byref(g), None, C.byref(n)) == capi.GBP_EINVAL
+    o = capi.gbp_options()
+    lib.gbp_default_options(C.byref(o))
+    o.max_factors = lim + 1
+    g = graph(2, 2, 4)
+    assert lib.gbp_workspace_bytes(1, C.byref(g), C.byref(o), C.byref(n)) == capi.GBP_EINVAL
+    h = C.c_void_p()
+    assert lib.gbp_create(C.byref(g), C.byref(cams[0]), C.byref(ms[0]), C.byref(o), C.byref(h)) == \
+        capi.GBP_EINVAL
+    assert b"batch too large" in lib.gbp_last_error(h)
+    lib.gbp_destroy(h)

@@ -164,6 +164,15 @@ def test_bad_pairs_and_growth_are_rejected(gbp):
         with pytest.raises(gbp.GBPError) as e:
             s.add_pair_factors(*args)
         assert e.value.status == -1
+    # a count beyond the 32-bit index limit is refused before the arrays are
+    # read (the pointers below are never dereferenced)
+    import ctypes as C
+    lib = gbp.load_library()
+    fi = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_int32))
+    fd = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_double))
+    for kind in (0, 1, 2):
+        assert lib.gbp_add_pair_factors(s.h, kind, (1 << 30) + 1, fi, fi, fd, fd) == -1
+        assert b"GBP_MAX_BATCH_ITEMS" in lib.gbp_last_error(s.h)
     s.add_pair_factors(1, [0], [1], z3, one3)
     with pytest.raises(gbp.GBPError) as e:
         s.add_keyframe(prob.kf_init[1], np.zeros((0, 3)), [], [], np.zeros((0, 2)))
