@@ -89,6 +89,11 @@ class GBPSolver:
             z = _f64(p.z)
             self._keep += [fkf, flm, kfi, lmi, anc, z]
             nk, nl, nf = kfi.shape[0], lmi.shape[0], fkf.shape[0]
+            # the library reads exactly these sizes from each array
+            if (fkf.shape != (nf,) or flm.shape != (nf,) or z.shape != (nf, 2) or kfi.shape != (nk, 6)
+                    or lmi.shape != (nl, 3) or (anc is not None and anc.shape != (nk,))):
+                raise ValueError(f"problem {i}: need factor_kf, factor_lm [nf], z [nf, 2], kf_init [nk, 6], "
+                                 f"lm_init [nl, 3] and kf_anchor_info [nk] or None")
             graphs[i] = _capi.gbp_graph(nk, nl, nf, _ptr(fkf, C.c_int32), _ptr(flm, C.c_int32),
                                         _ptr(kfi, C.c_double), _ptr(lmi, C.c_double),
                                         _ptr(anc, C.c_double))
@@ -272,6 +277,8 @@ class GBPSolver:
         lmi = _f64(lm_init).reshape(-1, 3)
         fk, fl = _i32(f_kf), _i32(f_lm)
         zz = _f64(z).reshape(-1, 2)
+        if fk.ndim != 1 or fl.shape != fk.shape or zz.shape[0] != fk.shape[0]:
+            raise ValueError("add_keyframe: f_kf, f_lm and z need one entry per new factor")
         self._check(self._lib.gbp_add_keyframe(self.h, _ptr(pose, C.c_double), lmi.shape[0],
                                                _ptr(lmi, C.c_double), fk.shape[0],
                                                _ptr(fk, C.c_int32), _ptr(fl, C.c_int32),

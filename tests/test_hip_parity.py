@@ -697,6 +697,23 @@ def _empty_problem(cam):
                      np.array([0.0]))
 
 
+def test_mismatched_array_shapes_are_refused(gbp):
+    """The library reads exactly n_factors, n_keyframes and n_landmarks
+    entries from each array: arrays that disagree with those sizes are
+    refused by the binding before any of them reaches the library."""
+    import dataclasses
+    base = synth.make_config0(seed=0)
+    bad = [dict(z=base.z[:-1]), dict(factor_lm=base.factor_lm[:-1]), dict(kf_init=base.kf_init[:, :5]),
+           dict(lm_init=base.lm_init.ravel()), dict(kf_anchor_info=base.kf_anchor_info[:-1])]
+    for change in bad:
+        with pytest.raises(ValueError, match="need factor_kf"):
+            gbp.GBPSolver([base, dataclasses.replace(base, **change)])
+    s = gbp.GBPSolver(base, capacity=(base.n_keyframes + 1, base.n_landmarks + 4, base.n_factors + 8))
+    with pytest.raises(ValueError, match="one entry per new factor"):
+        s.add_keyframe(base.kf_init[-1], np.zeros((0, 3)), [base.n_keyframes] * 3, [0, 1], np.zeros((3, 2)))
+    s.close()
+
+
 def test_empty_problems_and_isolated_variables(gbp):
     """Degenerate inputs: a problem with one keyframe and nothing else, and a
     problem with a keyframe and a landmark that no factor touches, batched
