@@ -253,6 +253,9 @@ class GBPSolver:
             return
         zr = _f64(z_ref)
         mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        nf = sum(self.f_counts)
+        if zr.shape != (nf, 2) or mk.shape != (nf,):
+            raise ValueError(f"set_reference: need z_ref [{nf}, 2] and mask [{nf}] (every factor of the batch)")
         self._check(self._lib.gbp_set_reference(self.h, _ptr(zr, C.c_double),
                                                 _ptr(mk, C.c_uint8)), self.h)
 

@@ -709,6 +709,10 @@ def test_mismatched_array_shapes_are_refused(gbp):
         with pytest.raises(ValueError, match="need factor_kf"):
             gbp.GBPSolver([base, dataclasses.replace(base, **change)])
     s = gbp.GBPSolver(base, capacity=(base.n_keyframes + 1, base.n_landmarks + 4, base.n_factors + 8))
+    with pytest.raises(ValueError, match="set_reference"):
+        s.set_reference(base.z_true[:-1], base.inlier[:-1])
+    with pytest.raises(ValueError, match="set_reference"):
+        s.set_reference(base.z_true, base.inlier[:-1])
     with pytest.raises(ValueError, match="one entry per new factor"):
         s.add_keyframe(base.kf_init[-1], np.zeros((0, 3)), [base.n_keyframes] * 3, [0, 1], np.zeros((3, 2)))
     s.close()
