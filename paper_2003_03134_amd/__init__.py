@@ -181,30 +181,34 @@ class GBPSolver:
         self._check(self._lib.gbp_relinearise(self.h, float(beta), C.byref(n)), self.h)
         return n.value
 
+    def _huber(self, huber_k):
+        # the threshold to pass: the new one, else the last one accepted
+        return float(self.huber_k if huber_k is None else huber_k)
+
     def iterate(self, n: int, damping: float = 0.4, huber_k: float | None = None) -> None:
-        if huber_k is not None:
-            self.huber_k = huber_k
-        self._check(self._lib.gbp_iterate(self.h, int(n), float(damping), float(self.huber_k)), self.h)
+        hk = self._huber(huber_k)
+        self._check(self._lib.gbp_iterate(self.h, int(n), float(damping), hk), self.h)
+        self.huber_k = hk
 
     def iterate_logged(self, n: int, damping: float = 0.4, huber_k: float | None = None,
                        log_every: int = 1) -> np.ndarray:
         """Returns [n // log_every, n_problems, 5] rows of (t, are_all, are_ref,
         n_linear, n_linear_ref)."""
-        if huber_k is not None:
-            self.huber_k = huber_k
-        rows = n // log_every
+        hk = self._huber(huber_k)
+        rows = n // log_every if log_every >= 1 else 0  # the library refuses log_every < 1
         out = np.zeros((max(rows, 1), self.n_problems, LOG_COLS))
-        self._check(self._lib.gbp_iterate_logged(self.h, int(n), float(damping), float(self.huber_k),
+        self._check(self._lib.gbp_iterate_logged(self.h, int(n), float(damping), hk,
                                                  int(log_every), _ptr(out, C.c_double)), self.h)
+        self.huber_k = hk
         return out[:rows]
 
     def phase_times(self, n: int, damping: float = 0.4, huber_k: float | None = None) -> dict:
         """Average ms per launch of each phase over n real iterations."""
-        if huber_k is not None:
-            self.huber_k = huber_k
+        hk = self._huber(huber_k)
         ms = np.zeros(6)
-        self._check(self._lib.gbp_phase_times(self.h, int(n), float(damping), float(self.huber_k),
+        self._check(self._lib.gbp_phase_times(self.h, int(n), float(damping), hk,
                                               _ptr(ms, C.c_double)), self.h)
+        self.huber_k = hk
         return dict(check=ms[0], relin=ms[1], factor_kf=ms[2], belief_lm=ms[3], reproj=ms[4],
                     k_factor_kf=ms[5])
 

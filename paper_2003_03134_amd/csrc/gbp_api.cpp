@@ -1489,8 +1489,8 @@ gbp_status gbp_iterate_logged(gbp_problem *p, int32_t n, double damping, double 
                               double *log_out) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
-    if (n < 0 || log_every < 1 || !log_out || !(damping >= 0.0 && damping < 1.0))
-        return fail(p, GBP_EINVAL, "need n >= 0, log_every >= 1, a log buffer and 0 <= damping < 1");
+    if (n < 0 || log_every < 1 || !log_out || !(damping >= 0.0 && damping < 1.0) || !std::isfinite(huber_k))
+        return fail(p, GBP_EINVAL, "need n >= 0, log_every >= 1, a log buffer, 0 <= damping < 1 and finite huber_k");
     const size_t rows = (size_t)(n / log_every);
     const size_t bytes = std::max<size_t>(rows, 1) * p->np * GBP_LOG_COLS * 8;
     if (bytes > p->log_cap) {
@@ -1819,7 +1819,8 @@ gbp_status gbp_mlp_train_step_static(const float *x, const float *y, const float
 gbp_status gbp_phase_times(gbp_problem *p, int32_t n, double damping, double huber_k, double *ms_out) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
-    if (n < 1 || !ms_out || !(damping >= 0.0 && damping < 1.0)) return fail(p, GBP_EINVAL, "need n >= 1 and ms_out");
+    if (n < 1 || !ms_out || !(damping >= 0.0 && damping < 1.0) || !std::isfinite(huber_k))
+        return fail(p, GBP_EINVAL, "need n >= 1, ms_out, 0 <= damping < 1 and finite huber_k");
     return p->precision == GBP_FP32 ? phase_times_impl<float>(p, n, damping, huber_k, ms_out)
                                     : phase_times_impl<double>(p, n, damping, huber_k, ms_out);
 }

@@ -718,6 +718,32 @@ def test_mismatched_array_shapes_are_refused(gbp):
     s.close()
 
 
+def test_bad_iteration_arguments_are_refused(gbp):
+    """Damping outside [0, 1), a non-finite Huber threshold, negative counts
+    and a logging period below one are refused by every iterating entry
+    point without running anything: the state and the stored threshold are
+    those of the last accepted call."""
+    prob = synth.make_config0(seed=2)
+    s, o = pair(gbp, prob, gbp.GBP_FP64)
+    s.iterate(5, 0.4, 2.0)
+    o.iterate(5, 0.4, 2.0)
+    t0 = s.t
+    calls = [lambda: s.iterate(1, 1.0, 2.0), lambda: s.iterate(1, -0.1, 2.0),
+             lambda: s.iterate(1, 0.4, float("nan")), lambda: s.iterate(-1, 0.4, 2.0),
+             lambda: s.iterate_logged(2, 0.4, float("inf")), lambda: s.iterate_logged(2, 0.4, 2.0, log_every=0),
+             lambda: s.iterate_logged(2, float("nan"), 2.0), lambda: s.phase_times(1, 0.4, float("nan")),
+             lambda: s.phase_times(0, 0.4, 2.0), lambda: s.phase_times(1, 1.5, 2.0)]
+    for call in calls:
+        with pytest.raises(gbp.GBPError) as e:
+            call()
+        assert e.value.status == -1
+    assert s.huber_k == 2.0 and s.t == t0
+    s.iterate(5, 0.4)
+    o.iterate(5, 0.4, 2.0)
+    assert mean_errs(s.beliefs(), o.beliefs()) < 1e-8
+    s.close()
+
+
 def test_empty_problems_and_isolated_variables(gbp):
     """Degenerate inputs: a problem with one keyframe and nothing else, and a
     problem with a keyframe and a landmark that no factor touches, batched
