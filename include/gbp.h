@@ -152,7 +152,7 @@ gbp_status gbp_create_batch(int32_t n, const gbp_graph *graphs,
  * linearisation point, with the Huber threshold last set on the problem;
  * the new linearisation is applied at the start of the next factor phase
  * (nothing in between depends on it). *n_relin (may be NULL) receives the
- * number selected; this call synchronises. */
+ * number selected; this call synchronises. GBP_EINVAL for a NaN beta. */
 gbp_status gbp_relinearise(gbp_problem *p, double beta, int32_t *n_relin);
 
 /* n synchronous iterations (Section 5): relinearisation check, factor

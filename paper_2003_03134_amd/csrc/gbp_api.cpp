@@ -993,9 +993,12 @@ gbp_status add_impl(gbp_problem *p, const double *pose, int n_new_lm, const doub
     if (n_new_lm < 0 || n_new_f < 0 || (n_new_lm > 0 && !lm_init) || (n_new_f > 0 && (!f_kf || !f_lm || !z)))
         return fail(p, GBP_EINVAL, "bad growth arguments");
     const int nk0 = p->nk, nl0 = p->nl, nf0 = p->nf;
-    const int nk1 = nk0 + (pose ? 1 : 0), nl1 = nl0 + n_new_lm, nf1 = nf0 + n_new_f;
-    if (nk1 > p->cap_k || nl1 > p->cap_l || nf1 > p->cap_f)
+    // sums in 64 bits: a count near INT32_MAX must fail the capacity test,
+    // not wrap below it
+    if ((long long)nk0 + (pose ? 1 : 0) > p->cap_k || (long long)nl0 + n_new_lm > p->cap_l ||
+        (long long)nf0 + n_new_f > p->cap_f)
         return fail(p, GBP_ENOMEM, "growth exceeds the capacity set at creation (max_keyframes/landmarks/factors)");
+    const int nk1 = nk0 + (pose ? 1 : 0), nl1 = nl0 + n_new_lm, nf1 = nf0 + n_new_f;
     for (int i = 0; i < n_new_f; ++i) {
         if (f_kf[i] < 0 || f_kf[i] >= nk1 || f_lm[i] < 0 || f_lm[i] >= nl1)
             return fail(p, GBP_EINVAL, "new factor " + std::to_string(i) + " has an out-of-range variable index");
@@ -1473,6 +1476,7 @@ gbp_status gbp_create_batch(int32_t n, const gbp_graph *graphs, const gbp_camera
 gbp_status gbp_relinearise(gbp_problem *p, double beta, int32_t *n_relin) {
     gbp_status st = check_live(p);
     if (st != GBP_OK) return st;
+    if (std::isnan(beta)) return fail(p, GBP_EINVAL, "gbp_relinearise: beta is NaN");
     return p->precision == GBP_FP32 ? relin_impl<float>(p, beta, n_relin) : relin_impl<double>(p, beta, n_relin);
 }
 

@@ -581,6 +581,16 @@ def test_growth_beyond_capacity_is_rejected(gbp):
     with pytest.raises(gbp.GBPError) as e:
         s.add_keyframe(prob.kf_init[1], np.zeros((1, 3)), [5], [prob.n_landmarks], [[300.0, 200.0]])
     assert "capacity" in str(e.value)
+    # counts near the 32-bit limit fail the capacity test instead of wrapping
+    # past it (checked before the arrays, never dereferenced here, are read)
+    import ctypes as C
+    lib = gbp.load_library()
+    fd = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_double))
+    fi = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_int32))
+    assert lib.gbp_add_keyframe(s.h, None, 2**31 - 1, fd, 0, None, None, None) == -2
+    assert lib.gbp_add_keyframe(s.h, None, 0, None, 2**31 - 1, fi, fi, fd) == -2
+    assert "capacity" in lib.gbp_last_error(s.h).decode()
+    s.iterate(2, 0.4, 2.0)
     s.close()
 
 
@@ -721,8 +731,9 @@ def test_mismatched_array_shapes_are_refused(gbp):
 def test_bad_iteration_arguments_are_refused(gbp):
     """Damping outside [0, 1), a non-finite Huber threshold, negative counts
     and a logging period below one are refused by every iterating entry
-    point without running anything: the state and the stored threshold are
-    those of the last accepted call."""
+    point without running anything, as are a NaN relinearisation threshold
+    and a problem index outside the batch: the state and the stored
+    threshold are those of the last accepted call."""
     prob = synth.make_config0(seed=2)
     s, o = pair(gbp, prob, gbp.GBP_FP64)
     s.iterate(5, 0.4, 2.0)
@@ -732,7 +743,8 @@ def test_bad_iteration_arguments_are_refused(gbp):
              lambda: s.iterate(1, 0.4, float("nan")), lambda: s.iterate(-1, 0.4, 2.0),
              lambda: s.iterate_logged(2, 0.4, float("inf")), lambda: s.iterate_logged(2, 0.4, 2.0, log_every=0),
              lambda: s.iterate_logged(2, float("nan"), 2.0), lambda: s.phase_times(1, 0.4, float("nan")),
-             lambda: s.phase_times(0, 0.4, 2.0), lambda: s.phase_times(1, 1.5, 2.0)]
+             lambda: s.phase_times(0, 0.4, 2.0), lambda: s.phase_times(1, 1.5, 2.0),
+             lambda: s.relinearise(float("nan")), lambda: s.reproj(1), lambda: s.reproj(-2)]
     for call in calls:
         with pytest.raises(gbp.GBPError) as e:
             call()
