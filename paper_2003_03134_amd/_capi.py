@@ -84,7 +84,7 @@ def load():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise HipLibraryMissing(
-            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+            f"{LIB_PATH} is not built; run `python -m paper_2003_03134_amd.build` from the repository root")
     # torch first: its HIP runtime (soname libamdhip64.so.7) then satisfies the
     # library's dependency, so the process holds a single HIP runtime
     import torch  # noqa: F401
