@@ -1023,13 +1023,14 @@ __global__ __launch_bounds__(128) void k_pairs(Dev<TS> d, IterOpts o) {
     }
 }
 
-// Queue segment of residual block b: relinearise and send (marks done); two
-// waves per segment (a segment holds ~22 due factors in most iterations, but
-// up to its 256 when a cohort of factors comes due together: one wave then
-// looped four times; with four waves the empty ones cost more than that).
-// The next nred workgroups (nred = np or 0) reduce the residual statistics
-// of the previous iteration's fused residual pass (whose check advanced the
-// clock: t_off -1) into log_row.
+// Queue segments of the residual blocks: their due factors relinearise and
+// send (marked done). A workgroup of two waves takes G consecutive segments
+// (tuned; 2 on the 256-problem batch): a segment holds ~22 due factors in
+// most iterations, but up to its 256 when a cohort of factors comes due
+// together. The workgroups past the segments' (np of them when statistics
+// are pending, else none: the launch's grid decides) reduce the residual
+// statistics of the previous iteration's fused residual pass (whose check
+// advanced the clock: t_off -1) into log_row.
 constexpr int RELIN_BS = 128;
 constexpr int RELIN_GROUP_MAX = 16;  // queue segments per relinearisation workgroup, at most
 
@@ -1037,7 +1038,7 @@ constexpr int RELIN_GROUP_MAX = 16;  // queue segments per relinearisation workg
 // was slower)
 template <typename TS>
 __global__ __launch_bounds__(RELIN_BS) __attribute__((amdgpu_waves_per_eu(2))) void k_relin(Dev<TS> d, IterOpts o,
-                                                                                            int nseg, int nred,
+                                                                                            int nseg,
                                                                                             double *log_row) {
     const int G = d.relin_group;
     const int nwg = (nseg + G - 1) / G;
@@ -1963,7 +1964,7 @@ template <typename TS>
 void launch_relin(const Dev<TS> &d, const IterOpts &o, hipStream_t s, double *pending_log_row) {
     const int nred = pending_log_row ? d.np : 0;
     const int g = (d.n_rblk + d.relin_group - 1) / d.relin_group + nred;
-    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(RELIN_BS), 0, s, d, o, d.n_rblk, nred, pending_log_row);
+    if (g > 0) hipLaunchKernelGGL(k_relin<TS>, dim3(g), dim3(RELIN_BS), 0, s, d, o, d.n_rblk, pending_log_row);
     // pairwise factors: they read the previous iteration's beliefs and
     // their own messages only, like the relinearised factors
     const int np = d.n_pair[0] + d.n_pair[1];
